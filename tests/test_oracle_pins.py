@@ -1,0 +1,508 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test ties one oracle routine to something other than itself: moment
+identities of the lattice and the equilibrium, relaxation of moments by the
+collision, the force-balance closed forms of Sec. 3 for the reconstruction
+variants, the reconstruction figure of Sec. 3 (golden fixture), brute-force
+enumeration of the variant sets, fixed points, conservation, symmetry.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import (Oracle, bc_value, collide_cell, equilibrium, lattice, opposite,
+                    reconstruct_set)
+from paper_2207_13962_amd import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ----------------------------------------------------------------------------
+# lattice and equilibrium (Sec. 2.1)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_lattice_isotropy(q):
+    """Weights sum to 1; second moment is delta/3; fourth moment is isotropic
+    (delta_ab delta_cd + perms)/9: the conditions that make the second-order
+    equilibrium recover Navier-Stokes. A wrong weight breaks one of them."""
+    c, w = lattice(q)
+    assert len({tuple(x) for x in c}) == q
+    assert abs(w.sum() - 1.0) < 1e-15
+    d = np.eye(3)
+    m2 = np.einsum("i,ia,ib->ab", w, c, c)
+    assert np.allclose(m2, d / 3.0, atol=1e-15)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9.0
+    assert np.allclose(m4, iso, atol=1e-15)
+    # odd moments vanish
+    assert np.allclose(np.einsum("i,ia->a", w, c), 0.0)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, c, c, c), 0.0)
+    for i in range(q):
+        assert np.array_equal(c[opposite(q, i)], -c[i])
+    if q == 19:  # D3Q19 = the 19 directions with |c|^2 <= 2
+        assert all((x * x).sum() <= 2 for x in c)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_equilibrium_moments(q):
+    """Sum feq = rho, sum c feq = rho u, sum cc feq = rho/3 delta + rho uu
+    (the identities used in the paper's force-balance appendix)."""
+    c, _ = lattice(q)
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        rho = rng.uniform(0.5, 1.5)
+        u = rng.uniform(-0.1, 0.1, 3)
+        feq = equilibrium(q, rho, u)
+        assert abs(feq.sum() - rho) < 1e-14
+        assert np.allclose(c.T @ feq, rho * u, atol=1e-15)
+        pi = np.einsum("i,ia,ib->ab", feq, c, c)
+        assert np.allclose(pi, rho / 3.0 * np.eye(3) + rho * np.outer(u, u), atol=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# collision (Sec. 2.1: SRT with Guo forcing; TRT)
+# ----------------------------------------------------------------------------
+
+def _random_pdf(q, rng, rho=1.0, u=(0.03, -0.02, 0.01), noise=1e-3):
+    f = equilibrium(q, rho, np.array(u))
+    return f + noise * rng.standard_normal(q) * f
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("coll", [I.SRT, I.TRT])
+def test_collision_moments(q, coll):
+    """Collision keeps rho, adds the force to the momentum (sum c f* = sum c f + F,
+    so u = (sum c f + F/2)/rho is the mid-step velocity), and relaxes the
+    second moment: Pi* = Pi_eq + (1 - w)(Pi - Pi_eq) + (1 - w/2)(uF + Fu), the
+    Guo forcing property. A sign error in the relaxation or a wrong rate fails."""
+    c, _ = lattice(q)
+    rng = np.random.default_rng(2)
+    tau, lam = 0.62, 3.0 / 16.0
+    g = np.array([1e-4, -2e-4, 5e-5])
+    for _ in range(20):
+        f = _random_pdf(q, rng)
+        fs, u = collide_cell(q, coll, tau, lam, g, f)
+        rho = f.sum()
+        F = rho * g
+        assert abs(fs.sum() - rho) < 1e-14
+        j = c.T @ f
+        assert np.allclose(u, (j + 0.5 * F) / rho, atol=1e-16)
+        assert np.allclose(c.T @ fs, j + F, atol=1e-15)
+        feq = equilibrium(q, rho, u)
+        pi = np.einsum("i,ia,ib->ab", f, c, c)
+        pieq = np.einsum("i,ia,ib->ab", feq, c, c)
+        pis = np.einsum("i,ia,ib->ab", fs, c, c)
+        w = 1.0 / tau  # the even moments relax with omega+ = 1/tau in TRT as well
+        expect = pieq + (1 - w) * (pi - pieq) + (1 - 0.5 * w) * (np.outer(u, F) + np.outer(F, u))
+        assert np.allclose(pis, expect, atol=1e-14)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_trt_reduces_to_srt(q):
+    """Lambda = (tau - 1/2)^2 gives omega- = omega+, i.e. SRT."""
+    rng = np.random.default_rng(3)
+    tau = 0.73
+    g = np.array([0.0, -1e-4, 2e-5])
+    for _ in range(20):
+        f = _random_pdf(q, rng)
+        a, ua = collide_cell(q, I.SRT, tau, 0.0, g, f)
+        b, ub = collide_cell(q, I.TRT, tau, (tau - 0.5) ** 2, g, f)
+        assert np.allclose(a, b, rtol=0, atol=1e-16)
+        assert np.array_equal(ua, ub)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_trt_odd_moment_rate(q):
+    """TRT relaxes the antisymmetric part with 1/omega- = 1/2 + Lambda/(tau - 1/2);
+    pinned through the third moment sum c_x c_x c_y f (odd) at g = 0."""
+    c, _ = lattice(q)
+    rng = np.random.default_rng(4)
+    tau, lam = 0.8, 3.0 / 16.0
+    wm = 1.0 / (0.5 + lam / (tau - 0.5))
+    for _ in range(10):
+        f = _random_pdf(q, rng, noise=1e-2)
+        fs, u = collide_cell(q, I.TRT, tau, lam, np.zeros(3), f)
+        feq = equilibrium(q, f.sum(), u)
+        k = c[:, 0] * c[:, 0] * c[:, 1]
+        assert abs(k @ fs - (k @ feq + (1 - wm) * (k @ (f - feq)))) < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# free-surface condition and the four variants (Sec. 2.2, Sec. 3)
+# ----------------------------------------------------------------------------
+
+def _force(c, fs, u, n, K, R, rec):
+    """F/A = -n_b (sum_K f*(x) (c-u)_a (c-u)_b + sum_R f_rec (c-u)_a (c-u)_b),
+    Sec. 3, general force balance."""
+    cu = c - u[None, :]
+    t = np.zeros((3, 3))
+    for i in K:
+        t += fs[i] * np.outer(cu[i], cu[i])
+    for i in R:
+        t += rec[i] * np.outer(cu[i], cu[i])
+    return -(t @ n)
+
+
+def _random_state(q, rng):
+    c, _ = lattice(q)
+    u = rng.uniform(-0.08, 0.08, 3)
+    fs = equilibrium(q, rng.uniform(0.9, 1.1), u) * (1 + 0.05 * rng.standard_normal(q))
+    n = rng.standard_normal(3)
+    rg = rng.uniform(0.95, 1.05)
+    rec = np.array([bc_value(q, i, rg, u, fs[opposite(q, i)]) for i in range(q)])
+    return c, u, fs, n, rg, rec
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_force_balance_nbrc(q):
+    """NBRC closed form (Sec. 3.1): F/A = -n p^G + n_b (f*_0 - feq_0) u_a u_b
+    + 2 n_b sum_K (f*_i - feq_i)(c_ia u_b + c_ib u_a)."""
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        c, u, fs, n, rg, rec = _random_state(q, rng)
+        R = np.nonzero(reconstruct_set(q, I.NBRC, n, 0))[0]
+        K = [i for i in range(q) if i not in R]
+        assert 0 in R and all(n @ c[i] < 0 for i in K) and all(n @ c[i] >= 0 for i in R)
+        feq = equilibrium(q, rg, u)
+        err = n @ np.outer(u, u) * (fs[0] - feq[0])
+        for i in K:
+            err += 2 * (fs[i] - feq[i]) * (np.outer(c[i], u) + np.outer(u, c[i])) @ n
+        expect = -n * rg / 3.0 + err
+        assert np.allclose(_force(c, fs, u, n, K, R, rec), expect, atol=1e-13)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_force_balance_nbkc(q):
+    """NBKC closed form (Sec. 3.2): the centre population in neither set,
+    F/A = -n p^G + n_b feq_0 u_a u_b + 2 n_b sum_K (f*_i - feq_i)(c_ia u_b + c_ib u_a)."""
+    rng = np.random.default_rng(6)
+    for _ in range(300):
+        c, u, fs, n, rg, rec = _random_state(q, rng)
+        Rm = reconstruct_set(q, I.NBKC, n, 0)
+        assert not Rm[0]
+        R = np.nonzero(Rm)[0]
+        K = [i for i in range(1, q) if not Rm[i]]
+        feq = equilibrium(q, rg, u)
+        err = n @ np.outer(u, u) * feq[0]
+        for i in K:
+            err += 2 * (fs[i] - feq[i]) * (np.outer(c[i], u) + np.outer(u, c[i])) @ n
+        expect = -n * rg / 3.0 + err
+        assert np.allclose(_force(c, fs, u, n, K, R, rec), expect, atol=1e-13)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_force_balance_om(q):
+    """OM closed form (Sec. 3.3), valid when no direction has gas on both sides
+    (G- and G+ disjoint): R = G-, K = N-."""
+    rng = np.random.default_rng(7)
+    pairs = [(i, i + 1) for i in range(1, q, 2)]
+    for _ in range(300):
+        c, u, fs, n, rg, rec = _random_state(q, rng)
+        gm = 0
+        for a, b in pairs:
+            r = rng.integers(0, 3)
+            if r == 1:
+                gm |= 1 << a
+            elif r == 2:
+                gm |= 1 << b
+        Rm = reconstruct_set(q, I.OM, n, gm)
+        Gm = [i for i in range(q) if (gm >> i) & 1]
+        assert sorted(np.nonzero(Rm)[0].tolist()) == Gm
+        Gp = [opposite(q, i) for i in Gm]
+        Nm = [i for i in range(q) if i not in Gm]
+        feq = equilibrium(q, rg, u)
+        t = np.zeros(3)
+        for i in Nm:
+            t -= fs[i] * (np.outer(c[i], c[i]) - np.outer(c[i], u) - np.outer(u, c[i])
+                          + np.outer(u, u)) @ n
+        for i in Gp:
+            t += fs[i] * (np.outer(c[i], c[i]) + np.outer(c[i], u) + np.outer(u, c[i])
+                          + np.outer(u, u)) @ n
+        for i in range(q):
+            if i in Gm or i in Gp:
+                continue
+            t += feq[i] * (np.outer(c[i], c[i]) - np.outer(c[i], u) - np.outer(u, c[i])
+                           + np.outer(u, u)) @ n
+        for i in Gp:
+            t -= 2 * feq[i] * (np.outer(c[i], u) + np.outer(u, c[i])) @ n
+        expect = -n * rg / 3.0 + t
+        assert np.allclose(_force(c, fs, u, n, Nm, Gm, rec), expect, atol=1e-13)
+
+
+def test_nb_balance_at_rest():
+    """At u = 0 the normal-based variants balance the forces exactly (Sec. 3.1, 3.2)."""
+    rng = np.random.default_rng(8)
+    for q in (19, 27):
+        for v in (I.NBRC, I.NBKC):
+            for _ in range(50):
+                c, _, fs, n, rg, _ = _random_state(q, rng)
+                u = np.zeros(3)
+                rec = np.array([bc_value(q, i, rg, u, fs[opposite(q, i)]) for i in range(q)])
+                Rm = reconstruct_set(q, v, n, 0)
+                R = np.nonzero(Rm)[0]
+                K = [i for i in range(1 if v == I.NBKC else 0, q) if not Rm[i]]
+                F = _force(c, fs, u, n, K, R, rec)
+                expect = -n * rg / 3.0 + (0 if v == I.NBRC else 0)
+                if v == I.NBKC:
+                    expect = -n * rg / 3.0  # feq_0 u u term vanishes at u = 0
+                assert np.allclose(F, expect, atol=1e-13)
+
+
+def test_reconstruction_figure_golden():
+    """The reconstruction figure of Sec. 3: with n = grad(phi) (the negative of
+    the arrow drawn into the gas) and R = {n.c >= 0}, the reconstructed in-plane
+    populations are exactly the green arrows of each panel."""
+    fx = json.load(open(os.path.join(HERE, "golden", "reconstruction_figure.json")))
+    a = fx["drawn_normal_arrow"]
+    n = -(np.array(a["to"]) - np.array(a["from"]))
+    n = np.array([n[0], n[1], 0.0])
+    q = 19
+    c, _ = lattice(q)
+    gas = [tuple(map(int, k.split(","))) for k, v in fx["neighbour_types"].items() if v == "gas"]
+    gm = 0
+    for i in range(1, q):
+        src = (-c[i][0], -c[i][1])
+        if c[i][2] == 0 and src in gas:
+            gm |= 1 << i
+    for name, v in (("NBRC", I.NBRC), ("NBKC", I.NBKC), ("OM", I.OM)):
+        R = reconstruct_set(q, v, n, gm)
+        inplane = {(int(c[i][0]), int(c[i][1])) for i in range(q) if c[i][2] == 0 and R[i]}
+        assert inplane == {tuple(x) for x in fx["reconstructed"][name]}, name
+        kept = {(int(c[i][0]), int(c[i][1])) for i in range(q) if c[i][2] == 0 and not R[i]}
+        assert kept == {tuple(x) for x in fx["kept"][name]}, name
+
+
+def test_variant_sets_bruteforce_q19():
+    """All 2^18 gas-source masks of D3Q19: OM reconstructs exactly the missing
+    populations; OM3 adds the NBKC set iff fewer than three are missing
+    (Sec. 3.3, 3.4); NBRC/NBKC always contain the missing ones."""
+    q = 19
+    c, _ = lattice(q)
+    n = np.array([0.3, 0.9, -0.2])
+    nb = np.array([(n @ c[i]) >= 0 for i in range(q)])
+    nb[0] = False
+    rng = np.random.default_rng(9)
+    masks = list(range(0, 1 << 18, 37)) + [0, 1, 3, 7, (1 << 18) - 1]
+    for m18 in masks:
+        gm = m18 << 1
+        miss = np.array([(gm >> i) & 1 for i in range(q)], dtype=bool)
+        om = reconstruct_set(q, I.OM, n, gm)
+        assert np.array_equal(om, miss)
+        om3 = reconstruct_set(q, I.OM3, n, gm)
+        if miss.sum() >= 3:
+            assert np.array_equal(om3, miss)
+        else:
+            assert np.array_equal(om3, miss | nb)
+        nbkc = reconstruct_set(q, I.NBKC, n, gm)
+        assert np.array_equal(nbkc, miss | nb)
+        nbrc = reconstruct_set(q, I.NBRC, n, gm)
+        assert nbrc[0] and np.array_equal(nbrc[1:], (miss | nb)[1:])
+    del rng
+
+
+def test_tie_band():
+    """n.c_i within delta*max|n| of zero counts as zero (reconstructed); n = 0
+    reconstructs every direction in the normal-based variants."""
+    q = 19
+    c, _ = lattice(q)
+    n = np.array([1.0, 1.0 + 1e-12, 0.0])   # (1,-1,0) is a tie up to 1e-12
+    R = reconstruct_set(q, I.NBKC, n, 0, tie_delta=1e-9)
+    i = [k for k in range(q) if tuple(c[k]) == (1, -1, 0)][0]
+    j = [k for k in range(q) if tuple(c[k]) == (-1, 1, 0)][0]
+    assert R[i] and R[j]
+    R0 = reconstruct_set(q, I.NBRC, np.zeros(3), 0)
+    assert R0.all()
+
+
+# ----------------------------------------------------------------------------
+# whole steps
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", [I.NBRC, I.NBKC, I.OM, I.OM3])
+@pytest.mark.parametrize("q", [19, 27])
+def test_flat_interface_rest_is_fixed_point(variant, q):
+    """rho = rho_G = 1, u = 0, g = 0 and a flat one-cell interface layer: the
+    reconstruction returns 2 w_i - w_i = w_i and all fluxes vanish, so the
+    state is reproduced by every variant. Only round-off of the weights (their
+    binary64 sum is not exactly 1) may move it; a wrong sign anywhere in the
+    condition or the flux would move it by O(w_i)."""
+    s = I.flat_interface_rest(q=q, variant=variant)
+    o = Oracle(s)
+    a = o.fields()
+    fs0 = o.post_collision()
+    assert o.step(50) == 0
+    b = o.fields()
+    assert np.array_equal(a["type"], b["type"])
+    assert np.abs(a["pdf"] - b["pdf"]).max() < 1e-15
+    assert np.abs(a["mass"] - b["mass"]).max() < 1e-13
+    assert np.abs(fs0 - o.post_collision()).max() < 1e-15
+
+
+def _closed_layer_ok(t, p):
+    nx, ny, nz = p.nx, p.ny, p.nz
+    t3 = t.reshape(nz, ny, nx)
+    liq = t3 == I.LIQUID
+    gas = t3 == I.GAS
+    b = p.boundary
+    for dz, dy, dx in itertools.product((-1, 0, 1), repeat=3):
+        n2 = dx * dx + dy * dy + dz * dz
+        if n2 == 0 or (p.q == 19 and n2 == 3):
+            continue
+        sh = gas
+        for axis, d, lo, hi in ((2, dx, b[0], b[1]), (1, dy, b[2], b[3]), (0, dz, b[4], b[5])):
+            if d == 0:
+                continue
+            sh = np.roll(sh, -d, axis=axis)
+            if (hi if d > 0 else lo) != I.PERIODIC:
+                idx = [slice(None)] * 3
+                idx[axis] = slice(-1, None) if d > 0 else slice(0, 1)
+                sh = sh.copy()
+                sh[tuple(idx)] = False
+        if (liq & sh).any():
+            return False
+    return True
+
+
+def test_wave_mass_and_closed_layer():
+    """Standing wave 64x64x1, 1000 steps: mass M = sum_liquid rho + sum_interface m
+    + lost is conserved to round-off and the interface layer stays closed."""
+    s = I.gravity_wave()
+    o = Oracle(s)
+    m0 = o.mass().total_mass
+    for _ in range(10):
+        assert o.step(100) == 0
+        assert _closed_layer_ok(o.fields()["type"], s.params)
+    r = o.mass()
+    assert abs(r.total_mass - m0) / m0 < 1e-12
+    assert r.n_interface > 0
+
+
+@pytest.mark.parametrize("q,coll,wall", [(19, I.SRT, I.WALL_NOSLIP), (27, I.TRT, I.WALL_FREESLIP)])
+def test_dam_break_mass_conversions(q, coll, wall):
+    """Mini 3D dam break with many conversions: mass conserved to round-off,
+    closed layer after every step, conversions actually happen."""
+    b = (wall, wall, I.WALL_NOSLIP, I.WALL_NOSLIP, wall, wall)
+    s = I.rect_dam_break(nx=24, ny=16, nz=6, wx=8, hy=12, g=2e-4, nu=0.01, q=q, collision=coll,
+                         storage=I.F64, boundary=b)
+    o = Oracle(s)
+    m0 = o.mass().total_mass
+    t0 = o.fields()["type"].copy()
+    changed = 0
+    for _ in range(30):
+        assert o.step(10) == 0
+        t = o.fields()["type"]
+        assert _closed_layer_ok(t, s.params)
+        changed += int((t != t0).sum())
+        t0 = t.copy()
+    r = o.mass()
+    assert changed > 50
+    assert abs(r.total_mass - m0) / m0 < 1e-12
+
+
+def test_liquid_box_hydrostatic():
+    """A closed box of liquid under gravity relaxes to rest with the hydrostatic
+    density gradient d(rho)/dy = -3 g rho (p = rho/3, dp/dy = -rho g)."""
+    g = 1e-4
+    b = (I.WALL_NOSLIP,) * 6
+    p = I.Params(4, 24, 4, q=19, collision=I.SRT, storage=I.F64, boundary=b, tau=0.8,
+                 gravity=(0.0, -g, 0.0))
+    n = p.n
+    s = I.Setup(p, np.full(n, I.LIQUID, np.uint8), np.ones(n), np.ones(n), np.zeros(n),
+                np.zeros(n), np.zeros(n))
+    o = Oracle(s)
+    m0 = o.mass().total_mass
+    assert o.step(3000) == 0
+    f = o.fields()
+    rho = f["rho"].reshape(4, 24, 4)[:, :, :].mean(axis=(0, 2))
+    umax = max(abs(f["ux"]).max(), abs(f["uy"]).max(), abs(f["uz"]).max())
+    assert umax < 1e-7
+    slope = np.diff(rho)
+    mid = 0.5 * (rho[1:] + rho[:-1])
+    assert np.allclose(slope, -3 * g * mid, rtol=2e-3)
+    assert abs(o.mass().total_mass - m0) / m0 < 1e-12
+
+
+def test_mirror_symmetry_wave():
+    """Mirror-symmetric initial data (the cosine wave is symmetric about
+    x = nx/2) stays symmetric for every variant: types identical under the
+    mirror, fields to round-off, velocity x-component antisymmetric."""
+    for v in (I.NBRC, I.NBKC, I.OM, I.OM3):
+        s = I.gravity_wave(nx=32, ny=32, depth=16, amp=0.9, g=1e-4, variant=v)
+        o = Oracle(s)
+        assert o.step(150) == 0
+        f = o.fields()
+        t = f["type"].reshape(32, 32)
+        assert np.array_equal(t, t[:, ::-1])
+        ph = f["phi"].reshape(32, 32)
+        assert np.allclose(ph, ph[:, ::-1], atol=1e-11)
+        ux = f["ux"].reshape(32, 32)
+        assert np.allclose(ux, -ux[:, ::-1], atol=1e-13)
+
+
+def test_cosine_fill_exact():
+    """Input generator: sum_j phi(i, j) equals the exact integral of the surface
+    height over the column, and the total equals depth * nx."""
+    nx, ny, h, a = 64, 64, 32.0, 0.64
+    col = I.cosine_column_fill(nx, ny, h, a, nx)
+    k = 2 * np.pi / nx
+    for i in range(nx):
+        exact = h + a / k * (np.sin(k * (i + 1)) - np.sin(k * i))
+        assert abs(col[:, i].sum() - exact) < 1e-12
+    assert abs(col.sum() - h * nx) < 1e-9
+
+
+def test_parker_youngs_normal_points_into_liquid():
+    """n = grad(phi) points from gas to liquid; a flat layer gives n along +y,
+    a planar interface meeting a wall keeps n exactly along the wall."""
+    s = I.flat_interface_rest()
+    o = Oracle(s)
+    n = o.normal(3, 6, 1)
+    assert n[1] < 0 and n[0] == 0 and n[2] == 0  # liquid is below (y < 6): grad phi points -y
+    # flat surface touching no-slip walls in x
+    b = (I.WALL_NOSLIP, I.WALL_NOSLIP, I.WALL_NOSLIP, I.WALL_NOSLIP, I.PERIODIC, I.PERIODIC)
+    s2 = I.flat_interface_rest(nx=6)
+    s2.params = s2.params.with_(boundary=b)
+    o2 = Oracle(s2)
+    n0 = o2.normal(0, 6, 1)
+    assert n0[0] == 0.0 and n0[1] < 0
+
+
+def test_sphere_curvature():
+    """kappa = -div(n_hat) of a drop of radius R tends to 2/R (positive for a
+    drop, negative for a bubble); coarse lattices are within 15 %."""
+    R = 8.0
+    for bubble, sign in ((False, 1.0), (True, -1.0)):
+        s = I.sphere_drop_static(L=24, radius=R, bubble=bubble)
+        o = Oracle(s)
+        t = s.type.reshape(24, 24, 24)
+        ks = []
+        zz, yy, xx = np.nonzero(t == I.INTERFACE)
+        for x, y, z in list(zip(xx, yy, zz))[::7][:40]:
+            ks.append(o.curvature(int(x), int(y), int(z)))
+        k = np.mean(ks)
+        assert abs(k - sign * 2.0 / R) < 0.15 * 2.0 / R, (bubble, k)
+
+
+def test_unstable_detected():
+    """A flow beyond the lattice speed of sound is reported as unstable."""
+    b = (I.PERIODIC,) * 6
+    p = I.Params(4, 4, 4, q=19, collision=I.SRT, boundary=b, tau=0.5 + 1e-5)
+    n = p.n
+    s = I.Setup(p, np.full(n, I.LIQUID, np.uint8), np.ones(n), np.ones(n), np.full(n, 0.7),
+                np.zeros(n), np.zeros(n))
+    o = Oracle(s)
+    assert o.step(5) == -4
+
+
+def test_create_rejects_liquid_next_to_gas():
+    p = I.Params(4, 4, 4)
+    t = np.full(p.n, I.LIQUID, np.uint8)
+    t[0] = I.GAS
+    s = I.Setup(p, t, np.ones(p.n), np.ones(p.n), np.zeros(p.n), np.zeros(p.n), np.zeros(p.n))
+    with pytest.raises(ValueError):
+        Oracle(s)
