@@ -1,0 +1,159 @@
+/*
+ * libfslbm - free-surface lattice Boltzmann time step on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the free-surface lattice Boltzmann method of Schwarzmeier & Rüde,
+ * "Analysis and comparison of boundary condition variants in the free-surface
+ * lattice Boltzmann method": lattice Boltzmann collision with Guo gravity forcing
+ * and streaming (Sec. 2.1), fill level, mass exchange, cell conversion with excess
+ * mass and reinitialisation, anti-bounce-back free-surface condition with gas,
+ * volume and Laplace pressure, Parker-Youngs normals (Sec. 2.2), and the four
+ * reconstruction variants NBRC, NBKC, OM and OM3 (Sec. 3).
+ *
+ * Conventions shared by every entry point
+ *  - Grid: nx*ny*nz cells, x fastest: idx = x + nx*(y + ny*z). Walls are ghost
+ *    layers just outside the domain (halfway bounce-back puts the wall on the face).
+ *  - Host arrays passed in are borrowed for the duration of the call and copied;
+ *    host arrays passed out must hold the stated number of elements.
+ *  - Every call returns an int status (FSLBM_OK = 0, negative on error), never
+ *    throws across the ABI and never exits the process. fslbm_last_error() gives
+ *    a message for the last failing call on a context.
+ *  - A context is not thread-safe; separate contexts may run concurrently on
+ *    separate streams.
+ *  - Populations are kept in device memory as the POST-collision state f* of
+ *    the current step (structure of arrays, q planes of N values); reported
+ *    fields are the pre-collision moments rho = sum f*, u = (sum c f* - rho g/2)/rho,
+ *    which equal the moments of the populations after streaming.
+ */
+#ifndef FSLBM_H
+#define FSLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSLBM_ABI_VERSION 1
+
+typedef struct fslbm_ctx fslbm_ctx;
+
+enum {
+  FSLBM_OK = 0,
+  FSLBM_EINVAL = -1,    /* bad argument or parameter, or initial state violating the closed layer */
+  FSLBM_ENOMEM = -2,    /* device allocation failed, or the caller's arena is too small */
+  FSLBM_EDEVICE = -3,   /* HIP runtime error (launch, copy, fault reported by the runtime) */
+  FSLBM_EUNSTABLE = -4, /* NaN, rho <= 0 or |u| >= c_s seen on the device (sticky) */
+  FSLBM_ESTATE = -5,    /* call not valid in the context's state (e.g. after a device error) */
+  FSLBM_EBUDGET = -6    /* server: request larger than the memory budget */
+};
+
+/* Reconstruction variants, Sec. 3.1-3.4. */
+enum { FSLBM_NBRC = 1, FSLBM_NBKC = 2, FSLBM_OM = 3, FSLBM_OM3 = 4 };
+/* Cell types (Sec. 2.2: gas, interface, liquid) and obstacles (Sec. 2.1). */
+enum { FSLBM_GAS = 0, FSLBM_INTERFACE = 1, FSLBM_LIQUID = 2, FSLBM_NOSLIP = 3, FSLBM_FREESLIP = 4 };
+enum { FSLBM_SRT = 0, FSLBM_TRT = 1 };
+/* Population storage: binary64; binary32; binary16 holding f_i - w_i (FP32 arithmetic). */
+enum { FSLBM_F64 = 0, FSLBM_F32 = 1, FSLBM_F16S = 2 };
+/* Domain faces. */
+enum { FSLBM_PERIODIC = 0, FSLBM_WALL_NOSLIP = 1, FSLBM_WALL_FREESLIP = 2 };
+
+typedef struct {
+  uint32_t abi_version;  /* must equal FSLBM_ABI_VERSION */
+  int32_t nx, ny, nz;    /* interior cells, each >= 1 */
+  int32_t q;             /* 19 (D3Q19) or 27 (D3Q27) */
+  int32_t collision;     /* FSLBM_SRT (Sec. 2.1) or FSLBM_TRT */
+  int32_t storage;       /* FSLBM_F64, FSLBM_F32 or FSLBM_F16S */
+  int32_t boundary[6];   /* faces -x,+x,-y,+y,-z,+z: FSLBM_PERIODIC or FSLBM_WALL_* */
+  int32_t variant;       /* FSLBM_NBRC .. FSLBM_OM3 */
+  int32_t thurey_flux;   /* 1: interface cells without liquid (gas) neighbours are forced to
+                            empty (fill) through the mass flux, Sec. 2.2; 0: plain flux */
+  int32_t bubble_model;  /* 0: constant volume pressure; 1: one enclosed bubble,
+                            p^V(t) = p^V(0) V(0)/V(t), Sec. 2.2 */
+  double tau;            /* relaxation time, > 0.5 (nu = (tau - 1/2)/3) */
+  double trt_lambda;     /* TRT magic parameter, used only for FSLBM_TRT */
+  double gravity[3];     /* acceleration; force density F = rho g, not weighted by phi */
+  double rho_gas;        /* gas density at zero surface tension, = 3 p^V(0) */
+  double sigma;          /* surface tension (0 = off): rho^G = 3 (p^V + sigma kappa) */
+  double eps_phi;        /* conversion threshold (the paper uses 1e-2) */
+  double tie_delta;      /* |n.c_i| <= tie_delta*max|n_a| counts as n.c_i = 0; 0 -> 1e-9 */
+} fslbm_params;
+
+typedef struct {
+  double total_mass;      /* liquid_mass + interface_mass + lost_mass (FP64) */
+  double liquid_mass;     /* sum over liquid cells of rho */
+  double interface_mass;  /* sum over interface cells of m */
+  double lost_mass;       /* excess mass of converted cells that had no interface neighbour */
+  double bubble_volume;   /* sum over non-obstacle cells of (1 - phi) */
+  double p_volume;        /* current volume pressure p^V */
+  int64_t n_liquid, n_interface, n_gas, step;
+} fslbm_mass_report;
+
+/* Device bytes fslbm_create needs for these parameters (for a caller-owned arena).
+ * Errors: FSLBM_EINVAL for NULL pointers or invalid parameters. */
+int fslbm_workspace_bytes(const fslbm_params* p, size_t* bytes);
+
+/* Creates a simulation (Sec. 2.2 statement of the problem: cell types, fill levels,
+ * density and velocity; interface mass m = phi * rho).
+ * type, phi, rho, ux, uy, uz: host arrays of N elements. Populations start at the
+ * equilibrium feq(rho, u) and are collided once, so the stored state is post-collision.
+ * pdf_or_null: q*N host doubles of post-collision populations (as exported by
+ *   fslbm_fields) for an exact resume; mass_or_null: N host doubles of interface mass.
+ * device_arena_or_null: caller-owned device memory of at least fslbm_workspace_bytes,
+ *   kept alive until fslbm_destroy; NULL lets the library allocate (and free) it.
+ * hip_stream: the hipStream_t all work is enqueued on (NULL = default stream).
+ * Errors: FSLBM_EINVAL (bad parameters, liquid cell next to gas, unknown type),
+ *   FSLBM_ENOMEM, FSLBM_EDEVICE. On error *out is NULL. */
+int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, const double* rho,
+                 const double* ux, const double* uy, const double* uz, const double* pdf_or_null,
+                 const double* mass_or_null, void* device_arena_or_null, size_t arena_bytes,
+                 void* hip_stream, fslbm_ctx** out);
+
+/* Selects the reconstruction variant (Sec. 3) from the next step on.
+ * Errors: FSLBM_EINVAL for an unknown variant or NULL context. */
+int fslbm_set_variant(fslbm_ctx* ctx, int variant);
+
+/* Enqueues nsteps time steps on the context's stream and returns without waiting.
+ * Each step: stream + boundary condition + mass exchange + fill level + marks +
+ * collision, then conversion, reinitialisation and excess-mass redistribution.
+ * Errors: FSLBM_EINVAL (nsteps < 0), FSLBM_ESTATE (earlier device error), FSLBM_EDEVICE. */
+int fslbm_step(fslbm_ctx* ctx, int64_t nsteps);
+
+/* Waits for the stream and reports mass, counts and the bubble state (FP64,
+ * deterministic reduction order). Returns FSLBM_EUNSTABLE if an instability was
+ * detected since creation (the report is still filled). */
+int fslbm_mass(fslbm_ctx* ctx, fslbm_mass_report* out);
+
+/* Waits for the stream and copies fields out (any pointer may be NULL):
+ * type (N bytes), phi, rho, ux, uy, uz, mass (N doubles each; mass is m for
+ * interface cells, rho for liquid cells, 0 for gas), pdf (q*N doubles,
+ * post-collision populations, gas cells 0). Returns FSLBM_EUNSTABLE like fslbm_mass. */
+int fslbm_fields(fslbm_ctx* ctx, uint8_t* type, double* phi, double* rho, double* ux, double* uy,
+                 double* uz, double* mass, double* pdf);
+
+/* Number of interface cells in the compacted interface list and, if list is not
+ * NULL, the list itself (ascending cell indices, at most max entries). Syncs. */
+int fslbm_interface_list(fslbm_ctx* ctx, int32_t* list, int64_t max, int64_t* count);
+
+/* Kernel timing for measurement. fslbm_set_timing(ctx, capacity) with
+ * capacity > 0 brackets the next `capacity` launches of the liquid
+ * stream-collide kernel with HIP events on the context's stream (capacity 0
+ * turns timing off and releases the events). fslbm_kernel_time syncs and
+ * returns the number of timed launches and their summed duration in ms.
+ * Errors: FSLBM_EINVAL (NULL, capacity < 0), FSLBM_EDEVICE. */
+int fslbm_set_timing(fslbm_ctx* ctx, int64_t capacity);
+int fslbm_kernel_time(fslbm_ctx* ctx, int64_t* launches, double* total_ms);
+
+/* Releases the context (NULL-safe; never fails). Does not free a caller arena. */
+void fslbm_destroy(fslbm_ctx* ctx);
+
+/* Static message for a status code. */
+const char* fslbm_strerror(int status);
+/* Message for the last failing call on ctx (or the last fslbm_create failure
+ * when ctx is NULL). The pointer stays valid until the next call on ctx. */
+const char* fslbm_last_error(const fslbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

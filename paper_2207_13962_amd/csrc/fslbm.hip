@@ -1,0 +1,426 @@
+// Host side of libfslbm: context, device memory layout, launches, C ABI.
+// The public interface is declared (and documented) in include/fslbm.h.
+// The kernels that do not depend on the population format live in this unit.
+#define FSLBM_HOST_KERNELS 1
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fslbm.h"
+#include "fslbm_kernels.h"
+
+using namespace fslbm;
+
+#include "fslbm_ops.h"
+
+using namespace fslbm_host;
+
+namespace {
+
+thread_local char g_create_error[512] = "";
+
+int set_err(fslbm_ctx* c, int st, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return st;
+}
+
+int hip_fail(fslbm_ctx* c, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (c) {
+    c->status = FSLBM_EDEVICE;
+    c->last_error = m;
+  } else {
+    snprintf(g_create_error, sizeof g_create_error, "%s", m.c_str());
+  }
+  return FSLBM_EDEVICE;
+}
+
+#define HIPCHK(ctx, expr)                              \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+Ops pick(const fslbm_params& p) {
+  if (p.storage == FSLBM_F32) return p.q == 27 ? ops_f32_q27(p.collision) : ops_f32_q19(p.collision);
+  if (p.storage == FSLBM_F16S) return p.q == 27 ? ops_f16s_q27(p.collision) : ops_f16s_q19(p.collision);
+  return p.q == 27 ? ops_f64_q27(p.collision) : ops_f64_q19(p.collision);
+}
+
+void bind(fslbm_ctx* c) {
+  const Layout& L = c->L;
+  char* a = c->arena;
+  Dev& d = c->d;
+  d.g.nx = c->p.nx;
+  d.g.ny = c->p.ny;
+  d.g.nz = c->p.nz;
+  for (int f = 0; f < 6; ++f) d.g.bnd[f] = c->p.boundary[f];
+  d.g.N = L.N;
+  d.g.stride = L.stride;
+  const double tau = c->p.tau;
+  d.omega = 1.0 / tau;
+  d.omega_m = c->p.collision == FSLBM_TRT ? 1.0 / (0.5 + c->p.trt_lambda / (tau - 0.5)) : d.omega;
+  d.gx = c->p.gravity[0];
+  d.gy = c->p.gravity[1];
+  d.gz = c->p.gravity[2];
+  d.rho_gas = c->p.rho_gas;
+  d.sigma = c->p.sigma;
+  d.eps = c->p.eps_phi;
+  d.delta = c->p.tie_delta > 0.0 ? c->p.tie_delta : 1e-9;
+  d.variant = c->p.variant;
+  d.thurey = c->p.thurey_flux;
+  d.bubble = c->p.bubble_model;
+  d.fA = a + L.off_fA;
+  d.fB = a + L.off_fB;
+  d.flags = reinterpret_cast<uint8_t*>(a + L.off_flags);
+  d.mark = reinterpret_cast<uint8_t*>(a + L.off_mark);
+  d.cls = reinterpret_cast<uint8_t*>(a + L.off_cls);
+  d.phiA = reinterpret_cast<double*>(a + L.off_phiA);
+  d.phiB = reinterpret_cast<double*>(a + L.off_phiB);
+  d.m = reinterpret_cast<double*>(a + L.off_m);
+  d.rho_if = reinterpret_cast<double*>(a + L.off_rho_if);
+  d.rhoG = c->p.sigma != 0.0 ? reinterpret_cast<double*>(a + L.off_rhoG) : nullptr;
+  d.phis = c->p.sigma != 0.0 ? reinterpret_cast<double*>(a + L.off_phis) : nullptr;
+  d.lost = reinterpret_cast<double*>(a + L.off_lost);
+  d.if_list = reinterpret_cast<int32_t*>(a + L.off_if_list);
+  d.conv_list = reinterpret_cast<int32_t*>(a + L.off_conv_list);
+  d.cnt = reinterpret_cast<int32_t*>(a + L.off_cnt);
+  d.scan_if = reinterpret_cast<unsigned long long*>(a + L.off_scan_if);
+  d.scan_cv = reinterpret_cast<unsigned long long*>(a + L.off_scan_cv);
+  d.pV = reinterpret_cast<double*>(a + L.off_pv);
+  d.partial = reinterpret_cast<double*>(a + L.off_partial);
+}
+
+double* stage(fslbm_ctx* c) { return reinterpret_cast<double*>(c->arena + c->L.off_stage); }
+
+// Bubble volume at t+1 (phiB, new types) and the volume pressure update.
+void launch_volume(fslbm_ctx* c, hipStream_t s, bool set_reference) {
+  hipLaunchKernelGGL(k_reduce_volume, dim3((unsigned)c->L.red_blocks), dim3(kBlock), 0, s, c->d,
+                     kRedCells);
+  double* out = c->d.partial + kRedN * c->L.red_blocks;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, c->d.partial, (int)c->L.red_blocks,
+                     1, out);
+  if (set_reference) {
+    // p^V(0) = rho_gas / 3; V(0) = V
+    hipMemcpyAsync(c->d.pV + 2, out, sizeof(double), hipMemcpyDeviceToDevice, s);
+  } else {
+    hipLaunchKernelGGL(k_update_pv, dim3(1), dim3(64), 0, s, c->d.pV, out);
+  }
+}
+
+int enqueue_steps(fslbm_ctx* c, int64_t n) {
+  const Ops ops = pick(c->p);
+  hipStream_t s = c->stream;
+  const bool st = c->p.sigma != 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    c->d.step = c->step;
+    c->d.epoch = ++c->epoch;
+    if (st) {
+      hipLaunchKernelGGL(k_smooth, dim3((unsigned)(((c->p.nx + 63) / 64) * ((c->p.ny + 3) / 4) *
+                                                   c->p.nz)),
+                         dim3(kBlock), 0, s, c->d);
+      hipLaunchKernelGGL(k_curvature, dim3(finish_blocks(c)), dim3(kBlock), 0, s, c->d);
+    }
+    ops.step(c, s);
+    ops.convert(c, s, 0);
+    ops.finish(c, s, 0);
+    if (c->p.bubble_model) launch_volume(c, s, false);
+    std::swap(c->d.fA, c->d.fB);
+    std::swap(c->d.phiA, c->d.phiB);
+    c->step += 1;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return FSLBM_OK;
+}
+
+int read_status(fslbm_ctx* c) {
+  int32_t cnt[CNT_N];
+  HIPCHK(c, hipMemcpyAsync(cnt, c->d.cnt, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int err = cnt[CNT_ERR];
+  if (err & ERR_SCAN) {
+    c->status = FSLBM_EDEVICE;
+    return set_err(c, FSLBM_EDEVICE, "interface-list scan did not complete");
+  }
+  if (err & (ERR_UNSTABLE | ERR_LAYER)) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "instability detected by step %lld (%s)", (long long)c->step,
+             (err & ERR_LAYER) ? "liquid cell next to gas" : "NaN, rho <= 0 or |u| >= c_s");
+    return set_err(c, FSLBM_EUNSTABLE, buf);
+  }
+  return FSLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fslbm_workspace_bytes(const fslbm_params* p, size_t* bytes) {
+  if (!bytes) return FSLBM_EINVAL;
+  const char* why = validate(p);
+  if (why) {
+    snprintf(g_create_error, sizeof g_create_error, "%s", why);
+    return FSLBM_EINVAL;
+  }
+  *bytes = make_layout(*p).total;
+  return FSLBM_OK;
+}
+
+int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, const double* rho,
+                 const double* ux, const double* uy, const double* uz, const double* pdf_or_null,
+                 const double* mass_or_null, void* device_arena_or_null, size_t arena_bytes,
+                 void* hip_stream, fslbm_ctx** out) {
+  if (!out) return FSLBM_EINVAL;
+  *out = nullptr;
+  const char* why = validate(p);
+  if (!why && (!type || !phi || !rho || !ux || !uy || !uz)) why = "field pointer is NULL";
+  if (why) {
+    snprintf(g_create_error, sizeof g_create_error, "%s", why);
+    return FSLBM_EINVAL;
+  }
+  fslbm_ctx* c = new (std::nothrow) fslbm_ctx();
+  if (!c) return FSLBM_ENOMEM;
+  c->p = *p;
+  c->L = make_layout(*p);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (device_arena_or_null) {
+    if (arena_bytes < c->L.total) {
+      snprintf(g_create_error, sizeof g_create_error, "arena of %zu bytes, %zu needed", arena_bytes,
+               c->L.total);
+      delete c;
+      return FSLBM_ENOMEM;
+    }
+    c->arena = static_cast<char*>(device_arena_or_null);
+  } else {
+    void* a = nullptr;
+    if (hipMalloc(&a, c->L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      snprintf(g_create_error, sizeof g_create_error, "hipMalloc of %zu bytes failed", c->L.total);
+      delete c;
+      return FSLBM_ENOMEM;
+    }
+    c->arena = static_cast<char*>(a);
+    c->own_arena = true;
+  }
+  bind(c);
+  const Ops ops = pick(c->p);
+  hipStream_t s = c->stream;
+  const int64_t N = c->L.N;
+  auto fail = [&](int st) {
+    snprintf(g_create_error, sizeof g_create_error, "%s", c->last_error.c_str());
+    fslbm_destroy(c);
+    return st;
+  };
+#define INITCHK(expr)                                      \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return fail(hip_fail(c, e_, #expr)); \
+  } while (0)
+  INITCHK(hipMemsetAsync(c->d.cnt, 0, 4 * CNT_N, s));
+  INITCHK(hipMemsetAsync(c->d.scan_if, 0, 8 * c->L.tiles, s));
+  INITCHK(hipMemsetAsync(c->d.scan_cv, 0, 8 * c->L.tiles, s));
+  INITCHK(hipMemsetAsync(c->d.fB, 0, (size_t)c->p.q * c->L.stride * storage_bytes(c->p.storage), s));
+  // types go straight into the flag array, fields into buffers used as staging
+  INITCHK(hipMemcpyAsync(c->d.flags, type, N, hipMemcpyHostToDevice, s));
+  INITCHK(hipMemcpyAsync(c->d.phiA, phi, 8 * N, hipMemcpyHostToDevice, s));
+  INITCHK(hipMemcpyAsync(c->d.rho_if, rho, 8 * N, hipMemcpyHostToDevice, s));
+  INITCHK(hipMemcpyAsync(c->d.m, ux, 8 * N, hipMemcpyHostToDevice, s));
+  INITCHK(hipMemcpyAsync(c->d.lost, uy, 8 * N, hipMemcpyHostToDevice, s));
+  INITCHK(hipMemcpyAsync(c->d.phiB, uz, 8 * N, hipMemcpyHostToDevice, s));
+  ops.init_flags(c, s);
+  hipLaunchKernelGGL(k_apply_border, dim3(grid_for(N)), dim3(kBlock), 0, s, c->d);
+  int32_t cnt[CNT_N];
+  INITCHK(hipMemcpyAsync(cnt, c->d.cnt, sizeof cnt, hipMemcpyDeviceToHost, s));
+  INITCHK(hipStreamSynchronize(s));
+  if (cnt[CNT_ERR] & ERR_TYPE) {
+    c->last_error = "unknown cell type in the initial types";
+    return fail(FSLBM_EINVAL);
+  }
+  if (cnt[CNT_ERR] & ERR_LAYER) {
+    c->last_error = "a liquid cell touches a gas cell: the interface layer is not closed";
+    return fail(FSLBM_EINVAL);
+  }
+  const bool resume = pdf_or_null != nullptr;
+  if (resume) {
+    for (int k = 0; k < c->p.q; ++k) {
+      INITCHK(hipMemcpyAsync(stage(c), pdf_or_null + (size_t)k * N, 8 * N, hipMemcpyHostToDevice, s));
+      ops.import_plane(c, s, stage(c), k);
+    }
+  }
+  ops.init_state(c, s, resume ? 1 : 0);
+  if (resume && mass_or_null) {
+    // interface mass verbatim; liquid/gas entries are ignored by the step
+    INITCHK(hipMemcpyAsync(c->d.m, mass_or_null, 8 * N, hipMemcpyHostToDevice, s));
+  }
+  // interface list, flux classes, volume pressure
+  c->d.step = 0;
+  c->d.epoch = ++c->epoch;
+  ops.convert(c, s, 1);
+  ops.finish(c, s, 1);
+  const double pv0[3] = {c->p.rho_gas / 3.0, c->p.rho_gas / 3.0, 0.0};
+  INITCHK(hipMemcpyAsync(c->d.pV, pv0, sizeof pv0, hipMemcpyHostToDevice, s));
+  // V(0) from phiB == phiA at this point
+  launch_volume(c, s, true);
+  INITCHK(hipGetLastError());
+  INITCHK(hipStreamSynchronize(s));
+#undef INITCHK
+  *out = c;
+  return FSLBM_OK;
+}
+
+int fslbm_set_variant(fslbm_ctx* c, int variant) {
+  if (!c) return FSLBM_EINVAL;
+  if (variant < FSLBM_NBRC || variant > FSLBM_OM3) return set_err(c, FSLBM_EINVAL, "unknown variant");
+  c->p.variant = variant;
+  c->d.variant = variant;
+  return FSLBM_OK;
+}
+
+int fslbm_step(fslbm_ctx* c, int64_t nsteps) {
+  if (!c) return FSLBM_EINVAL;
+  if (nsteps < 0) return set_err(c, FSLBM_EINVAL, "nsteps < 0");
+  if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  return enqueue_steps(c, nsteps);
+}
+
+int fslbm_mass(fslbm_ctx* c, fslbm_mass_report* r) {
+  if (!c || !r) return FSLBM_EINVAL;
+  if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  const Ops ops = pick(c->p);
+  hipStream_t s = c->stream;
+  ops.reduce_mass(c, s);
+  double* out = c->d.partial + kRedN * c->L.red_blocks;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, c->d.partial, (int)c->L.red_blocks,
+                     kRedN, out);
+  double v[kRedN], pv[3];
+  HIPCHK(c, hipMemcpyAsync(v, out, sizeof v, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(pv, c->d.pV, sizeof pv, hipMemcpyDeviceToHost, s));
+  const int st = read_status(c);
+  if (st == FSLBM_EDEVICE) return st;
+  r->liquid_mass = v[0];
+  r->interface_mass = v[1];
+  r->lost_mass = v[2];
+  r->total_mass = v[0] + v[1] + v[2];
+  r->bubble_volume = v[3];
+  r->p_volume = pv[0];
+  r->n_liquid = (int64_t)v[4];
+  r->n_interface = (int64_t)v[5];
+  r->n_gas = (int64_t)v[6];
+  r->step = c->step;
+  return st;
+}
+
+int fslbm_fields(fslbm_ctx* c, uint8_t* type, double* phi, double* rho, double* ux, double* uy,
+                 double* uz, double* mass, double* pdf) {
+  if (!c) return FSLBM_EINVAL;
+  if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  const Ops ops = pick(c->p);
+  hipStream_t s = c->stream;
+  const int64_t N = c->L.N;
+  double* st = stage(c);
+  if (type) {
+    std::vector<uint8_t> fl(N);
+    HIPCHK(c, hipMemcpyAsync(fl.data(), c->d.flags, N, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int64_t i = 0; i < N; ++i) type[i] = fl[i] & T_MASK;
+  }
+  double* outs[6] = {rho, ux, uy, uz, mass, phi};
+  for (int w = 0; w < 6; ++w) {
+    if (!outs[w]) continue;
+    ops.export_field(c, s, st, w);
+    HIPCHK(c, hipMemcpyAsync(outs[w], st, 8 * N, hipMemcpyDeviceToHost, s));
+  }
+  if (pdf) {
+    for (int k = 0; k < c->p.q; ++k) {
+      ops.export_field(c, s, st, 10 + k);
+      HIPCHK(c, hipMemcpyAsync(pdf + (size_t)k * N, st, 8 * N, hipMemcpyDeviceToHost, s));
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  return read_status(c);
+}
+
+int fslbm_interface_list(fslbm_ctx* c, int32_t* list, int64_t max, int64_t* count) {
+  if (!c || !count) return FSLBM_EINVAL;
+  int32_t cnt[CNT_N];
+  HIPCHK(c, hipMemcpyAsync(cnt, c->d.cnt, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *count = cnt[CNT_IF];
+  if (list && max > 0) {
+    const int64_t n = std::min<int64_t>(max, cnt[CNT_IF]);
+    HIPCHK(c, hipMemcpyAsync(list, c->d.if_list, 4 * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return FSLBM_OK;
+}
+
+static void release_events(fslbm_ctx* c) {
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  c->ev_used = 0;
+}
+
+int fslbm_set_timing(fslbm_ctx* c, int64_t capacity) {
+  if (!c || capacity < 0) return FSLBM_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  release_events(c);
+  c->ev.reserve((size_t)(2 * capacity));
+  for (int64_t i = 0; i < 2 * capacity; ++i) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  return FSLBM_OK;
+}
+
+int fslbm_kernel_time(fslbm_ctx* c, int64_t* launches, double* total_ms) {
+  if (!c || !launches || !total_ms) return FSLBM_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double t = 0.0;
+  for (int64_t i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    t += ms;
+  }
+  *launches = c->ev_used;
+  *total_ms = t;
+  return FSLBM_OK;
+}
+
+void fslbm_destroy(fslbm_ctx* c) {
+  if (!c) return;
+  if (c->arena) {
+    (void)hipStreamSynchronize(c->stream);
+    if (c->own_arena) (void)hipFree(c->arena);
+  }
+  release_events(c);
+  delete c;
+}
+
+const char* fslbm_strerror(int status) {
+  switch (status) {
+    case FSLBM_OK: return "ok";
+    case FSLBM_EINVAL: return "invalid argument";
+    case FSLBM_ENOMEM: return "out of device memory";
+    case FSLBM_EDEVICE: return "device error";
+    case FSLBM_EUNSTABLE: return "simulation unstable";
+    case FSLBM_ESTATE: return "invalid state";
+    case FSLBM_EBUDGET: return "request exceeds the memory budget";
+    default: return "unknown status";
+  }
+}
+
+const char* fslbm_last_error(const fslbm_ctx* c) {
+  if (!c) return g_create_error;
+  return c->last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,374 @@
+// Device-side building blocks of the free-surface LBM step for gfx950:
+// lattice tables, cell flags, population storage codecs, neighbour resolution,
+// collision. Everything here is header-only and templated on the lattice (Q),
+// the storage format (S) and the collision operator (TRT) so that the direction
+// loops unroll into immediate offsets.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fslbm {
+
+// ---------------------------------------------------------------------------
+// Velocity sets (Sec. 2.1). Direction k: rest; +-x, +-y, +-z; the twelve edge
+// directions; the eight corners. D3Q19 uses k < 19, D3Q27 all 27. Opposite
+// pairs are (1,2), (3,4), ..., (25,26). The order is part of the exported
+// population layout.
+// ---------------------------------------------------------------------------
+constexpr int kCX[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                         1, -1, 1, -1, 1, -1, -1, 1};
+constexpr int kCY[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                         1, -1, 1, -1, -1, 1, 1, -1};
+constexpr int kCZ[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                         1, -1, -1, 1, 1, -1, 1, -1};
+
+__host__ __device__ constexpr int opp(int k) { return k == 0 ? 0 : ((k & 1) ? k + 1 : k - 1); }
+
+template <int Q>
+__host__ __device__ constexpr double weight(int k) {
+  return Q == 19
+             ? (k == 0 ? 1.0 / 3.0 : (k < 7 ? 1.0 / 18.0 : 1.0 / 36.0))
+             : (k == 0 ? 8.0 / 27.0 : (k < 7 ? 2.0 / 27.0 : (k < 19 ? 1.0 / 54.0 : 1.0 / 216.0)));
+}
+
+// ---------------------------------------------------------------------------
+// Cell flags: one byte per cell.
+//   bits 0-2 type: gas, interface, liquid, no-slip obstacle, free-slip obstacle
+//   bit 3 BORDER   (static) the 3x3x3 neighbourhood leaves the domain or holds
+//                  an obstacle: neighbour lookups need wrap/wall handling
+//   bit 4 NEW_GAS  became interface from gas in the last conversion
+//   bit 5 NEW_LIQ  became interface from liquid in the last conversion
+//   bit 6 CONV     interface cell converted to liquid or gas in the last conversion
+// ---------------------------------------------------------------------------
+enum : uint8_t { T_GAS = 0, T_IF = 1, T_LIQ = 2, T_NOSLIP = 3, T_FREESLIP = 4 };
+constexpr uint8_t T_MASK = 7;
+constexpr uint8_t F_BORDER = 8;
+constexpr uint8_t F_NEW_GAS = 16;
+constexpr uint8_t F_NEW_LIQ = 32;
+constexpr uint8_t F_CONV = 64;
+constexpr uint8_t F_TRANSIENT = F_NEW_GAS | F_NEW_LIQ | F_CONV;
+
+__host__ __device__ inline bool is_obst(int t) { return t == T_NOSLIP || t == T_FREESLIP; }
+__host__ __device__ inline bool is_fluid(int t) { return t == T_IF || t == T_LIQ; }
+
+enum : uint8_t { MK_NONE = 0, MK_L = 1, MK_G = 2 };
+enum : uint8_t { CLS_STD = 0, CLS_NOLIQ = 1, CLS_NOGAS = 2 };
+enum { BND_PERIODIC = 0, BND_NOSLIP = 1, BND_FREESLIP = 2 };
+
+// Counter slots in device memory.
+enum {
+  CNT_IF = 0,      // interface cells in the list
+  CNT_CONV = 1,    // converted cells in the list
+  CNT_MARK0 = 2,   // marked cells, slot (step & 1)
+  CNT_TICKET = 4,  // block tickets of the compaction scan
+  CNT_ERR = 5,     // error bits (see ERR_*)
+  CNT_N = 8
+};
+enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8 };
+
+// ---------------------------------------------------------------------------
+// Population storage. R is the arithmetic type; kShift tells whether the
+// values handled by the kernels are f_k or h_k = f_k - w_k.
+// ---------------------------------------------------------------------------
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2 };
+
+template <int S, int Q>
+struct Store;
+
+// F64 keeps f itself (binary64 arithmetic, the reference path). The FP32
+// formats keep the shifted population h_k = f_k - w_k: near rest f_k is close to
+// its weight, so h_k carries the significant digits, and mass sums 1 + sum h
+// do not pick up the rounding of the weights. F32 stores h in binary32, F16S in
+// binary16 (round to nearest even); arithmetic is binary32 in both.
+template <int Q>
+struct Store<ST_F64, Q> {
+  using T = double;
+  using R = double;
+  static constexpr bool kShift = false;
+  static __device__ __forceinline__ R ld(const T* p, int64_t o, int) { return p[o]; }
+  static __device__ __forceinline__ void st(T* p, int64_t o, int, R v) { p[o] = v; }
+};
+
+template <int Q>
+struct Store<ST_F32, Q> {
+  using T = float;
+  using R = float;
+  static constexpr bool kShift = true;
+  static __device__ __forceinline__ R ld(const T* p, int64_t o, int) { return p[o]; }
+  static __device__ __forceinline__ void st(T* p, int64_t o, int, R v) { p[o] = v; }
+};
+
+template <int Q>
+struct Store<ST_F16S, Q> {
+  using T = _Float16;
+  using R = float;
+  static constexpr bool kShift = true;
+  static __device__ __forceinline__ R ld(const T* p, int64_t o, int) {
+    return static_cast<float>(p[o]);
+  }
+  static __device__ __forceinline__ void st(T* p, int64_t o, int, R v) {
+    p[o] = static_cast<_Float16>(v);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Geometry and neighbour lookup.
+// ---------------------------------------------------------------------------
+struct Geom {
+  int nx, ny, nz;
+  int bnd[6];
+  int64_t N;       // nx*ny*nz
+  int64_t stride;  // distance between population planes (>= N)
+};
+
+__device__ __forceinline__ void coords(const Geom& g, int64_t c, int& x, int& y, int& z) {
+  int64_t nxy = (int64_t)g.nx * g.ny;
+  z = (int)(c / nxy);
+  int64_t r = c - (int64_t)z * nxy;
+  y = (int)(r / g.nx);
+  x = (int)(r - (int64_t)y * g.nx);
+}
+
+// Index of (x,y,z)+(dx,dy,dz) after periodic wrap, or -1 beyond a wall face;
+// *wall receives the ghost's obstacle type (no-slip wins where faces meet).
+__device__ __forceinline__ int64_t nb_index(const Geom& g, int x, int y, int z, int dx, int dy,
+                                            int dz, int* wall) {
+  int c[3] = {x + dx, y + dy, z + dz};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int w = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int face = -1;
+    if (c[a] < 0)
+      face = 2 * a;
+    else if (c[a] >= n[a])
+      face = 2 * a + 1;
+    if (face < 0) continue;
+    int b = g.bnd[face];
+    if (b == BND_PERIODIC) {
+      int m = c[a] % n[a];
+      c[a] = m < 0 ? m + n[a] : m;
+    } else {
+      int t = (b == BND_NOSLIP) ? T_NOSLIP : T_FREESLIP;
+      if (w != T_NOSLIP) w = t;
+    }
+  }
+  *wall = w;
+  if (w) return -1;
+  return c[0] + (int64_t)g.nx * (c[1] + (int64_t)g.ny * c[2]);
+}
+
+// Type of a neighbour (ghost walls included) and its index (-1 for ghosts).
+__device__ __forceinline__ int nb_type(const Geom& g, const uint8_t* flags, int x, int y, int z,
+                                       int dx, int dy, int dz, int64_t* idx) {
+  int w;
+  int64_t j = nb_index(g, x, y, z, dx, dy, dz, &w);
+  *idx = j;
+  if (j < 0) return w;
+  return flags[j] & T_MASK;
+}
+
+// Where the population arriving at x in direction k comes from (Sec. 2.1 walls):
+// plain neighbour x - c_k; bounce-back at a no-slip obstacle; specular reflection
+// at a free-slip obstacle (the axes along which the one-axis step back is an
+// obstacle are mirrored; the population leaves y in direction j). A gas source
+// (directly or after reflection) is reported as SRC_GAS.
+enum { SRC_FLUID = 0, SRC_GAS = 1, SRC_BOUNCE = 2 };
+
+// Specular part of resolve_source (free-slip source).
+template <int Q>
+__device__ __forceinline__ int reflect_source(const Geom& g, const uint8_t* flags, int x, int y, int z,
+                                           int k, int64_t* src, int* dir) {
+  const int c[3] = {kCX[k], kCY[k], kCZ[k]};
+  int d[3] = {-c[0], -c[1], -c[2]};
+  int cj[3] = {c[0], c[1], c[2]};
+  bool any = false;
+  for (int a = 0; a < 3; ++a) {
+    if (c[a] == 0) continue;
+    int e[3] = {0, 0, 0};
+    e[a] = -c[a];
+    int64_t jj;
+    if (is_obst(nb_type(g, flags, x, y, z, e[0], e[1], e[2], &jj))) {
+      d[a] += c[a];
+      cj[a] = -c[a];
+      any = true;
+    }
+  }
+  if (!any) return SRC_BOUNCE;
+  int64_t yi;
+  int ty = nb_type(g, flags, x, y, z, d[0], d[1], d[2], &yi);
+  if (is_obst(ty)) return SRC_BOUNCE;
+  if (ty == T_GAS) return SRC_GAS;
+  *src = yi;
+  int r = 0;
+  for (int i = 0; i < Q; ++i)
+    if (kCX[i] == cj[0] && kCY[i] == cj[1] && kCZ[i] == cj[2]) r = i;
+  *dir = r;
+  return SRC_FLUID;
+}
+
+template <int Q>
+__device__ __forceinline__ int resolve_source(const Geom& g, const uint8_t* flags, int x, int y,
+                                              int z, int k, int64_t* src, int* dir, bool* wall) {
+  int64_t j;
+  int st = nb_type(g, flags, x, y, z, -kCX[k], -kCY[k], -kCZ[k], &j);
+  *dir = k;
+  *src = j;
+  *wall = is_obst(st);
+  if (st == T_GAS) return SRC_GAS;
+  if (is_fluid(st)) return SRC_FLUID;
+  if (st == T_NOSLIP) return SRC_BOUNCE;
+  return reflect_source<Q>(g, flags, x, y, z, k, src, dir);
+}
+
+// ---------------------------------------------------------------------------
+// Collision (Sec. 2.1): moments with the half-force shift, second-order
+// equilibrium, Guo source, SRT or TRT relaxation. The operation order follows
+// the definitions term by term; built without contraction so that every step
+// is one rounded IEEE operation.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct CollideParams {
+  R omega, omega_m;  // 1/tau and the TRT antisymmetric rate
+  R gx, gy, gz;
+};
+
+template <typename R, int Q, bool SH>
+__device__ __forceinline__ void moments(const R* f, R gx, R gy, R gz, R& rho, R& dr, R& ux, R& uy,
+                                        R& uz) {
+  R r = R(0), j0 = R(0), j1 = R(0), j2 = R(0);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) r += f[k];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if (kCX[k] > 0) j0 += f[k];
+    if (kCX[k] < 0) j0 += -f[k];
+    if (kCY[k] > 0) j1 += f[k];
+    if (kCY[k] < 0) j1 += -f[k];
+    if (kCZ[k] > 0) j2 += f[k];
+    if (kCZ[k] < 0) j2 += -f[k];
+  }
+  // shifted values: sum h = rho - 1 (the weights sum to one, their first
+  // moment vanishes)
+  dr = SH ? r : r - R(1);
+  rho = SH ? R(1) + r : r;
+  ux = (j0 + R(0.5) * (rho * gx)) / rho;
+  uy = (j1 + R(0.5) * (rho * gy)) / rho;
+  uz = (j2 + R(0.5) * (rho * gz)) / rho;
+}
+
+// Velocity of the collision that produced the post-collision populations fs:
+// sum c f* = sum c f + F, so u = (sum c f* - F/2) / rho with rho = sum f*.
+template <typename R, int Q, bool SH>
+__device__ __forceinline__ void post_moments(const R* fs, R gx, R gy, R gz, R& rho, R& ux, R& uy,
+                                             R& uz) {
+  R r = R(0), j0 = R(0), j1 = R(0), j2 = R(0);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) r += fs[k];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if (kCX[k] > 0) j0 += fs[k];
+    if (kCX[k] < 0) j0 += -fs[k];
+    if (kCY[k] > 0) j1 += fs[k];
+    if (kCY[k] < 0) j1 += -fs[k];
+    if (kCZ[k] > 0) j2 += fs[k];
+    if (kCZ[k] < 0) j2 += -fs[k];
+  }
+  rho = SH ? R(1) + r : r;
+  ux = (j0 - R(0.5) * (rho * gx)) / rho;
+  uy = (j1 - R(0.5) * (rho * gy)) / rho;
+  uz = (j2 - R(0.5) * (rho * gz)) / rho;
+}
+
+// rho = sum of the populations in binary64 (mass bookkeeping).
+template <typename R, int Q, bool SH>
+__device__ __forceinline__ double density64(const R* f) {
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) r += (double)f[k];
+  return SH ? 1.0 + r : r;
+}
+
+template <typename R>
+__device__ __forceinline__ R cdot(int cx, int cy, int cz, R ax, R ay, R az) {
+  // c.a for c in {-1,0,1}^3 without multiplications (exact)
+  R s = R(0);
+  if (cx > 0) s += ax;
+  if (cx < 0) s += -ax;
+  if (cy > 0) s += ay;
+  if (cy < 0) s += -ay;
+  if (cz > 0) s += az;
+  if (cz < 0) s += -az;
+  return s;
+}
+
+// Equilibrium (Sec. 2.1) of direction k; shifted: feq_k - w_k, written with
+// dr = rho - 1 so that no large term cancels.
+template <typename R, int Q, bool SH>
+__device__ __forceinline__ R feq_k(int k, R rho, R dr, R cu, R usq) {
+  if (SH) return R(weight<Q>(k)) * (dr + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq));
+  return R(weight<Q>(k)) * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
+}
+
+// f <- collide(f); returns pre-collision rho and u (u with the half-force shift).
+// The shift commutes with the relaxation (f - feq = h - heq) and the source sums
+// to zero, so the same update applies to f and to h.
+template <typename R, int Q, bool TRT, bool SH>
+__device__ __forceinline__ void collide(R* f, const CollideParams<R>& cp, R& rho, R& ux, R& uy,
+                                        R& uz) {
+  R dr;
+  moments<R, Q, SH>(f, cp.gx, cp.gy, cp.gz, rho, dr, ux, uy, uz);
+  const R Fx = rho * cp.gx, Fy = rho * cp.gy, Fz = rho * cp.gz;
+  const R usq = ux * ux + uy * uy + uz * uz;
+  const R om = cp.omega;
+  if (!TRT) {
+    const R sf = R(1) - R(0.5) * om;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const R cu = cdot<R>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
+      const R cF = cdot<R>(kCX[k], kCY[k], kCZ[k], Fx, Fy, Fz);
+      const R cmuF = (R(kCX[k]) - ux) * Fx + (R(kCY[k]) - uy) * Fy + (R(kCZ[k]) - uz) * Fz;
+      const R fe = feq_k<R, Q, SH>(k, rho, dr, cu, usq);
+      const R S = R(weight<Q>(k)) * (R(3) * cmuF + R(9) * cu * cF);
+      f[k] = f[k] - om * (f[k] - fe) + sf * S;
+    }
+    return;
+  }
+  const R omm = cp.omega_m;
+  const R sp = R(1) - R(0.5) * om, sm = R(1) - R(0.5) * omm;
+  R fe[Q], S[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const R cu = cdot<R>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
+    const R cF = cdot<R>(kCX[k], kCY[k], kCZ[k], Fx, Fy, Fz);
+    const R cmuF = (R(kCX[k]) - ux) * Fx + (R(kCY[k]) - uy) * Fy + (R(kCZ[k]) - uz) * Fz;
+    fe[k] = feq_k<R, Q, SH>(k, rho, dr, cu, usq);
+    S[k] = R(weight<Q>(k)) * (R(3) * cmuF + R(9) * cu * cF);
+  }
+  R out[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const int kb = opp(k);
+    const R fp = R(0.5) * (f[k] + f[kb]), fm = R(0.5) * (f[k] - f[kb]);
+    const R ep = R(0.5) * (fe[k] + fe[kb]), em = R(0.5) * (fe[k] - fe[kb]);
+    const R p = R(0.5) * (S[k] + S[kb]), m = R(0.5) * (S[k] - S[kb]);
+    out[k] = f[k] - om * (fp - ep) - omm * (fm - em) + sp * p + sm * m;
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) f[k] = out[k];
+}
+
+// Anti-bounce-back value (Sec. 2.2): feq_k + feq_kbar at (rhoG, u) minus the
+// cell's own post-collision f*_kbar; the odd parts cancel. Shifted:
+// h_k = 2 w_k (rhoG - 1 + rhoG (4.5 (c.u)^2 - 1.5 u^2)) - h*_kbar.
+template <typename R, int Q, bool SH>
+__device__ __forceinline__ R abb_value(int k, R rhoG, R ux, R uy, R uz, R usq, R fs_kbar) {
+  const R cu = cdot<R>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
+  if (SH)
+    return R(2) * R(weight<Q>(k)) * ((rhoG - R(1)) + rhoG * (R(4.5) * cu * cu - R(1.5) * usq)) -
+           fs_kbar;
+  return R(2) * R(weight<Q>(k)) * rhoG * (R(1) + R(4.5) * cu * cu - R(1.5) * usq) - fs_kbar;
+}
+
+}  // namespace fslbm

@@ -1,0 +1,190 @@
+// Context, device memory layout and the per-format kernel table of libfslbm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fslbm.h"
+#include "fslbm_kernels.h"
+
+using namespace fslbm;
+
+namespace fslbm_host {
+
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+inline int storage_bytes(int storage) { return storage == FSLBM_F64 ? 8 : (storage == FSLBM_F32 ? 4 : 2); }
+
+// Device memory layout (one arena, 256-byte aligned sub-buffers).
+struct Layout {
+  int64_t N, stride, tiles, red_blocks;
+  size_t off_fA, off_fB, off_flags, off_mark, off_cls, off_phiA, off_phiB, off_m, off_rho_if,
+      off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_cnt, off_scan_if, off_scan_cv,
+      off_pv, off_partial, off_stage, total;
+};
+
+constexpr int kRedCells = 8192;  // cells per reduction block
+
+inline Layout make_layout(const fslbm_params& p) {
+  Layout L{};
+  L.N = (int64_t)p.nx * p.ny * p.nz;
+  L.stride = round_up(L.N, 256);
+  L.tiles = (L.N + kConvTile - 1) / kConvTile;
+  L.red_blocks = (L.N + kRedCells - 1) / kRedCells;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (size_t)round_up((int64_t)bytes, 256);
+    return at;
+  };
+  const size_t pdf = (size_t)p.q * (size_t)L.stride * storage_bytes(p.storage);
+  L.off_fA = take(pdf);
+  L.off_fB = take(pdf);
+  L.off_flags = take(L.N);
+  L.off_mark = take(L.N);
+  L.off_cls = take(L.N);
+  L.off_phiA = take(8 * L.N);
+  L.off_phiB = take(8 * L.N);
+  L.off_m = take(8 * L.N);
+  L.off_rho_if = take(8 * L.N);
+  L.off_rhoG = take(p.sigma != 0.0 ? 8 * L.N : 0);
+  L.off_phis = take(p.sigma != 0.0 ? 8 * L.N : 0);
+  L.off_lost = take(8 * L.N);
+  L.off_if_list = take(4 * L.N);
+  L.off_conv_list = take(4 * L.N);
+  L.off_cnt = take(4 * CNT_N);
+  L.off_scan_if = take(8 * L.tiles);
+  L.off_scan_cv = take(8 * L.tiles);
+  L.off_pv = take(8 * 8);
+  L.off_partial = take(8 * kRedN * L.red_blocks + 8 * 16);
+  L.off_stage = take(8 * L.N);
+  L.total = o;
+  return L;
+}
+
+inline const char* validate(const fslbm_params* p) {
+  if (!p) return "params is NULL";
+  if (p->abi_version != FSLBM_ABI_VERSION) return "abi_version mismatch";
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "nx, ny, nz must be >= 1";
+  if ((int64_t)p->nx * p->ny * p->nz >= (1LL << 30)) return "domain larger than 2^30 cells";
+  if (p->q != 19 && p->q != 27) return "q must be 19 or 27";
+  if (p->collision != FSLBM_SRT && p->collision != FSLBM_TRT) return "unknown collision operator";
+  if (p->storage < FSLBM_F64 || p->storage > FSLBM_F16S) return "unknown storage format";
+  for (int f = 0; f < 6; ++f)
+    if (p->boundary[f] < FSLBM_PERIODIC || p->boundary[f] > FSLBM_WALL_FREESLIP)
+      return "unknown boundary kind";
+  for (int a = 0; a < 3; ++a)
+    if ((p->boundary[2 * a] == FSLBM_PERIODIC) != (p->boundary[2 * a + 1] == FSLBM_PERIODIC))
+      return "a periodic face needs a periodic opposite face";
+  if (p->variant < FSLBM_NBRC || p->variant > FSLBM_OM3) return "unknown variant";
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return "tau must be > 0.5";
+  if (p->collision == FSLBM_TRT && !(p->trt_lambda > 0.0)) return "trt_lambda must be > 0";
+  if (!(p->rho_gas > 0.0)) return "rho_gas must be > 0";
+  if (!(p->eps_phi >= 0.0)) return "eps_phi must be >= 0";
+  if (p->sigma < 0.0) return "sigma must be >= 0";
+  return nullptr;
+}
+
+}  // namespace fslbm_host
+
+struct fslbm_ctx {
+  fslbm_params p;
+  fslbm_host::Layout L;
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  bool own_arena = false;
+  Dev d{};
+  int64_t step = 0;
+  uint32_t epoch = 0;
+  int status = FSLBM_OK;  // sticky device / runtime failure
+  std::string last_error;
+  // optional events around the liquid stream-collide launches
+  std::vector<hipEvent_t> ev;
+  int64_t ev_used = 0;
+};
+
+
+namespace fslbm_host {
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// interface blocks of k_step: enough to cover a large interface list with few
+// launches' worth of work per thread
+inline unsigned if_blocks(const fslbm_ctx* c) {
+  int64_t b = grid_for(c->L.N) / 8 + 64;
+  return (unsigned)std::min<int64_t>(b, 4096);
+}
+
+inline unsigned finish_blocks(const fslbm_ctx* c) {
+  int64_t b = grid_for(c->L.N) / 16 + 64;
+  return (unsigned)std::min<int64_t>(b, 2048);
+}
+
+// Kernel table for one (storage, lattice, collision) combination.
+struct Ops {
+  void (*step)(fslbm_ctx*, hipStream_t);
+  void (*convert)(fslbm_ctx*, hipStream_t, int rebuild_only);
+  void (*finish)(fslbm_ctx*, hipStream_t, int classes_only);
+  void (*reduce_mass)(fslbm_ctx*, hipStream_t);
+  void (*init_state)(fslbm_ctx*, hipStream_t, int resume);
+  void (*init_flags)(fslbm_ctx*, hipStream_t);
+  void (*import_plane)(fslbm_ctx*, hipStream_t, const double*, int);
+  void (*export_field)(fslbm_ctx*, hipStream_t, double*, int);
+};
+
+template <int S, int Q, bool TRT>
+struct Impl {
+  static void step(fslbm_ctx* c, hipStream_t s) {
+    const bool timed = 2 * (c->ev_used + 1) <= (int64_t)c->ev.size();
+    if (timed) hipEventRecord(c->ev[2 * c->ev_used], s);
+    hipLaunchKernelGGL((k_liquid<S, Q, TRT>), dim3(grid_for(c->L.N)), dim3(kBlock), 0, s, c->d);
+    if (timed) hipEventRecord(c->ev[2 * c->ev_used++ + 1], s);
+    hipLaunchKernelGGL((k_interface<S, Q, TRT>), dim3(if_blocks(c)), dim3(kBlock), 0, s, c->d);
+  }
+  static void convert(fslbm_ctx* c, hipStream_t s, int rebuild) {
+    hipLaunchKernelGGL((k_convert<Q>), dim3((unsigned)c->L.tiles), dim3(kBlock), 0, s, c->d,
+                       rebuild);
+  }
+  static void finish(fslbm_ctx* c, hipStream_t s, int classes_only) {
+    hipLaunchKernelGGL((k_finish<S, Q, TRT>), dim3(finish_blocks(c)), dim3(kBlock), 0, s, c->d,
+                       classes_only);
+  }
+  static void reduce_mass(fslbm_ctx* c, hipStream_t s) {
+    hipLaunchKernelGGL((k_reduce_mass<S, Q>), dim3((unsigned)c->L.red_blocks), dim3(kBlock), 0, s,
+                       c->d, kRedCells);
+  }
+  static void init_state(fslbm_ctx* c, hipStream_t s, int resume) {
+    hipLaunchKernelGGL((k_init_state<S, Q, TRT>), dim3(grid_for(c->L.N)), dim3(kBlock), 0, s, c->d,
+                       resume);
+  }
+  static void init_flags(fslbm_ctx* c, hipStream_t s) {
+    hipLaunchKernelGGL((k_init_flags<Q>), dim3(grid_for(c->L.N)), dim3(kBlock), 0, s, c->d);
+  }
+  static void import_plane(fslbm_ctx* c, hipStream_t s, const double* src, int k) {
+    hipLaunchKernelGGL((k_import_plane<S, Q>), dim3(grid_for(c->L.N)), dim3(kBlock), 0, s, c->d,
+                       src, k);
+  }
+  static void export_field(fslbm_ctx* c, hipStream_t s, double* out, int what) {
+    hipLaunchKernelGGL((k_export<S, Q>), dim3(grid_for(c->L.N)), dim3(kBlock), 0, s, c->d, out,
+                       what);
+  }
+  static constexpr Ops ops() {
+    return Ops{&step, &convert, &finish, &reduce_mass, &init_state, &init_flags, &import_plane,
+               &export_field};
+  }
+};
+
+
+Ops ops_f64_q19(int coll);
+Ops ops_f64_q27(int coll);
+Ops ops_f32_q19(int coll);
+Ops ops_f32_q27(int coll);
+Ops ops_f16s_q19(int coll);
+Ops ops_f16s_q27(int coll);
+
+}  // namespace fslbm_host

@@ -1,0 +1,73 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and validates parameters on the host (no GPU call is made)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2207_13962_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fslbm.h")).read()
+    return sorted(set(re.findall(r"\b(fslbm_[a-z_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_2207_13962_amd import fslbm
+    if not os.path.exists(fslbm.LIB_PATH):
+        from paper_2207_13962_amd import build
+        build.build()
+    return fslbm
+
+
+def test_exports_every_declared_symbol():
+    fs = _lib()
+    lib = C.CDLL(fs.LIB_PATH)
+    names = _declared_symbols()
+    assert "fslbm_create" in names and "fslbm_step" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(fs.EXPORTED) <= set(names)
+
+
+def test_workspace_bytes_and_validation():
+    fs = _lib()
+    p = I.Params(256, 128, 64, q=19, storage=I.F32, collision=I.TRT, tau=0.503)
+    n = fs.workspace_bytes(p)
+    # two population grids of 19 x N floats dominate
+    assert n > 2 * 19 * p.n * 4
+    assert fs.workspace_bytes(p.with_(storage=I.F64)) > n
+    assert fs.workspace_bytes(p.with_(storage=I.F16S)) < n
+    bad = [p.with_(q=15), p.with_(tau=0.5), p.with_(variant=7), p.with_(nx=0),
+           p.with_(storage=9), p.with_(boundary=(0, 1, 1, 1, 1, 1))]
+    for b in bad:
+        with pytest.raises(fs.FslbmError) as e:
+            fs.workspace_bytes(b)
+        assert e.value.status == fs.EINVAL
+
+
+def test_strerror_and_abi_version():
+    fs = _lib()
+    lib = fs.load_library()
+    assert lib.fslbm_strerror(0) == b"ok"
+    assert lib.fslbm_strerror(-4) == b"simulation unstable"
+    cp = fs.make_params(I.Params(8, 8, 8))
+    cp.abi_version = 99
+    n = C.c_size_t()
+    assert lib.fslbm_workspace_bytes(C.byref(cp), C.byref(n)) == fs.EINVAL
+    assert b"abi" in lib.fslbm_last_error(None)
+
+
+def test_create_rejects_bad_arguments_without_gpu():
+    """fslbm_create validates on the host before touching the device."""
+    fs = _lib()
+    lib = fs.load_library()
+    cp = fs.make_params(I.Params(8, 8, 8, tau=0.4))
+    h = C.c_void_p()
+    st = lib.fslbm_create(C.byref(cp), None, None, None, None, None, None, None, None, None, 0,
+                          None, C.byref(h))
+    assert st == fs.EINVAL and not h.value
