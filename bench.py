@@ -1,0 +1,208 @@
+"""Throughput of the free-surface LBM step on one MI355X.
+
+Workload (default): the 3D rectangular dam break, 256 x 128 x 64 cells, D3Q19
+TRT (Lambda = 3/16), FP32 populations (stored shifted by the lattice weights),
+FP64 mass, no-slip walls, liquid column 64 x 96 x 64 at rest in the corner,
+g = 2e-5, nu = 1e-3, run with all four reconstruction variants in turn: one
+bench step advances each of the four variant runs by one time step.
+
+Prints one JSON line: fluid+interface cell updates per second (MLUPS) over the
+timed steps, the roofline of the dominant kernel (the liquid stream-collide
+kernel, HBM bound) from HIP events around its launches, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+KERNEL_SOURCES = ["paper_2207_13962_amd/csrc/fslbm_kernels.h", "paper_2207_13962_amd/csrc/fslbm_device.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_liquid_dam256_traffic.txt")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the liquid kernel from the committed rocprofv3
+    counter summary, or None if it is missing or was taken on other kernel code."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bytes_per_update(q, storage_bytes):
+    """Algorithmic bytes of one liquid cell update: read q populations, write q
+    populations, read the cell's flag byte."""
+    return 2 * q * storage_bytes + 1
+
+
+def cpu_baseline(setup_fn, steps):
+    """FP64 oracle on the host: fluid+interface updates per second over `steps`
+    steps of the same workload (single thread)."""
+    from oracle import Oracle
+    s = setup_fn()
+    p = s.params
+    s.params = p.with_(storage=0)
+    o = Oracle(s)
+    upd = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = o.mass()
+        upd += r.n_liquid + r.n_interface
+        st = o.step(1)
+        if st != 0:
+            break
+    dt = time.perf_counter() - t0
+    return upd / dt / 1e6, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="dam256")
+    ap.add_argument("--variants", default="1,2,3,4")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the free-surface LBM step here runs on a single "
+              "MI355X (no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2207_13962_amd import inputs as I
+    from paper_2207_13962_amd.fslbm import Simulation
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    variants = [int(v) for v in args.variants.split(",")]
+    setup_fn = lambda: I.workload(args.workload)  # noqa: E731
+    base = setup_fn()
+    p = base.params
+    sims = [Simulation(base, variant=v, device="cuda:0") for v in variants]
+    # warmup, in the same interleaving as the timed region
+    for s in sims:
+        s.step(args.warmup)
+    torch.cuda.synchronize()
+    before = [s.mass() for s in sims]
+    for s in sims:
+        s.set_timing(args.steps)
+    chunk = 50
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    done = 0
+    while done < args.steps:
+        n = min(chunk, args.steps - done)
+        for s in sims:
+            s.step(n)
+        done += n
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    after = [s.mass() for s in sims]
+    # fluid+interface updates: average of the counts before and after the window
+    updates = 0.0
+    per_variant = {}
+    for v, b, a in zip(variants, before, after):
+        nb = b["n_liquid"] + b["n_interface"]
+        na = a["n_liquid"] + a["n_interface"]
+        u = 0.5 * (nb + na) * args.steps
+        updates += u
+        per_variant[I.VARIANT_NAMES[v]] = dict(
+            fluid_cells=int(na), interface_cells=int(a["n_interface"]),
+            mass_drift=(a["total_mass"] - before[0]["total_mass"] * 0 - b["total_mass"]) / b["total_mass"])
+    mlups = updates / (ms * 1e-3) / 1e6
+    # dominant kernel: liquid stream-collide
+    launches, kms = 0, 0.0
+    liq_bytes = 0.0
+    sb = {I.F64: 8, I.F32: 4, I.F16S: 2}[p.storage]
+    for s, b, a in zip(sims, before, after):
+        n, t = s.kernel_time()
+        launches += n
+        kms += t
+        nliq = 0.5 * (b["n_liquid"] + a["n_liquid"])
+        liq_bytes += n * (nliq * bytes_per_update(p.q, sb) + (p.n - nliq) * 1.0)
+    avg_ms = kms / max(launches, 1)
+    bytes_per_launch = liq_bytes / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    whole_gbs = updates * bytes_per_update(p.q, sb) / (ms * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu:
+        try:
+            v, dt = cpu_baseline(setup_fn, args.cpu_steps)
+            cpu = {"value": v, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+                   "sample": "first %d steps of the %s workload (%dx%dx%d, FP64 oracle, variant OM),"
+                             " %.1f s" % (args.cpu_steps, args.workload, p.nx, p.ny, p.nz, dt),
+                   "host_cpus": os.cpu_count()}
+        except Exception as e:  # the baseline must never hide the GPU result
+            cpu = {"value": None, "error": repr(e)}
+
+    out = {
+        "metric": "fluid+interface MLUPS (free-surface LBM step)",
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {I.F64: "f64", I.F32: "f32", I.F16S: "f16-shifted/f32"}[p.storage],
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: rectangular dam break %dx%dx%d, D3Q%d %s, variants %s, %d steps per variant run"
+                        % (args.workload, p.nx, p.ny, p.nz, p.q, "TRT" if p.collision else "SRT",
+                           "/".join(I.VARIANT_NAMES[v] for v in variants), args.steps),
+            "cells": p.n,
+            "parallelism": "single GPU",
+            "effective_GBps_whole_step": whole_gbs,
+            "per_variant": per_variant,
+        },
+        "roofline": {
+            "kernel": "k_liquid (pull stream + walls + TRT collision)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "avg_launch_ms": avg_ms,
+            "launches": launches,
+            "bytes_per_launch": bytes_per_launch,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

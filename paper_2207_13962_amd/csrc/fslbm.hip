@@ -91,9 +91,11 @@ void bind(fslbm_ctx* c) {
   d.lost = reinterpret_cast<double*>(a + L.off_lost);
   d.if_list = reinterpret_cast<int32_t*>(a + L.off_if_list);
   d.conv_list = reinterpret_cast<int32_t*>(a + L.off_conv_list);
+  d.chunk_list = reinterpret_cast<int32_t*>(a + L.off_chunk_list);
   d.cnt = reinterpret_cast<int32_t*>(a + L.off_cnt);
   d.scan_if = reinterpret_cast<unsigned long long*>(a + L.off_scan_if);
   d.scan_cv = reinterpret_cast<unsigned long long*>(a + L.off_scan_cv);
+  d.scan_ch = reinterpret_cast<unsigned long long*>(a + L.off_scan_ch);
   d.pV = reinterpret_cast<double*>(a + L.off_pv);
   d.partial = reinterpret_cast<double*>(a + L.off_partial);
 }
@@ -121,7 +123,6 @@ int enqueue_steps(fslbm_ctx* c, int64_t n) {
   const bool st = c->p.sigma != 0.0;
   for (int64_t i = 0; i < n; ++i) {
     c->d.step = c->step;
-    c->d.epoch = ++c->epoch;
     if (st) {
       hipLaunchKernelGGL(k_smooth, dim3((unsigned)(((c->p.nx + 63) / 64) * ((c->p.ny + 3) / 4) *
                                                    c->p.nz)),
@@ -224,9 +225,15 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
     hipError_t e_ = (expr);                                \
     if (e_ != hipSuccess) return fail(hip_fail(c, e_, #expr)); \
   } while (0)
-  INITCHK(hipMemsetAsync(c->d.cnt, 0, 4 * CNT_N, s));
+  {
+    int32_t cnt0[CNT_N] = {0};
+    cnt0[CNT_EPOCH] = 1;  // status arrays start at epoch 0
+    INITCHK(hipMemcpyAsync(c->d.cnt, cnt0, sizeof cnt0, hipMemcpyHostToDevice, s));
+    INITCHK(hipStreamSynchronize(s));
+  }
   INITCHK(hipMemsetAsync(c->d.scan_if, 0, 8 * c->L.tiles, s));
   INITCHK(hipMemsetAsync(c->d.scan_cv, 0, 8 * c->L.tiles, s));
+  INITCHK(hipMemsetAsync(c->d.scan_ch, 0, 8 * c->L.tiles, s));
   INITCHK(hipMemsetAsync(c->d.fB, 0, (size_t)c->p.q * c->L.stride * storage_bytes(c->p.storage), s));
   // types go straight into the flag array, fields into buffers used as staging
   INITCHK(hipMemcpyAsync(c->d.flags, type, N, hipMemcpyHostToDevice, s));
@@ -262,7 +269,6 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   }
   // interface list, flux classes, volume pressure
   c->d.step = 0;
-  c->d.epoch = ++c->epoch;
   ops.convert(c, s, 1);
   ops.finish(c, s, 1);
   const double pv0[3] = {c->p.rho_gas / 3.0, c->p.rho_gas / 3.0, 0.0};

@@ -63,6 +63,8 @@ enum {
   CNT_MARK0 = 2,   // marked cells, slot (step & 1)
   CNT_TICKET = 4,  // block tickets of the compaction scan
   CNT_ERR = 5,     // error bits (see ERR_*)
+  CNT_EPOCH = 6,   // launch epoch of the compaction scan (advanced by every k_liquid)
+  CNT_CHUNKS = 7,  // 64-cell chunks holding at least one liquid cell
   CNT_N = 8
 };
 enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8 };

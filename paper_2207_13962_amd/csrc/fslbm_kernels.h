@@ -48,13 +48,14 @@ struct Dev {
   double* lost;  // per-cell lost excess mass
   int32_t* if_list;
   int32_t* conv_list;
+  int32_t* chunk_list;  // 64-cell chunks with liquid cells, ascending
   int32_t* cnt;
   unsigned long long* scan_if;
   unsigned long long* scan_cv;
+  unsigned long long* scan_ch;
   double* pV;  // device scalars: [0] p^V, [1] p^V(0), [2] V(0)
   double* partial;  // reduction partials
-  int64_t step;
-  uint32_t epoch;
+  int64_t step;  // parity selects the mark-counter slot
 };
 
 // ---------------------------------------------------------------------------
@@ -263,14 +264,22 @@ __device__ __forceinline__ void interface_cell(const Dev& d, int64_t c) {
   for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
 }
 
+// Each wave takes 64-cell chunks from the chunk list (chunks without liquid
+// cells are never visited), one cell per lane.
 template <int S, int Q, bool TRT>
 __global__ __launch_bounds__(kBlock) void k_liquid(Dev d) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // slot of the next step
     d.cnt[CNT_TICKET] = 0;
+    d.cnt[CNT_EPOCH] += 1;  // a new epoch for this step's compaction scan
   }
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (c < d.g.N) liquid_cell<S, Q, TRT>(d, c);
+  const int nch = d.cnt[CNT_CHUNKS];
+  const int lane = threadIdx.x & 63;
+  const int waves = gridDim.x * (kBlock / 64);
+  for (int w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); w < nch; w += waves) {
+    const int64_t c = (int64_t)d.chunk_list[w] * 64 + lane;
+    if (c < d.g.N) liquid_cell<S, Q, TRT>(d, c);
+  }
 }
 
 template <int S, int Q, bool TRT>
@@ -320,6 +329,8 @@ __device__ __forceinline__ unsigned long long pack_status(uint32_t epoch, uint32
 // at once and its inclusive prefix (flag 2) when known; a tile sums the
 // aggregates of its predecessors back to the nearest inclusive prefix, 64 tiles
 // per round. Entries carry the launch epoch, so the array never needs clearing.
+// The status word is the only datum exchanged, so relaxed device-scope atomics
+// suffice (no acquire/release: those would flush the XCD's L2 on every poll).
 // The wait on a predecessor is bounded: on expiry the scan error bit is set and
 // the kernel completes (with a wrong list, reported by the host).
 __device__ uint32_t lookback_wave(unsigned long long* status, int tile, uint32_t agg,
@@ -327,7 +338,7 @@ __device__ uint32_t lookback_wave(unsigned long long* status, int tile, uint32_t
   const int lane = threadIdx.x & 63;
   if (lane == 0)
     __hip_atomic_store(&status[tile], pack_status(epoch, tile == 0 ? 2u : 1u, agg),
-                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint32_t excl = 0;
   int base = tile - 1;
   bool done = (tile == 0);
@@ -338,7 +349,7 @@ __device__ uint32_t lookback_wave(unsigned long long* status, int tile, uint32_t
     uint32_t fl = 3u;  // before the first tile: acts as an inclusive prefix of 0
     if (t >= 0) {
       for (;;) {
-        v = __hip_atomic_load(&status[t], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        v = __hip_atomic_load(&status[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((uint32_t)(v >> 32) == epoch) break;
         if (++spins > (1 << 22)) {
           atomicOr(err, ERR_SCAN);
@@ -361,7 +372,7 @@ __device__ uint32_t lookback_wave(unsigned long long* status, int tile, uint32_t
       base -= 64;
   }
   if (lane == 0 && tile > 0)
-    __hip_atomic_store(&status[tile], pack_status(epoch, 2u, excl + agg), __ATOMIC_RELEASE,
+    __hip_atomic_store(&status[tile], pack_status(epoch, 2u, excl + agg), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   return excl;
 }
@@ -422,10 +433,12 @@ __global__ __launch_bounds__(kBlock) void k_convert(Dev d, int rebuild_only) {
   if (!rebuild_only && d.cnt[CNT_MARK0 + (d.step & 1)] == 0) return;
   __shared__ int s_tile;
   __shared__ uint32_t s_wc[2][kConvPer][kBlock / 64];
-  __shared__ uint32_t s_excl[2];
+  __shared__ uint8_t s_ch[kConvPer][kBlock / 64];
+  __shared__ uint32_t s_excl[3];
   if (threadIdx.x == 0) s_tile = atomicAdd(&d.cnt[CNT_TICKET], 1);
   __syncthreads();
   const int tile = s_tile;
+  const uint32_t epoch = (uint32_t)d.cnt[CNT_EPOCH];
   const int64_t base = (int64_t)tile * kConvTile;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -434,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_convert(Dev d, int rebuild_only) {
 #pragma unroll
   for (int j = 0; j < kConvPer; ++j) {
     const int64_t c = base + j * kBlock + threadIdx.x;
-    bool is_if = false, is_cv = false;
+    bool is_if = false, is_cv = false, is_liq = false;
     if (c < d.g.N) {
       const uint8_t fl = d.flags[c];
       uint8_t nf = fl;
@@ -443,8 +456,10 @@ __global__ __launch_bounds__(kBlock) void k_convert(Dev d, int rebuild_only) {
         if (nf != fl) d.flags[c] = nf;
       }
       is_if = (nf & T_MASK) == T_IF;
+      is_liq = (nf & T_MASK) == T_LIQ;
       is_cv = (nf & F_CONV) != 0;
     }
+    const bool chunk_active = __ballot(is_liq) != 0ull;
     pif |= (uint32_t)is_if << j;
     pcv |= (uint32_t)is_cv << j;
     const unsigned long long bi = __ballot(is_if), bc = __ballot(is_cv);
@@ -453,24 +468,34 @@ __global__ __launch_bounds__(kBlock) void k_convert(Dev d, int rebuild_only) {
     if (lane == 0) {
       s_wc[0][j][wv] = __popcll(bi);
       s_wc[1][j][wv] = __popcll(bc);
+      s_ch[j][wv] = chunk_active;
     }
   }
   __syncthreads();
   // tile aggregates
-  uint32_t agg[2] = {0, 0};
+  uint32_t agg[3] = {0, 0, 0};
 #pragma unroll
   for (int j = 0; j < kConvPer; ++j)
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) {
       agg[0] += s_wc[0][j][w];
       agg[1] += s_wc[1][j][w];
+      agg[2] += s_ch[j][w];
     }
-  if (wv < 2) {
-    const uint32_t e = lookback_wave(wv == 0 ? d.scan_if : d.scan_cv, tile, agg[wv], d.epoch,
-                                     &d.cnt[CNT_ERR]);
+  if (wv < 3) {
+    unsigned long long* st = wv == 0 ? d.scan_if : (wv == 1 ? d.scan_cv : d.scan_ch);
+    const uint32_t e = lookback_wave(st, tile, agg[wv], epoch, &d.cnt[CNT_ERR]);
     if (lane == 0) s_excl[wv] = e;
   }
   __syncthreads();
+  // chunk list: one entry per active (slice, wave) pair, thread 0 writes them
+  if (threadIdx.x == 0) {
+    uint32_t o = s_excl[2];
+    for (int j = 0; j < kConvPer; ++j)
+      for (int w = 0; w < kBlock / 64; ++w)
+        if (s_ch[j][w]) d.chunk_list[o++] = tile * (kConvTile / 64) + j * (kBlock / 64) + w;
+    if (tile == (int)gridDim.x - 1) d.cnt[CNT_CHUNKS] = (int32_t)o;
+  }
   uint32_t off[2] = {s_excl[0], s_excl[1]};
 #pragma unroll
   for (int j = 0; j < kConvPer; ++j) {

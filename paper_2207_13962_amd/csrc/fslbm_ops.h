@@ -24,7 +24,8 @@ inline int storage_bytes(int storage) { return storage == FSLBM_F64 ? 8 : (stora
 struct Layout {
   int64_t N, stride, tiles, red_blocks;
   size_t off_fA, off_fB, off_flags, off_mark, off_cls, off_phiA, off_phiB, off_m, off_rho_if,
-      off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_cnt, off_scan_if, off_scan_cv,
+      off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_cnt, off_scan_if,
+      off_scan_cv, off_scan_ch,
       off_pv, off_partial, off_stage, total;
 };
 
@@ -57,9 +58,11 @@ inline Layout make_layout(const fslbm_params& p) {
   L.off_lost = take(8 * L.N);
   L.off_if_list = take(4 * L.N);
   L.off_conv_list = take(4 * L.N);
+  L.off_chunk_list = take(4 * (L.N / 64 + 1));
   L.off_cnt = take(4 * CNT_N);
   L.off_scan_if = take(8 * L.tiles);
   L.off_scan_cv = take(8 * L.tiles);
+  L.off_scan_ch = take(8 * L.tiles);
   L.off_pv = take(8 * 8);
   L.off_partial = take(8 * kRedN * L.red_blocks + 8 * 16);
   L.off_stage = take(8 * L.N);
@@ -100,7 +103,6 @@ struct fslbm_ctx {
   bool own_arena = false;
   Dev d{};
   int64_t step = 0;
-  uint32_t epoch = 0;
   int status = FSLBM_OK;  // sticky device / runtime failure
   std::string last_error;
   // optional events around the liquid stream-collide launches
@@ -115,6 +117,13 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 // interface blocks of k_step: enough to cover a large interface list with few
 // launches' worth of work per thread
+// persistent-style grid of the liquid kernel: about the waves the GPU holds
+// at this kernel's occupancy, capped by the number of chunks
+inline unsigned liquid_blocks(const fslbm_ctx* c) {
+  const int64_t chunks = c->L.N / 64 + 1;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((chunks + 3) / 4, 256 * 7));
+}
+
 inline unsigned if_blocks(const fslbm_ctx* c) {
   int64_t b = grid_for(c->L.N) / 8 + 64;
   return (unsigned)std::min<int64_t>(b, 4096);
@@ -142,7 +151,7 @@ struct Impl {
   static void step(fslbm_ctx* c, hipStream_t s) {
     const bool timed = 2 * (c->ev_used + 1) <= (int64_t)c->ev.size();
     if (timed) hipEventRecord(c->ev[2 * c->ev_used], s);
-    hipLaunchKernelGGL((k_liquid<S, Q, TRT>), dim3(grid_for(c->L.N)), dim3(kBlock), 0, s, c->d);
+    hipLaunchKernelGGL((k_liquid<S, Q, TRT>), dim3(liquid_blocks(c)), dim3(kBlock), 0, s, c->d);
     if (timed) hipEventRecord(c->ev[2 * c->ev_used++ + 1], s);
     hipLaunchKernelGGL((k_interface<S, Q, TRT>), dim3(if_blocks(c)), dim3(kBlock), 0, s, c->d);
   }

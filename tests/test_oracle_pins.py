@@ -506,3 +506,45 @@ def test_create_rejects_liquid_next_to_gas():
     s = I.Setup(p, t, np.ones(p.n), np.ones(p.n), np.zeros(p.n), np.zeros(p.n), np.zeros(p.n))
     with pytest.raises(ValueError):
         Oracle(s)
+
+
+@pytest.mark.slow
+def test_standing_wave_frequency_and_damping():
+    """Whole step against the analytic standing wave (Sec. 4.1): frequency
+    w0 = sqrt(g k tanh(k d)) and viscous decay exp(-2 nu k^2 t), valid for
+    k a0 << 1 and k a0 << k d. 128 x 128 x 1, depth 64, a0 = 2, tau = 0.51,
+    g = 1e-4, variant OM. The surface elevation is projected on the cosine mode
+    (cell averages of cos(kx)). The period from the first and third zero
+    crossing is within 5 % of 2 pi / w0, and the amplitude at the first trough
+    within 20 % of the decay envelope (the paper's own runs lie within a few
+    per cent of the analytic curve at its finer resolutions; coarser lattices
+    damp more)."""
+    import math
+    L, h, a0, g, tau = 128, 64.0, 2.0, 1e-4, 0.51
+    s = I.gravity_wave(nx=L, ny=L, depth=h, amp=a0, g=g, tau=tau, variant=I.OM)
+    o = Oracle(s)
+    k = 2 * math.pi / L
+    w0 = math.sqrt(g * k * math.tanh(k * h))
+    T = 2 * math.pi / w0
+    nu = (tau - 0.5) / 3.0
+    xs = np.arange(L)
+    basis = (np.sin(k * (xs + 1)) - np.sin(k * xs)) / k
+    series = []
+    nsteps = int(1.35 * T)
+    for n in range(0, nsteps, 10):
+        ph = o.fields()["phi"].reshape(L, L)
+        series.append((n, ((ph.sum(axis=0) - h) * basis).sum() / (basis * basis).sum()))
+        assert o.step(10) == 0
+    series = np.array(series)
+    zc = []
+    for (n0, e0), (n1, e1) in zip(series[:-1], series[1:]):
+        if (e0 > 0) != (e1 > 0):
+            zc.append(n0 + (n1 - n0) * e0 / (e0 - e1))
+    assert len(zc) >= 3
+    period = zc[2] - zc[0]
+    assert abs(period - T) / T < 0.05, (period, T)
+    # first trough: between the first two zero crossings
+    mid = series[(series[:, 0] > zc[0]) & (series[:, 0] < zc[1])]
+    i = np.argmin(mid[:, 1])
+    env = a0 * math.exp(-2 * nu * k * k * mid[i, 0])
+    assert abs(-mid[i, 1] - env) / env < 0.2, (mid[i], env)
