@@ -77,6 +77,8 @@ typedef struct {
   double sigma;          /* surface tension (0 = off): rho^G = 3 (p^V + sigma kappa) */
   double eps_phi;        /* conversion threshold (the paper uses 1e-2) */
   double tie_delta;      /* |n.c_i| <= tie_delta*max|n_a| counts as n.c_i = 0; 0 -> 1e-9 */
+  double smagorinsky;    /* Smagorinsky constant C_S (Sec. 2.1 turbulence model), 0 = off;
+                            the local tau replaces tau (TRT keeps trt_lambda) */
 } fslbm_params;
 
 typedef struct {

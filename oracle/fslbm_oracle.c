@@ -169,14 +169,37 @@ static void moments(int q, const double* f, long stride, const double g[3], doub
   *rho_out = rho;
 }
 
+/* Smagorinsky model (Sec. 2.1, turbulence relaxation time): momentum fluxes
+ * of the non-equilibrium part Q_ab = sum_i c_ia c_ib (f_i - feq_i), filtered
+ * flux Qbar = sqrt(2 sum_ab Q_ab Q_ab), and the total relaxation time
+ * tau = tau0 + tau_t with tau_t = (sqrt(tau0^2 + 2 sqrt(2) C_S^2 Qbar /
+ * (rho c_s^4)) - tau0) / 2 (filter width 1). The printed expression drops the
+ * parentheses around the difference, which would give tau = tau0/2 at
+ * Qbar = 0; the parenthesised form is the one that reduces to tau0. */
+static double les_tau(int q, double tau0, double cs, double rho, const double* f,
+                      const double* feq) {
+  double Qab[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int i = 0; i < q; ++i) Qab[a][b] += CV[i][a] * CV[i][b] * (f[i] - feq[i]);
+  double s2 = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) s2 += Qab[a][b] * Qab[a][b];
+  double Qbar = sqrt(2.0 * s2);
+  double cs4 = 1.0 / 9.0;
+  double tau_t = 0.5 * (sqrt(tau0 * tau0 + 2.0 * sqrt(2.0) * cs * cs * Qbar / (rho * cs4)) - tau0);
+  return tau0 + tau_t;
+}
+
 /* Collision of one cell, Sec. 2.1: f* = f - omega (f - feq) + (1 - omega/2) S
  * with the Guo source S_i = w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)].
  * The relaxation term is subtracted (standard BGK; the printed operator has
  * the opposite sign). TRT (not in the paper): the same step applied to the
  * symmetric (+) and antisymmetric (-) parts with rates omega+ = 1/tau and
- * 1/omega- = 1/2 + lambda/(tau - 1/2); lambda = (tau - 1/2)^2 reduces it to SRT. */
-void orc_collide_cell(int q, int collision, double tau, double lambda, const double g[3],
-                      const double* f, double* fs, double u[3]) {
+ * 1/omega- = 1/2 + lambda/(tau - 1/2); lambda = (tau - 1/2)^2 reduces it to SRT.
+ * With cs > 0, tau is the Smagorinsky total relaxation time of this cell. */
+void orc_collide_cell(int q, int collision, double tau, double lambda, double cs, const double g[3],
+                      const double* f, double* fs, double u[3], double* tau_out) {
   double rho;
   moments(q, f, 1, g, &rho, u);
   double F[3] = {rho * g[0], rho * g[1], rho * g[2]};
@@ -190,6 +213,8 @@ void orc_collide_cell(int q, int collision, double tau, double lambda, const dou
     feq[i] = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
     S[i] = w * (3.0 * cmuF + 9.0 * cu * cF);
   }
+  if (cs > 0.0) tau = les_tau(q, tau, cs, rho, f, feq);
+  if (tau_out) *tau_out = tau;
   double omega = 1.0 / tau;
   if (collision == ORC_SRT) {
     for (int i = 0; i < q; ++i)
@@ -546,7 +571,8 @@ static void collide_all(orc_sim* s, const double* f, double* fs, double* ut) {
       continue;
     }
     for (int i = 0; i < q; ++i) fl[i] = f[i * N + c];
-    orc_collide_cell(q, s->p.collision, s->p.tau, s->p.trt_lambda, s->p.gravity, fl, fo, u);
+    orc_collide_cell(q, s->p.collision, s->p.tau, s->p.trt_lambda, s->p.smagorinsky, s->p.gravity,
+                     fl, fo, u, NULL);
     for (int i = 0; i < q; ++i) fs[i * N + c] = fo[i];
     if (ut) {
       ut[3 * c + 0] = u[0];

@@ -50,6 +50,7 @@ typedef struct {
   double sigma;          /* surface tension, 0 = off */
   double eps_phi;        /* conversion threshold */
   double tie_delta;      /* band for n.c = 0 decisions, relative to max|n_a| */
+  double smagorinsky;    /* Smagorinsky constant C_S of the LES model (0 = off) */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -86,9 +87,11 @@ void orc_equilibrium(int q, double rho, const double u[3], double* feq);
 /* Lattice velocity c_i (3 ints) and weight. */
 void orc_lattice(int q, int i, int c[3], double* w);
 int orc_opposite(int q, int i);
-/* One collision of a single cell: f (q) -> fs (q); returns collision velocity in u. */
-void orc_collide_cell(int q, int collision, double tau, double lambda, const double g[3],
-                      const double* f, double* fs, double u[3]);
+/* One collision of a single cell: f (q) -> fs (q); returns collision velocity in u
+ * and, if tau_out is not NULL, the relaxation time used (tau, or tau0 + tau_t
+ * with the Smagorinsky model when cs > 0). */
+void orc_collide_cell(int q, int collision, double tau, double lambda, double cs, const double g[3],
+                      const double* f, double* fs, double u[3], double* tau_out);
 /* Reconstruction set of one interface cell: given the normal n, the gas-source
  * mask (bit i set when x - c_i is gas) and the variant, writes R[i] = 1 for
  * every direction overwritten by the anti-bounce-back condition (forced gas

@@ -29,7 +29,8 @@ class _Params(C.Structure):
                 ("collision", C.c_int32), ("boundary", C.c_int32 * 6), ("variant", C.c_int32),
                 ("thurey_flux", C.c_int32), ("bubble_model", C.c_int32), ("tau", C.c_double),
                 ("trt_lambda", C.c_double), ("gravity", C.c_double * 3), ("rho_gas", C.c_double),
-                ("sigma", C.c_double), ("eps_phi", C.c_double), ("tie_delta", C.c_double)]
+                ("sigma", C.c_double), ("eps_phi", C.c_double), ("tie_delta", C.c_double),
+                ("smagorinsky", C.c_double)]
 
 
 class _Report(C.Structure):
@@ -77,7 +78,8 @@ def _L():
         lib.orc_lattice.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), dp]
         lib.orc_opposite.argtypes = [C.c_int, C.c_int]
         lib.orc_opposite.restype = C.c_int
-        lib.orc_collide_cell.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
+        lib.orc_collide_cell.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, dp,
+                                         dp, dp, dp, dp]
         lib.orc_reconstruct_set.argtypes = [C.c_int, C.c_int, dp, C.c_uint32, C.c_double, u8]
         lib.orc_bc_value.argtypes = [C.c_int, C.c_int, C.c_double, dp, C.c_double]
         lib.orc_bc_value.restype = C.c_double
@@ -121,11 +123,15 @@ def opposite(q, i):
     return _L().orc_opposite(q, i)
 
 
-def collide_cell(q, collision, tau, lam, g, f):
+def collide_cell(q, collision, tau, lam, g, f, cs=0.0, return_tau=False):
     fs = np.zeros(q)
     u = np.zeros(3)
-    _L().orc_collide_cell(q, collision, tau, lam, _dp(np.ascontiguousarray(g, dtype=np.float64)),
-                          _dp(np.ascontiguousarray(f, dtype=np.float64)), _dp(fs), _dp(u))
+    t = C.c_double()
+    _L().orc_collide_cell(q, collision, tau, lam, cs, _dp(np.ascontiguousarray(g, dtype=np.float64)),
+                          _dp(np.ascontiguousarray(f, dtype=np.float64)), _dp(fs), _dp(u),
+                          C.cast(C.byref(t), C.POINTER(C.c_double)))
+    if return_tau:
+        return fs, u, t.value
     return fs, u
 
 
@@ -161,6 +167,7 @@ class Oracle:
             cp.gravity[k] = p.gravity[k]
         cp.rho_gas, cp.sigma, cp.eps_phi = p.rho_gas, p.sigma, p.eps_phi
         cp.tie_delta = p.tie_delta if p.tie_delta > 0 else 1e-9
+        cp.smagorinsky = p.smagorinsky
         self._keep = [np.ascontiguousarray(a) for a in
                       (setup.type.astype(np.uint8), setup.phi, setup.rho, setup.ux, setup.uy, setup.uz)]
         t, phi, rho, ux, uy, uz = self._keep

@@ -67,6 +67,9 @@ void bind(fslbm_ctx* c) {
   const double tau = c->p.tau;
   d.omega = 1.0 / tau;
   d.omega_m = c->p.collision == FSLBM_TRT ? 1.0 / (0.5 + c->p.trt_lambda / (tau - 0.5)) : d.omega;
+  d.tau0 = tau;
+  d.lambda = c->p.trt_lambda;
+  d.cs = c->p.smagorinsky;
   d.gx = c->p.gravity[0];
   d.gy = c->p.gravity[1];
   d.gz = c->p.gravity[2];
@@ -92,10 +95,14 @@ void bind(fslbm_ctx* c) {
   d.if_list = reinterpret_cast<int32_t*>(a + L.off_if_list);
   d.conv_list = reinterpret_cast<int32_t*>(a + L.off_conv_list);
   d.chunk_list = reinterpret_cast<int32_t*>(a + L.off_chunk_list);
+  d.gen_list = reinterpret_cast<int32_t*>(a + L.off_gen_list);
+  d.tile_dirty = reinterpret_cast<uint8_t*>(a + L.off_tile_dirty);
+  d.cand = reinterpret_cast<uint8_t*>(a + L.off_cand);
   d.cnt = reinterpret_cast<int32_t*>(a + L.off_cnt);
   d.scan_if = reinterpret_cast<unsigned long long*>(a + L.off_scan_if);
   d.scan_cv = reinterpret_cast<unsigned long long*>(a + L.off_scan_cv);
   d.scan_ch = reinterpret_cast<unsigned long long*>(a + L.off_scan_ch);
+  d.scan_gen = reinterpret_cast<unsigned long long*>(a + L.off_scan_gen);
   d.pV = reinterpret_cast<double*>(a + L.off_pv);
   d.partial = reinterpret_cast<double*>(a + L.off_partial);
 }
@@ -234,6 +241,9 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   INITCHK(hipMemsetAsync(c->d.scan_if, 0, 8 * c->L.tiles, s));
   INITCHK(hipMemsetAsync(c->d.scan_cv, 0, 8 * c->L.tiles, s));
   INITCHK(hipMemsetAsync(c->d.scan_ch, 0, 8 * c->L.tiles, s));
+  INITCHK(hipMemsetAsync(c->d.scan_gen, 0, 8 * c->L.tiles, s));
+  INITCHK(hipMemsetAsync(c->d.tile_dirty, 0, c->L.tiles, s));
+  INITCHK(hipMemsetAsync(c->d.cand, 0, c->L.N, s));
   INITCHK(hipMemsetAsync(c->d.fB, 0, (size_t)c->p.q * c->L.stride * storage_bytes(c->p.storage), s));
   // types go straight into the flag array, fields into buffers used as staging
   INITCHK(hipMemcpyAsync(c->d.flags, type, N, hipMemcpyHostToDevice, s));

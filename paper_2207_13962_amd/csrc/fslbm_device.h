@@ -65,7 +65,8 @@ enum {
   CNT_ERR = 5,     // error bits (see ERR_*)
   CNT_EPOCH = 6,   // launch epoch of the compaction scan (advanced by every k_liquid)
   CNT_CHUNKS = 7,  // 64-cell chunks holding at least one liquid cell
-  CNT_N = 8
+  CNT_GEN = 8,     // liquid cells next to the domain boundary or an obstacle
+  CNT_N = 12
 };
 enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8 };
 
@@ -124,12 +125,16 @@ struct Geom {
   int64_t stride;  // distance between population planes (>= N)
 };
 
+// Cell coordinates; domains hold fewer than 2^30 cells, so 32-bit unsigned
+// arithmetic suffices.
 __device__ __forceinline__ void coords(const Geom& g, int64_t c, int& x, int& y, int& z) {
-  int64_t nxy = (int64_t)g.nx * g.ny;
-  z = (int)(c / nxy);
-  int64_t r = c - (int64_t)z * nxy;
-  y = (int)(r / g.nx);
-  x = (int)(r - (int64_t)y * g.nx);
+  const uint32_t cc = (uint32_t)c, nx = (uint32_t)g.nx, nxy = nx * (uint32_t)g.ny;
+  const uint32_t zz = cc / nxy;
+  const uint32_t r = cc - zz * nxy;
+  const uint32_t yy = r / nx;
+  z = (int)zz;
+  y = (int)yy;
+  x = (int)(r - yy * nx);
 }
 
 // Index of (x,y,z)+(dx,dy,dz) after periodic wrap, or -1 beyond a wall face;
@@ -158,7 +163,7 @@ __device__ __forceinline__ int64_t nb_index(const Geom& g, int x, int y, int z, 
   }
   *wall = w;
   if (w) return -1;
-  return c[0] + (int64_t)g.nx * (c[1] + (int64_t)g.ny * c[2]);
+  return (int64_t)(c[0] + g.nx * (c[1] + g.ny * c[2]));
 }
 
 // Type of a neighbour (ghost walls included) and its index (-1 for ghosts).
@@ -234,7 +239,29 @@ template <typename R>
 struct CollideParams {
   R omega, omega_m;  // 1/tau and the TRT antisymmetric rate
   R gx, gy, gz;
+  R tau0, lambda, cs;  // Smagorinsky model (cs > 0): tau0, TRT magic parameter, C_S
 };
+
+// Smagorinsky model (Sec. 2.1): total relaxation time tau0 + tau_t from the
+// non-equilibrium momentum flux, tau_t = (sqrt(tau0^2 + 2 sqrt(2) C_S^2 Qbar /
+// (rho c_s^4)) - tau0) / 2, Qbar = sqrt(2 Q_ab Q_ab) (sum over all a, b).
+template <typename R>
+__device__ __forceinline__ R les_tau(R tau0, R cs, R rho, R qxx, R qyy, R qzz, R qxy, R qxz,
+                                     R qyz) {
+  R s2 = qxx * qxx;
+  s2 += qxy * qxy;
+  s2 += qxz * qxz;
+  s2 += qxy * qxy;
+  s2 += qyy * qyy;
+  s2 += qyz * qyz;
+  s2 += qxz * qxz;
+  s2 += qyz * qyz;
+  s2 += qzz * qzz;
+  const R Qbar = sqrt(R(2) * s2);
+  const R cs4 = R(1.0 / 9.0);
+  const R tt = R(0.5) * (sqrt(tau0 * tau0 + R(2) * sqrt(R(2)) * cs * cs * Qbar / (rho * cs4)) - tau0);
+  return tau0 + tt;
+}
 
 template <typename R, int Q, bool SH>
 __device__ __forceinline__ void moments(const R* f, R gx, R gy, R gz, R& rho, R& dr, R& ux, R& uy,
@@ -323,22 +350,6 @@ __device__ __forceinline__ void collide(R* f, const CollideParams<R>& cp, R& rho
   moments<R, Q, SH>(f, cp.gx, cp.gy, cp.gz, rho, dr, ux, uy, uz);
   const R Fx = rho * cp.gx, Fy = rho * cp.gy, Fz = rho * cp.gz;
   const R usq = ux * ux + uy * uy + uz * uz;
-  const R om = cp.omega;
-  if (!TRT) {
-    const R sf = R(1) - R(0.5) * om;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      const R cu = cdot<R>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
-      const R cF = cdot<R>(kCX[k], kCY[k], kCZ[k], Fx, Fy, Fz);
-      const R cmuF = (R(kCX[k]) - ux) * Fx + (R(kCY[k]) - uy) * Fy + (R(kCZ[k]) - uz) * Fz;
-      const R fe = feq_k<R, Q, SH>(k, rho, dr, cu, usq);
-      const R S = R(weight<Q>(k)) * (R(3) * cmuF + R(9) * cu * cF);
-      f[k] = f[k] - om * (f[k] - fe) + sf * S;
-    }
-    return;
-  }
-  const R omm = cp.omega_m;
-  const R sp = R(1) - R(0.5) * om, sm = R(1) - R(0.5) * omm;
   R fe[Q], S[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
@@ -348,6 +359,34 @@ __device__ __forceinline__ void collide(R* f, const CollideParams<R>& cp, R& rho
     fe[k] = feq_k<R, Q, SH>(k, rho, dr, cu, usq);
     S[k] = R(weight<Q>(k)) * (R(3) * cmuF + R(9) * cu * cF);
   }
+  R om = cp.omega, omm = cp.omega_m;
+  if (cp.cs > R(0)) {
+    // momentum flux of the non-equilibrium part, summed in direction order
+    R qxx = R(0), qyy = R(0), qzz = R(0), qxy = R(0), qxz = R(0), qyz = R(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const R nq = f[k] - fe[k];
+      if (kCX[k] != 0) qxx += nq;
+      if (kCY[k] != 0) qyy += nq;
+      if (kCZ[k] != 0) qzz += nq;
+      if (kCX[k] * kCY[k] > 0) qxy += nq;
+      if (kCX[k] * kCY[k] < 0) qxy += -nq;
+      if (kCX[k] * kCZ[k] > 0) qxz += nq;
+      if (kCX[k] * kCZ[k] < 0) qxz += -nq;
+      if (kCY[k] * kCZ[k] > 0) qyz += nq;
+      if (kCY[k] * kCZ[k] < 0) qyz += -nq;
+    }
+    const R tau = les_tau<R>(cp.tau0, cp.cs, rho, qxx, qyy, qzz, qxy, qxz, qyz);
+    om = R(1) / tau;
+    omm = TRT ? R(1) / (R(0.5) + cp.lambda / (tau - R(0.5))) : om;
+  }
+  if (!TRT) {
+    const R sf = R(1) - R(0.5) * om;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = f[k] - om * (f[k] - fe[k]) + sf * S[k];
+    return;
+  }
+  const R sp = R(1) - R(0.5) * om, sm = R(1) - R(0.5) * omm;
   R out[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {

@@ -2,12 +2,14 @@
 //
 // One time step is four launches (plus two for surface tension, two for the
 // bubble volume):
-//   k_liquid    every liquid cell : pull streaming with walls, collision, store
-//                                   (the bandwidth kernel)
-//   k_interface list-driven       : every interface cell of the compacted list -
+//   k_liquid    chunk-list-driven : every liquid cell away from walls - pull
+//                                   streaming, collision, store (the bandwidth
+//                                   kernel)
+//   k_generic   list-driven       : every interface cell of the compacted list -
 //                                   streaming, free-surface condition with the
 //                                   variant's set, mass exchange, fill level,
-//                                   conversion mark, collision
+//                                   conversion mark, collision - and every liquid
+//                                   cell next to a wall or obstacle
 //   k_convert  every cell         : new type from the marks (to-gas marks next to
 //                                   a to-liquid mark are dropped), in place; the
 //                                   new interface list and the converted list are
@@ -26,11 +28,14 @@
 namespace fslbm {
 
 constexpr int kBlock = 256;
+constexpr int kConvPer = 16;                   // cells per thread in k_convert
+constexpr int kConvTile = kBlock * kConvPer;  // cells per compaction tile
 
 struct Dev {
   Geom g;
   // parameters
   double omega, omega_m, gx, gy, gz;
+  double tau0, lambda, cs;  // Smagorinsky model (cs = 0: off)
   double rho_gas, sigma, eps, delta;
   int variant, thurey, bubble;
   // state
@@ -49,17 +54,21 @@ struct Dev {
   int32_t* if_list;
   int32_t* conv_list;
   int32_t* chunk_list;  // 64-cell chunks with liquid cells, ascending
+  int32_t* gen_list;    // liquid cells with the BORDER flag, ascending
+  uint8_t* tile_dirty;  // per compaction tile: a conversion mark lies in or next to it
+  uint8_t* cand;        // per cell: lies in the 3x3x3 neighbourhood of a marked cell
   int32_t* cnt;
   unsigned long long* scan_if;
   unsigned long long* scan_cv;
   unsigned long long* scan_ch;
+  unsigned long long* scan_gen;
   double* pV;  // device scalars: [0] p^V, [1] p^V(0), [2] V(0)
   double* partial;  // reduction partials
   int64_t step;  // parity selects the mark-counter slot
 };
 
 // ---------------------------------------------------------------------------
-// k_liquid and k_interface
+// k_liquid and k_generic
 // ---------------------------------------------------------------------------
 template <int S, int Q>
 __device__ __forceinline__ void load_plain(const typename Store<S, Q>::T* A, int64_t stride,
@@ -79,38 +88,23 @@ __device__ __forceinline__ bool unstable(R rho, R ux, R uy, R uz) {
          rho > R(1e30);
 }
 
+// Liquid cell whose 3x3x3 neighbourhood is inside the domain and free of
+// obstacles: plain pull from the linear neighbour offsets, collision, store.
+// (A liquid cell never has a gas neighbour, so no free-surface logic applies.)
 template <int S, int Q, bool TRT>
 __device__ __forceinline__ void liquid_cell(const Dev& d, int64_t c) {
   using St = Store<S, Q>;
   using T = typename St::T;
   using R = typename St::R;
   const uint8_t fl = d.flags[c];
-  if ((fl & T_MASK) != T_LIQ) return;
+  if ((fl & (T_MASK | F_BORDER)) != T_LIQ) return;
   const T* A = static_cast<const T*>(d.fA);
   T* B = static_cast<T*>(d.fB);
   const Geom& g = d.g;
   const int64_t stride = g.stride;
   R f[Q];
-  if (!(fl & F_BORDER)) {
-    load_plain<S, Q>(A, stride, c, g.nx, (int64_t)g.nx * g.ny, f);
-  } else {
-    int x, y, z;
-    coords(g, c, x, y, z);
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      int64_t src;
-      int dir;
-      bool wall;
-      int kind = resolve_source<Q>(g, d.flags, x, y, z, k, &src, &dir, &wall);
-      if (kind == SRC_FLUID) {
-        f[k] = St::ld(A, dir * stride + src, dir);
-      } else {
-        if (kind == SRC_GAS) atomicOr(&d.cnt[CNT_ERR], ERR_LAYER);
-        f[k] = St::ld(A, opp(k) * stride + c, opp(k));
-      }
-    }
-  }
-  CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz)};
+  load_plain<S, Q>(A, stride, c, g.nx, (int64_t)g.nx * g.ny, f);
+  CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
   R rho, ux, uy, uz;
   collide<R, Q, TRT, St::kShift>(f, cp, rho, ux, uy, uz);
   if (unstable(rho, ux, uy, uz)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
@@ -158,110 +152,221 @@ __device__ __forceinline__ double flux_term(int cx, int cn, double in, double ou
   return -out;
 }
 
+// ---------------------------------------------------------------------------
+// List-driven kernels work on one cell per group of 32 lanes: lane k handles
+// lattice direction k (lanes >= q idle in the direction work). Sums over
+// directions are butterfly reductions over the group: every lane performs the
+// same additions (a + b and b + a round alike), so all lanes hold the same,
+// deterministic result. The order differs from a sequential loop only by
+// rounding.
+// ---------------------------------------------------------------------------
+constexpr int kG = 32;
+
+// sum over the lanes k < n of the group (callers pass 0 from lanes >= n)
+template <typename T>
+__device__ __forceinline__ T gsum(T v, int) {
+#pragma unroll
+  for (int o = kG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kG);
+  return v;
+}
+
+// ballot restricted to the calling lane's group (bit k = lane k of the group)
+__device__ __forceinline__ uint32_t gballot(bool p) {
+  return (uint32_t)(__ballot(p) >> (threadIdx.x & 32));
+}
+
+// Collision of one cell held one direction per lane (f = population of this
+// lane's direction k); same arithmetic as collide().
+template <typename R, int Q, bool TRT, bool SH>
+__device__ __forceinline__ R gcollide(R f, int k, const CollideParams<R>& cp, R& rho, R& ux, R& uy,
+                                      R& uz) {
+  const bool act = k < Q;
+  const int kk = act ? k : 0;
+  const int cx = kCX[kk], cy = kCY[kk], cz = kCZ[kk];
+  const R fv = act ? f : R(0);
+  const R r = gsum(fv, Q);
+  const R j0 = gsum(cx > 0 ? fv : (cx < 0 ? -fv : R(0)), Q);
+  const R j1 = gsum(cy > 0 ? fv : (cy < 0 ? -fv : R(0)), Q);
+  const R j2 = gsum(cz > 0 ? fv : (cz < 0 ? -fv : R(0)), Q);
+  const R dr = SH ? r : r - R(1);
+  rho = SH ? R(1) + r : r;
+  ux = (j0 + R(0.5) * (rho * cp.gx)) / rho;
+  uy = (j1 + R(0.5) * (rho * cp.gy)) / rho;
+  uz = (j2 + R(0.5) * (rho * cp.gz)) / rho;
+  const R Fx = rho * cp.gx, Fy = rho * cp.gy, Fz = rho * cp.gz;
+  const R usq = ux * ux + uy * uy + uz * uz;
+  const R cu = cdot<R>(cx, cy, cz, ux, uy, uz);
+  const R cF = cdot<R>(cx, cy, cz, Fx, Fy, Fz);
+  const R cmuF = (R(cx) - ux) * Fx + (R(cy) - uy) * Fy + (R(cz) - uz) * Fz;
+  const R w = R(weight<Q>(kk));
+  const R fe = SH ? w * (dr + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq))
+                  : w * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
+  const R S = w * (R(3) * cmuF + R(9) * cu * cF);
+  R om = cp.omega, omm = cp.omega_m;
+  if (cp.cs > R(0)) {
+    const R nq = act ? fv - fe : R(0);
+    const R qxx = gsum(cx != 0 ? nq : R(0), Q), qyy = gsum(cy != 0 ? nq : R(0), Q);
+    const R qzz = gsum(cz != 0 ? nq : R(0), Q);
+    const R qxy = gsum(R(cx * cy) * nq, Q), qxz = gsum(R(cx * cz) * nq, Q);
+    const R qyz = gsum(R(cy * cz) * nq, Q);
+    const R tau = les_tau<R>(cp.tau0, cp.cs, rho, qxx, qyy, qzz, qxy, qxz, qyz);
+    om = R(1) / tau;
+    omm = TRT ? R(1) / (R(0.5) + cp.lambda / (tau - R(0.5))) : om;
+  }
+  if (!TRT) return fv - om * (fv - fe) + (R(1) - R(0.5) * om) * S;
+  const int kb = opp(kk);
+  const R fb = __shfl(fv, kb, kG), eb = __shfl(fe, kb, kG), Sb = __shfl(S, kb, kG);
+  const R fp = R(0.5) * (fv + fb), fm = R(0.5) * (fv - fb);
+  const R ep = R(0.5) * (fe + eb), em = R(0.5) * (fe - eb);
+  const R p = R(0.5) * (S + Sb), m = R(0.5) * (S - Sb);
+  return fv - om * (fp - ep) - omm * (fm - em) + (R(1) - R(0.5) * om) * p +
+         (R(1) - R(0.5) * omm) * m;
+}
+
+// Interface cells (free-surface condition, mass exchange, fill level, mark)
+// and liquid cells next to walls or obstacles (streaming with walls only).
 template <int S, int Q, bool TRT>
-__device__ __forceinline__ void interface_cell(const Dev& d, int64_t c) {
+__global__ __launch_bounds__(kBlock) void k_generic(Dev d) {
   using St = Store<S, Q>;
   using T = typename St::T;
   using R = typename St::R;
+  constexpr bool SH = St::kShift;
   const T* A = static_cast<const T*>(d.fA);
   T* B = static_cast<T*>(d.fB);
   const Geom& g = d.g;
   const int64_t stride = g.stride;
-  int x, y, z;
-  coords(g, c, x, y, z);
-
-  // own post-collision populations and the velocity of the collision at t
-  R fo[Q];
-#pragma unroll
-  for (int k = 0; k < Q; ++k) fo[k] = St::ld(A, k * stride + c, k);
-  R rho_t, ux, uy, uz;
-  constexpr bool SH = St::kShift;
-  post_moments<R, Q, SH>(fo, R(d.gx), R(d.gy), R(d.gz), rho_t, ux, uy, uz);
-  const R usq = ux * ux + uy * uy + uz * uz;
-
-  // missing populations: direct gas sources
-  uint32_t gas = 0;
-#pragma unroll
-  for (int k = 1; k < Q; ++k) {
-    int64_t j;
-    if (nb_type(g, d.flags, x, y, z, -kCX[k], -kCY[k], -kCZ[k], &j) == T_GAS) gas |= 1u << k;
-  }
-  const int missing = __builtin_popcount(gas);
-
-  // the variant's reconstruction set (Sec. 3)
-  uint32_t R_set = gas;
-  const int v = d.variant;
-  const bool nb_based = (v == 1 || v == 2 || (v == 4 && missing < 3));
-  const double phi_c = d.phiA[c];
-  if (nb_based) {
-    double n[3];
-    py_normal(g, d.flags, d.phiA, x, y, z, phi_c, n);
-    double nmax = fabs(n[0]);
-    nmax = fabs(n[1]) > nmax ? fabs(n[1]) : nmax;
-    nmax = fabs(n[2]) > nmax ? fabs(n[2]) : nmax;
-    const double thr = -d.delta * nmax;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      if (k == 0 && v != 1) continue;
-      const double dot = n[0] * kCX[k] + n[1] * kCY[k] + n[2] * kCZ[k];
-      if (dot >= thr) R_set |= 1u << k;
-    }
-  }
-
-  const R rhoG = d.rhoG ? R(d.rhoG[c]) : R(d.pV[0] * 3.0);
-  const int cls_c = d.cls[c];
-
-  // streaming, boundary condition and mass exchange (Sec. 2.2)
-  R f[Q];
-  double dm = 0.0;
-#pragma unroll
-  for (int k = 0; k < Q; ++k) {
+  const int nif = d.cnt[CNT_IF];
+  const int total = nif + d.cnt[CNT_GEN];
+  const int l = threadIdx.x & (kG - 1);
+  const bool act = l < Q;
+  const int k = act ? l : 0;
+  const int kb = opp(k);
+  const int cx = kCX[k], cy = kCY[k], cz = kCZ[k];
+  const int ngroups = gridDim.x * (kBlock / kG);
+  CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
+  for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < total; item += ngroups) {
+    const bool is_if = item < nif;
+    const int64_t c = is_if ? d.if_list[item] : d.gen_list[item - nif];
+    int x, y, z;
+    coords(g, c, x, y, z);
+    // own post-collision population of this direction and of its opposite
+    const R fo = act ? St::ld(A, k * stride + c, k) : R(0);
+    const R fo_b = __shfl(fo, kb, kG);
     int64_t src;
     int dir;
     bool wall;
     const int kind = resolve_source<Q>(g, d.flags, x, y, z, k, &src, &dir, &wall);
     R in_val = R(0);
-    if (kind == SRC_FLUID) in_val = St::ld(A, dir * stride + src, dir);
-    if (kind == SRC_BOUNCE) {
-      f[k] = fo[opp(k)];
-    } else if (kind == SRC_GAS || (((R_set >> k) & 1u) && !wall)) {
-      f[k] = abb_value<R, Q, SH>(k, rhoG, ux, uy, uz, usq, fo[opp(k)]);
+    if (act && kind == SRC_FLUID) in_val = St::ld(A, dir * stride + src, dir);
+    R f;
+    if (!is_if) {
+      if (act && kind == SRC_GAS) atomicOr(&d.cnt[CNT_ERR], ERR_LAYER);
+      f = (kind == SRC_FLUID) ? in_val : fo_b;
     } else {
-      f[k] = in_val;
-    }
-    if (k > 0 && kind == SRC_FLUID) {
-      const double in = (double)in_val, out = (double)fo[opp(k)];
-      const uint8_t ts = d.flags[src] & T_MASK;
-      if (ts == T_LIQ) {
-        dm += in - out;
-      } else {
-        const double T_ = d.thurey ? flux_term(cls_c, d.cls[src], in, out) : in - out;
-        dm += 0.5 * (phi_c + d.phiA[src]) * T_;
+      // velocity of the collision at t, from the post-collision populations
+      // (fo is zero on lanes >= q)
+      const R r0 = gsum(fo, Q);
+      const R a0 = gsum(cx > 0 ? fo : (cx < 0 ? -fo : R(0)), Q);
+      const R a1 = gsum(cy > 0 ? fo : (cy < 0 ? -fo : R(0)), Q);
+      const R a2 = gsum(cz > 0 ? fo : (cz < 0 ? -fo : R(0)), Q);
+      const R rho_t = SH ? R(1) + r0 : r0;
+      const R ux = (a0 - R(0.5) * (rho_t * R(d.gx))) / rho_t;
+      const R uy = (a1 - R(0.5) * (rho_t * R(d.gy))) / rho_t;
+      const R uz = (a2 - R(0.5) * (rho_t * R(d.gz))) / rho_t;
+      const R usq = ux * ux + uy * uy + uz * uz;
+      // missing populations (direct gas sources) and the variant's set (Sec. 3)
+      const uint32_t gas = gballot(act && l > 0 && kind == SRC_GAS && !wall);
+      const int missing = __popc(gas);
+      const int v = d.variant;
+      const bool nb_based = (v == 1 || v == 2 || (v == 4 && missing < 3));
+      bool in_R = ((gas >> k) & 1u) != 0;
+      const double phi_c = d.phiA[c];
+      if (nb_based) {
+        // Parker-Youngs normal (Sec. 2.2): lane l holds phi at offset
+        // (l%3-1, (l/3)%3-1, l/9-1); obstacle points take the centre value
+        double vphi = phi_c;
+        if (l < 27) {
+          int64_t j;
+          const int t = nb_type(g, d.flags, x, y, z, l % 3 - 1, (l / 3) % 3 - 1, l / 9 - 1, &j);
+          vphi = is_obst(t) ? phi_c : d.phiA[j];
+        }
+        // lane stride of each axis in the 3x3x3 numbering
+        double n[3];
+#pragma unroll 1
+        for (int a = 0; a < 3; ++a) {
+          const int sa = a == 0 ? 1 : (a == 1 ? 3 : 9);
+          const int s1 = a == 0 ? 3 : (a == 1 ? 9 : 1);
+          const int s2 = a == 0 ? 9 : (a == 1 ? 1 : 3);
+          double sacc = 0.0;
+#pragma unroll 1
+          for (int b = -1; b <= 1; ++b) {
+            const double wb = b == 0 ? 2.0 : 1.0;
+#pragma unroll
+            for (int cc = -1; cc <= 1; ++cc) {
+              const int lc = 13 + b * s1 + cc * s2;
+              const double vp = __shfl(vphi, lc + sa, kG), vm = __shfl(vphi, lc - sa, kG);
+              sacc += wb * (cc == 0 ? 2.0 : 1.0) * (vp - vm);
+            }
+          }
+          n[a] = sacc;
+        }
+        double nmax = fabs(n[0]);
+        nmax = fabs(n[1]) > nmax ? fabs(n[1]) : nmax;
+        nmax = fabs(n[2]) > nmax ? fabs(n[2]) : nmax;
+        const double dot = n[0] * cx + n[1] * cy + n[2] * cz;
+        if ((k > 0 || v == 1) && dot >= -d.delta * nmax) in_R = true;
+      }
+      const R rhoG = d.rhoG ? R(d.rhoG[c]) : R(d.pV[0] * 3.0);
+      if (kind == SRC_BOUNCE)
+        f = fo_b;
+      else if (kind == SRC_GAS || (in_R && !wall))
+        f = abb_value<R, Q, SH>(k, rhoG, ux, uy, uz, usq, fo_b);
+      else
+        f = in_val;
+      // mass exchange (Sec. 2.2) along the actual streaming path of direction k
+      double term = 0.0;
+      if (act && l > 0 && kind == SRC_FLUID) {
+        const double in = (double)in_val, out = (double)fo_b;
+        if ((d.flags[src] & T_MASK) == T_LIQ) {
+          term = in - out;
+        } else {
+          const double T_ = d.thurey ? flux_term(d.cls[c], d.cls[src], in, out) : in - out;
+          term = 0.5 * (phi_c + d.phiA[src]) * T_;
+        }
+      }
+      const double dm = gsum(term, Q);
+      const double rho_n = (SH ? 1.0 : 0.0) + gsum(act ? (double)f : 0.0, Q);
+      const double m_new = d.m[c] + dm;
+      const double phi_n = m_new / rho_n;
+      uint8_t mk = MK_NONE;
+      if (phi_n > 1.0 + d.eps)
+        mk = MK_L;
+      else if (phi_n < -d.eps)
+        mk = MK_G;
+      if (l == 0) {
+        d.m[c] = m_new;
+        d.rho_if[c] = rho_n;
+        d.phiB[c] = phi_n;
+        d.mark[c] = mk;
+        if (mk) atomicAdd(&d.cnt[CNT_MARK0 + (d.step & 1)], 1);
+        if (!(m_new == m_new)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
+      }
+      if (mk && l < 27) {
+        // the conversion pass re-types the 3x3x3 neighbourhood of a marked
+        // cell (every writer stores the same value)
+        int w;
+        const int64_t j = nb_index(g, x, y, z, l % 3 - 1, (l / 3) % 3 - 1, l / 9 - 1, &w);
+        if (j >= 0) {
+          d.cand[j] = 1;
+          d.tile_dirty[j / kConvTile] = 1;
+        }
       }
     }
+    R rho, vx, vy, vz;
+    const R fs = gcollide<R, Q, TRT, SH>(f, l, cp, rho, vx, vy, vz);
+    if (l == 0 && unstable(rho, vx, vy, vz)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
+    if (act) St::st(B, k * stride + c, k, fs);
   }
-
-  // fill level and conversion mark
-  const double rho_n = density64<R, Q, SH>(f);
-  const double m_new = d.m[c] + dm;
-  const double phi_n = m_new / rho_n;
-  uint8_t mk = MK_NONE;
-  if (phi_n > 1.0 + d.eps)
-    mk = MK_L;
-  else if (phi_n < -d.eps)
-    mk = MK_G;
-  d.m[c] = m_new;
-  d.rho_if[c] = rho_n;
-  d.phiB[c] = phi_n;
-  d.mark[c] = mk;
-  if (mk) atomicAdd(&d.cnt[CNT_MARK0 + (d.step & 1)], 1);
-
-  CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz)};
-  R rho, vx, vy, vz;
-  collide<R, Q, TRT, SH>(f, cp, rho, vx, vy, vz);
-  if (unstable(rho, vx, vy, vz) || !(m_new == m_new)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
-#pragma unroll
-  for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
 }
 
 // Each wave takes 64-cell chunks from the chunk list (chunks without liquid
@@ -282,43 +387,9 @@ __global__ __launch_bounds__(kBlock) void k_liquid(Dev d) {
   }
 }
 
-template <int S, int Q, bool TRT>
-__global__ __launch_bounds__(kBlock) void k_interface(Dev d) {
-  const int nif = d.cnt[CNT_IF];
-  for (int k = blockIdx.x * kBlock + threadIdx.x; k < nif; k += gridDim.x * kBlock)
-    interface_cell<S, Q, TRT>(d, d.if_list[k]);
-}
-
 // ---------------------------------------------------------------------------
 // k_convert: new types from marks, in place, plus compaction.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool any_nb_mark(const Dev& d, int x, int y, int z, int64_t c,
-                                            bool border, int Q, uint8_t want) {
-  const Geom& g = d.g;
-  const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
-  for (int k = 1; k < Q; ++k) {
-    int64_t j;
-    if (!border) {
-      j = c + kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
-    } else {
-      int w;
-      j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
-      if (j < 0) continue;
-    }
-    if (d.mark[j] == want) return true;
-  }
-  return false;
-}
-
-// A to-gas mark survives unless a to-liquid mark is in its neighbourhood
-// (Sec. 2.2: separation of liquid and gas has priority).
-__device__ __forceinline__ bool gas_mark_kept(const Dev& d, int64_t j, int Q) {
-  if (d.mark[j] != MK_G) return false;
-  int x, y, z;
-  coords(d.g, j, x, y, z);
-  return !any_nb_mark(d, x, y, z, j, (d.flags[j] & F_BORDER) != 0, Q, MK_L);
-}
-
 __device__ __forceinline__ unsigned long long pack_status(uint32_t epoch, uint32_t flag,
                                                           uint32_t val) {
   return ((unsigned long long)epoch << 32) | ((unsigned long long)flag << 30) | val;
@@ -377,6 +448,31 @@ __device__ uint32_t lookback_wave(unsigned long long* status, int tile, uint32_t
   return excl;
 }
 
+// Marks of the q-1 stencil neighbours of c, gathered with independent loads;
+// returns a bit set: bit 0 some neighbour is marked to-liquid, bit 1 some
+// neighbour is marked to-gas. (Only interface cells carry marks.)
+template <int Q>
+__device__ __forceinline__ int nb_marks(const Dev& d, int64_t c, bool border) {
+  const Geom& g = d.g;
+  int x = 0, y = 0, z = 0;
+  if (border) coords(g, c, x, y, z);
+  const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
+  int acc = 0;
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
+    int64_t j;
+    if (!border) {
+      j = c + kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
+    } else {
+      int w;
+      j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
+    }
+    const uint8_t m = j >= 0 ? d.mark[j] : (uint8_t)MK_NONE;
+    acc |= m;  // MK_L = 1, MK_G = 2
+  }
+  return acc;
+}
+
 // New cell type of cell c from its flags and the marks around it.
 template <int Q>
 __device__ __forceinline__ uint8_t new_flags(const Dev& d, int64_t c, uint8_t fl) {
@@ -385,139 +481,179 @@ __device__ __forceinline__ uint8_t new_flags(const Dev& d, int64_t c, uint8_t fl
   int nt = t;
   uint8_t bits = 0;
   const bool border = (fl & F_BORDER) != 0;
-  int x = 0, y = 0, z = 0;
-  if (border) coords(g, c, x, y, z);
-  if (t == T_IF) {
-    const uint8_t mk = d.mark[c];
-    if (mk == MK_L) {
-      nt = T_LIQ;
-      bits = F_CONV;
-    } else if (mk == MK_G && !any_nb_mark(d, x, y, z, c, border, Q, MK_L)) {
-      nt = T_GAS;
-      bits = F_CONV;
-    }
-  } else if (t == T_GAS) {
-    if (any_nb_mark(d, x, y, z, c, border, Q, MK_L)) {
-      nt = T_IF;
-      bits = F_NEW_GAS;
-    }
-  } else if (t == T_LIQ) {
-    const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
-    for (int k = 1; k < Q; ++k) {
-      int64_t j;
-      if (!border) {
-        j = c + kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
-      } else {
-        int w;
-        j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
-        if (j < 0) continue;
+  const uint8_t mk = (t == T_IF) ? d.mark[c] : (uint8_t)MK_NONE;
+  if (t == T_GAS || t == T_LIQ || (t == T_IF && mk != MK_NONE)) {
+    const int around = nb_marks<Q>(d, c, border);
+    if (t == T_IF) {
+      // a to-gas mark next to a to-liquid mark is dropped (Sec. 2.2:
+      // separation of liquid and gas has priority)
+      if (mk == MK_L) {
+        nt = T_LIQ;
+        bits = F_CONV;
+      } else if (!(around & MK_L)) {
+        nt = T_GAS;
+        bits = F_CONV;
       }
-      if (gas_mark_kept(d, j, Q)) {
+    } else if (t == T_GAS) {
+      if (around & MK_L) {
         nt = T_IF;
-        bits = F_NEW_LIQ;
-        break;
+        bits = F_NEW_GAS;
+      }
+    } else if (around & MK_G) {
+      // liquid next to a to-gas mark: becomes interface if that mark survives
+      int x = 0, y = 0, z = 0;
+      if (border) coords(g, c, x, y, z);
+      const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
+#pragma unroll 1
+      for (int k = 1; k < Q; ++k) {
+        int64_t j;
+        if (!border) {
+          j = c + kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
+        } else {
+          int w;
+          j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
+          if (j < 0) continue;
+        }
+        if (d.mark[j] == MK_G && !(nb_marks<Q>(d, j, (d.flags[j] & F_BORDER) != 0) & MK_L)) {
+          nt = T_IF;
+          bits = F_NEW_LIQ;
+          break;
+        }
       }
     }
   }
   return (uint8_t)((fl & F_BORDER) | nt | bits);
 }
 
-constexpr int kConvPer = 16;                   // cells per thread in k_convert
-constexpr int kConvTile = kBlock * kConvPer;  // cells per tile
 
-// One tile = kConvTile consecutive cells, slice j = cells [j*256, (j+1)*256) of
-// the tile. List order inside a tile is slice-major, thread-minor, i.e.
-// ascending cell index.
+// Block-wide exclusive scan of a per-thread count (wave prefix by shuffles,
+// wave totals through LDS). Returns the prefix; *total receives the block sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    if (w < wv) before += sh[w];
+    tot += sh[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return before + inc - v;
+}
+
+// Conversion pass. A tile is kConvTile = 4096 consecutive cells; thread t owns
+// the 16 cells [16t, 16t+16) of the tile, read as one 16-byte vector. Only
+// cells flagged as candidates (the 3x3x3 neighbourhood of a marked cell) are
+// re-typed; every cell's transient bits of an earlier conversion are cleared.
+// The interface list, the converted list, the chunk list and the list of
+// liquid cells next to walls are then compacted in ascending cell order: block
+// scan of the per-thread counts, decoupled look-back over the tiles (one wave
+// per list), each thread writing its own entries.
 template <int Q>
 __global__ __launch_bounds__(kBlock) void k_convert(Dev d, int rebuild_only) {
   if (!rebuild_only && d.cnt[CNT_MARK0 + (d.step & 1)] == 0) return;
   __shared__ int s_tile;
-  __shared__ uint32_t s_wc[2][kConvPer][kBlock / 64];
-  __shared__ uint8_t s_ch[kConvPer][kBlock / 64];
-  __shared__ uint32_t s_excl[3];
+  __shared__ uint32_t s_scan[4][kBlock / 64];
+  __shared__ uint32_t s_excl[4];
   if (threadIdx.x == 0) s_tile = atomicAdd(&d.cnt[CNT_TICKET], 1);
   __syncthreads();
   const int tile = s_tile;
   const uint32_t epoch = (uint32_t)d.cnt[CNT_EPOCH];
-  const int64_t base = (int64_t)tile * kConvTile;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t pif = 0, pcv = 0;
-  uint32_t rif[kConvPer], rcv[kConvPer];
-#pragma unroll
-  for (int j = 0; j < kConvPer; ++j) {
-    const int64_t c = base + j * kBlock + threadIdx.x;
-    bool is_if = false, is_cv = false, is_liq = false;
-    if (c < d.g.N) {
-      const uint8_t fl = d.flags[c];
-      uint8_t nf = fl;
-      if (!rebuild_only) {
-        nf = new_flags<Q>(d, c, fl);
-        if (nf != fl) d.flags[c] = nf;
-      }
-      is_if = (nf & T_MASK) == T_IF;
-      is_liq = (nf & T_MASK) == T_LIQ;
-      is_cv = (nf & F_CONV) != 0;
-    }
-    const bool chunk_active = __ballot(is_liq) != 0ull;
-    pif |= (uint32_t)is_if << j;
-    pcv |= (uint32_t)is_cv << j;
-    const unsigned long long bi = __ballot(is_if), bc = __ballot(is_cv);
-    rif[j] = __popcll(bi & below);
-    rcv[j] = __popcll(bc & below);
-    if (lane == 0) {
-      s_wc[0][j][wv] = __popcll(bi);
-      s_wc[1][j][wv] = __popcll(bc);
-      s_ch[j][wv] = chunk_active;
+  const int64_t base = (int64_t)tile * kConvTile + 16 * threadIdx.x;
+  const bool update = !rebuild_only && d.tile_dirty[tile];
+  const int64_t N = d.g.N;
+  // the 16 flag bytes (and candidate bytes) of this thread
+  union V16 {
+    uint4 v;
+    uint8_t b[16];
+  } fl, cand;
+  const bool full = base + 16 <= N;
+  fl.v = make_uint4(0, 0, 0, 0);
+  cand.v = make_uint4(0, 0, 0, 0);
+  if (full) {
+    fl.v = *reinterpret_cast<const uint4*>(d.flags + base);
+    if (update) cand.v = *reinterpret_cast<const uint4*>(d.cand + base);
+  } else {
+    for (int j = 0; j < 16 && base + j < N; ++j) {
+      fl.b[j] = d.flags[base + j];
+      if (update) cand.b[j] = d.cand[base + j];
     }
   }
-  __syncthreads();
-  // tile aggregates
-  uint32_t agg[3] = {0, 0, 0};
+  uint32_t mif = 0, mcv = 0, mgn = 0;
+  bool changed = false, any_cand = false;
 #pragma unroll
-  for (int j = 0; j < kConvPer; ++j)
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-      agg[0] += s_wc[0][j][w];
-      agg[1] += s_wc[1][j][w];
-      agg[2] += s_ch[j][w];
+  for (int j = 0; j < 16; ++j) {
+    if (base + j >= N) break;
+    const uint8_t f0 = fl.b[j];
+    uint8_t nf = f0 & (uint8_t)~F_TRANSIENT;
+    if (cand.b[j]) {
+      any_cand = true;
+      nf = new_flags<Q>(d, base + j, f0);
     }
-  if (wv < 3) {
-    unsigned long long* st = wv == 0 ? d.scan_if : (wv == 1 ? d.scan_cv : d.scan_ch);
-    const uint32_t e = lookback_wave(st, tile, agg[wv], epoch, &d.cnt[CNT_ERR]);
+    changed |= (nf != f0);
+    fl.b[j] = nf;
+    const int t = nf & T_MASK;
+    mif |= (uint32_t)(t == T_IF) << j;
+    mcv |= (uint32_t)((nf & F_CONV) != 0) << j;
+    mgn |= (uint32_t)((nf & (T_MASK | F_BORDER)) == (T_LIQ | F_BORDER)) << j;
+    // chunk activity uses liquid cells away from walls
+    if ((nf & (T_MASK | F_BORDER)) == T_LIQ) mgn |= 1u << (16 + j);
+  }
+  if (changed) {
+    if (full) {
+      *reinterpret_cast<uint4*>(d.flags + base) = fl.v;
+    } else {
+      for (int j = 0; j < 16 && base + j < N; ++j) d.flags[base + j] = fl.b[j];
+    }
+  }
+  if (any_cand) {
+    if (full) {
+      *reinterpret_cast<uint4*>(d.cand + base) = make_uint4(0, 0, 0, 0);
+    } else {
+      for (int j = 0; j < 16 && base + j < N; ++j) d.cand[base + j] = 0;
+    }
+  }
+  // a 64-cell chunk is four consecutive threads
+  bool liq = (mgn >> 16) != 0u;
+  liq |= __shfl_xor(liq, 1, 64);
+  liq |= __shfl_xor(liq, 2, 64);
+  const uint32_t cch = ((threadIdx.x & 3) == 0 && liq) ? 1u : 0u;
+  const uint32_t cnts[4] = {(uint32_t)__popc(mif), (uint32_t)__popc(mcv), cch,
+                            (uint32_t)__popc(mgn & 0xffffu)};
+  uint32_t pre[4], tot[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) pre[i] = block_excl_scan(cnts[i], s_scan[i], &tot[i]);
+  if (threadIdx.x == 0 && update) d.tile_dirty[tile] = 0;
+  {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned long long* st =
+        wv == 0 ? d.scan_if : (wv == 1 ? d.scan_cv : (wv == 2 ? d.scan_ch : d.scan_gen));
+    const uint32_t e = lookback_wave(st, tile, tot[wv], epoch, &d.cnt[CNT_ERR]);
     if (lane == 0) s_excl[wv] = e;
   }
   __syncthreads();
-  // chunk list: one entry per active (slice, wave) pair, thread 0 writes them
-  if (threadIdx.x == 0) {
-    uint32_t o = s_excl[2];
-    for (int j = 0; j < kConvPer; ++j)
-      for (int w = 0; w < kBlock / 64; ++w)
-        if (s_ch[j][w]) d.chunk_list[o++] = tile * (kConvTile / 64) + j * (kBlock / 64) + w;
-    if (tile == (int)gridDim.x - 1) d.cnt[CNT_CHUNKS] = (int32_t)o;
-  }
-  uint32_t off[2] = {s_excl[0], s_excl[1]};
+  uint32_t o0 = s_excl[0] + pre[0], o1 = s_excl[1] + pre[1], o3 = s_excl[3] + pre[3];
 #pragma unroll
-  for (int j = 0; j < kConvPer; ++j) {
-    uint32_t wo0 = 0, wo1 = 0, t0 = 0, t1 = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-      if (w < wv) {
-        wo0 += s_wc[0][j][w];
-        wo1 += s_wc[1][j][w];
-      }
-      t0 += s_wc[0][j][w];
-      t1 += s_wc[1][j][w];
-    }
-    const int64_t c = base + j * kBlock + threadIdx.x;
-    if ((pif >> j) & 1u) d.if_list[off[0] + wo0 + rif[j]] = (int32_t)c;
-    if ((pcv >> j) & 1u) d.conv_list[off[1] + wo1 + rcv[j]] = (int32_t)c;
-    off[0] += t0;
-    off[1] += t1;
+  for (int j = 0; j < 16; ++j) {
+    const int32_t c = (int32_t)(base + j);
+    if ((mif >> j) & 1u) d.if_list[o0++] = c;
+    if ((mcv >> j) & 1u) d.conv_list[o1++] = c;
+    if ((mgn >> j) & 1u) d.gen_list[o3++] = c;
   }
-  if (tile == (int)gridDim.x - 1 && threadIdx.x == 0) {
-    d.cnt[CNT_IF] = (int32_t)off[0];
-    d.cnt[CNT_CONV] = (int32_t)off[1];
+  if (cch) d.chunk_list[s_excl[2] + pre[2]] = tile * (kConvTile / 64) + (int)(threadIdx.x >> 2);
+  if (tile == (int)gridDim.x - 1 && threadIdx.x == kBlock - 1) {
+    d.cnt[CNT_IF] = (int32_t)o0;
+    d.cnt[CNT_CONV] = (int32_t)o1;
+    d.cnt[CNT_GEN] = (int32_t)o3;
+    d.cnt[CNT_CHUNKS] = (int32_t)(s_excl[2] + pre[2] + cch);
   }
 }
 
@@ -529,6 +665,7 @@ __device__ __forceinline__ int count_if_nb(const Dev& d, int64_t z) {
   int x, y, zz;
   coords(d.g, z, x, y, zz);
   int n = 0;
+#pragma unroll 1
   for (int k = 1; k < Q; ++k) {
     int w;
     int64_t j = nb_index(d.g, x, y, zz, kCX[k], kCY[k], kCZ[k], &w);
@@ -543,8 +680,11 @@ __device__ __forceinline__ double excess_of(const Dev& d, int64_t z) {
   return t == T_LIQ ? d.m[z] - d.rho_if[z] : d.m[z];
 }
 
+// Completion of one interface cell of the new list by a group of 32 lanes,
+// lane k looking at the neighbour x + c_k.
 template <int S, int Q, bool TRT>
-__device__ void finish_interface(const Dev& d, int64_t c) {
+__device__ __forceinline__ void finish_interface(const Dev& d, int64_t c, int l,
+                                                 bool classes_only) {
   using St = Store<S, Q>;
   using T = typename St::T;
   using R = typename St::R;
@@ -552,85 +692,94 @@ __device__ void finish_interface(const Dev& d, int64_t c) {
   T* B = static_cast<T*>(d.fB);
   const Geom& g = d.g;
   const int64_t stride = g.stride;
-  const uint8_t fl = d.flags[c];
+  const bool act = l < Q;
+  const int k = act ? l : 0;
   int x, y, z;
   coords(g, c, x, y, z);
+  int w;
+  int64_t j = -1;
+  uint8_t fj = 0;
+  if (act && l > 0) {
+    j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
+    if (j >= 0) fj = d.flags[j];
+  }
+  const int tj = j >= 0 ? (fj & T_MASK) : -1;
+  const bool has_liq = gballot(tj == T_LIQ) != 0u;
+  const bool has_gas = gballot(tj == T_GAS) != 0u;
+  const uint8_t cls = (!has_liq && has_gas) ? CLS_NOLIQ : ((!has_gas && has_liq) ? CLS_NOGAS : CLS_STD);
+  if (classes_only) {
+    if (l == 0) d.cls[c] = cls;
+    return;
+  }
+  const uint8_t fl = d.flags[c];
   double mass, rho_n;
   if (fl & F_NEW_GAS) {
     // equilibrium of the mean density and velocity of the liquid and old
     // interface neighbours (Sec. 2.2), then the collision of this step
-    R rs = R(0), us0 = R(0), us1 = R(0), us2 = R(0);
-    int cnt = 0;
-    for (int k = 1; k < Q; ++k) {
-      int w;
-      int64_t j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
-      if (j < 0) continue;
-      const uint8_t fj = d.flags[j];
-      if (!is_fluid(fj & T_MASK) || (fj & F_NEW_GAS)) continue;
+    const bool use = j >= 0 && is_fluid(tj) && !(fj & F_NEW_GAS);
+    R r = R(0), a = R(0), b = R(0), cc = R(0);
+    if (use) {
       R fj_[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) fj_[i] = St::ld(B, i * stride + j, i);
-      R r, a, b, cc;
       post_moments<R, Q, SH>(fj_, R(d.gx), R(d.gy), R(d.gz), r, a, b, cc);
-      rs += r;
-      us0 += a;
-      us1 += b;
-      us2 += cc;
-      cnt += 1;
     }
-    const R rb = rs / R(cnt);
-    const R ub0 = us0 / R(cnt), ub1 = us1 / R(cnt), ub2 = us2 / R(cnt);
+    const int cnt = __popc(gballot(use));
+    const R rb = gsum(r, Q) / R(cnt);
+    const R ub0 = gsum(a, Q) / R(cnt), ub1 = gsum(b, Q) / R(cnt), ub2 = gsum(cc, Q) / R(cnt);
     const R usq = ub0 * ub0 + ub1 * ub1 + ub2 * ub2;
-    R f[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-      f[k] = feq_k<R, Q, SH>(k, rb, rb - R(1), cdot<R>(kCX[k], kCY[k], kCZ[k], ub0, ub1, ub2),
-                             usq);
-    CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz)};
+    const R fe = feq_k<R, Q, SH>(k, rb, rb - R(1), cdot<R>(kCX[k], kCY[k], kCZ[k], ub0, ub1, ub2),
+                                 usq);
+    CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
     R rr, vx, vy, vz;
-    collide<R, Q, TRT, SH>(f, cp, rr, vx, vy, vz);
-#pragma unroll
-    for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
+    const R fs = gcollide<R, Q, TRT, SH>(fe, l, cp, rr, vx, vy, vz);
+    if (act) St::st(B, k * stride + c, k, fs);
     mass = 0.0;
     rho_n = (double)rb;
   } else if (fl & F_NEW_LIQ) {
-    R fc[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) fc[k] = St::ld(B, k * stride + c, k);
-    const double r = density64<R, Q, SH>(fc);
-    mass = r;
-    rho_n = r;
+    const R fc = act ? St::ld(B, k * stride + c, k) : R(0);
+    rho_n = (SH ? 1.0 : 0.0) + gsum(act ? (double)fc : 0.0, Q);
+    mass = rho_n;
   } else {
     mass = d.m[c];
     rho_n = d.rho_if[c];
   }
-  // excess mass of converted neighbours, equal shares over their interface
-  // neighbours, added in direction order
-  bool has_liq = false, has_gas = false;
-  for (int k = 1; k < Q; ++k) {
-    int w;
-    int64_t j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
-    if (j < 0) continue;
-    const uint8_t fj = d.flags[j];
-    const int tj = fj & T_MASK;
-    has_liq |= (tj == T_LIQ);
-    has_gas |= (tj == T_GAS);
-    if (fj & F_CONV) mass += excess_of(d, j) / (double)count_if_nb<Q>(d, j);
+  // excess mass of converted neighbours: equal shares over their interface
+  // neighbours (Sec. 2.2), added in direction order
+  double share = 0.0;
+  if (j >= 0 && (fj & F_CONV)) share = excess_of(d, j) / (double)count_if_nb<Q>(d, j);
+  for (int i = 1; i < Q; ++i) {
+    const double si = __shfl(share, i, kG);
+    if (__shfl((int)((fj & F_CONV) != 0), i, kG)) mass += si;
   }
-  d.m[c] = mass;
-  d.rho_if[c] = rho_n;
-  d.phiB[c] = mass / rho_n;
-  d.cls[c] = (!has_liq && has_gas) ? CLS_NOLIQ : ((!has_gas && has_liq) ? CLS_NOGAS : CLS_STD);
+  if (l == 0) {
+    d.m[c] = mass;
+    d.rho_if[c] = rho_n;
+    d.phiB[c] = mass / rho_n;
+    d.cls[c] = cls;
+  }
 }
 
 template <int Q>
-__device__ void finish_converted(const Dev& d, int64_t z) {
-  const int t = d.flags[z] & T_MASK;
-  if (count_if_nb<Q>(d, z) == 0) d.lost[z] += excess_of(d, z);
-  d.mark[z] = MK_NONE;
-  const double v = (t == T_LIQ) ? 1.0 : 0.0;
-  d.phiA[z] = v;
-  d.phiB[z] = v;
+__device__ __forceinline__ void finish_converted(const Dev& d, int64_t z, int l) {
+  const bool act = l < Q;
+  int x, y, zz;
+  coords(d.g, z, x, y, zz);
+  bool nbif = false;
+  if (act && l > 0) {
+    int w;
+    const int64_t j = nb_index(d.g, x, y, zz, kCX[l], kCY[l], kCZ[l], &w);
+    nbif = j >= 0 && (d.flags[j] & T_MASK) == T_IF;
+  }
+  const int nif = __popc(gballot(nbif));
+  if (l == 0) {
+    const int t = d.flags[z] & T_MASK;
+    if (nif == 0) d.lost[z] += excess_of(d, z);
+    d.mark[z] = MK_NONE;
+    const double v = (t == T_LIQ) ? 1.0 : 0.0;
+    d.phiA[z] = v;
+    d.phiB[z] = v;
+  }
 }
 
 template <int S, int Q, bool TRT>
@@ -639,28 +788,13 @@ __global__ __launch_bounds__(kBlock) void k_finish(Dev d, int classes_only) {
   const int nif = d.cnt[CNT_IF];
   const int ncv = classes_only ? 0 : d.cnt[CNT_CONV];
   const int total = nif + ncv;
-  for (int k = blockIdx.x * kBlock + threadIdx.x; k < total; k += gridDim.x * kBlock) {
-    if (k < nif) {
-      const int64_t c = d.if_list[k];
-      if (classes_only) {
-        int x, y, z;
-        coords(d.g, c, x, y, z);
-        bool has_liq = false, has_gas = false;
-        for (int i = 1; i < Q; ++i) {
-          int w;
-          int64_t j = nb_index(d.g, x, y, z, kCX[i], kCY[i], kCZ[i], &w);
-          if (j < 0) continue;
-          const int tj = d.flags[j] & T_MASK;
-          has_liq |= (tj == T_LIQ);
-          has_gas |= (tj == T_GAS);
-        }
-        d.cls[c] = (!has_liq && has_gas) ? CLS_NOLIQ : ((!has_gas && has_liq) ? CLS_NOGAS : CLS_STD);
-      } else {
-        finish_interface<S, Q, TRT>(d, c);
-      }
-    } else {
-      finish_converted<Q>(d, d.conv_list[k - nif]);
-    }
+  const int l = threadIdx.x & (kG - 1);
+  const int ngroups = gridDim.x * (kBlock / kG);
+  for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < total; item += ngroups) {
+    if (item < nif)
+      finish_interface<S, Q, TRT>(d, d.if_list[item], l, classes_only != 0);
+    else
+      finish_converted<Q>(d, d.conv_list[item - nif], l);
   }
 }
 
@@ -935,7 +1069,7 @@ __global__ __launch_bounds__(kBlock) void k_init_state(Dev d, int resume) {
       for (int k = 0; k < Q; ++k)
         f[k] = feq_k<R, Q, St::kShift>(k, R(rho), R(rho - 1.0),
                                        cdot<R>(kCX[k], kCY[k], kCZ[k], R(ux), R(uy), R(uz)), usq);
-      CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz)};
+      CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
       R rr, vx, vy, vz;
       collide<R, Q, TRT, St::kShift>(f, cp, rr, vx, vy, vz);
 #pragma unroll

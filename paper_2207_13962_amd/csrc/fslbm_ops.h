@@ -24,8 +24,8 @@ inline int storage_bytes(int storage) { return storage == FSLBM_F64 ? 8 : (stora
 struct Layout {
   int64_t N, stride, tiles, red_blocks;
   size_t off_fA, off_fB, off_flags, off_mark, off_cls, off_phiA, off_phiB, off_m, off_rho_if,
-      off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_cnt, off_scan_if,
-      off_scan_cv, off_scan_ch,
+      off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_gen_list,
+      off_tile_dirty, off_cand, off_cnt, off_scan_if, off_scan_cv, off_scan_ch, off_scan_gen,
       off_pv, off_partial, off_stage, total;
 };
 
@@ -46,7 +46,7 @@ inline Layout make_layout(const fslbm_params& p) {
   const size_t pdf = (size_t)p.q * (size_t)L.stride * storage_bytes(p.storage);
   L.off_fA = take(pdf);
   L.off_fB = take(pdf);
-  L.off_flags = take(L.N);
+  L.off_flags = take(L.N + 16);
   L.off_mark = take(L.N);
   L.off_cls = take(L.N);
   L.off_phiA = take(8 * L.N);
@@ -59,10 +59,14 @@ inline Layout make_layout(const fslbm_params& p) {
   L.off_if_list = take(4 * L.N);
   L.off_conv_list = take(4 * L.N);
   L.off_chunk_list = take(4 * (L.N / 64 + 1));
+  L.off_gen_list = take(4 * L.N);
+  L.off_tile_dirty = take(L.tiles);
+  L.off_cand = take(L.N + 16);
   L.off_cnt = take(4 * CNT_N);
   L.off_scan_if = take(8 * L.tiles);
   L.off_scan_cv = take(8 * L.tiles);
   L.off_scan_ch = take(8 * L.tiles);
+  L.off_scan_gen = take(8 * L.tiles);
   L.off_pv = take(8 * 8);
   L.off_partial = take(8 * kRedN * L.red_blocks + 8 * 16);
   L.off_stage = take(8 * L.N);
@@ -90,6 +94,7 @@ inline const char* validate(const fslbm_params* p) {
   if (!(p->rho_gas > 0.0)) return "rho_gas must be > 0";
   if (!(p->eps_phi >= 0.0)) return "eps_phi must be >= 0";
   if (p->sigma < 0.0) return "sigma must be >= 0";
+  if (!(p->smagorinsky >= 0.0)) return "smagorinsky must be >= 0";
   return nullptr;
 }
 
@@ -153,7 +158,7 @@ struct Impl {
     if (timed) hipEventRecord(c->ev[2 * c->ev_used], s);
     hipLaunchKernelGGL((k_liquid<S, Q, TRT>), dim3(liquid_blocks(c)), dim3(kBlock), 0, s, c->d);
     if (timed) hipEventRecord(c->ev[2 * c->ev_used++ + 1], s);
-    hipLaunchKernelGGL((k_interface<S, Q, TRT>), dim3(if_blocks(c)), dim3(kBlock), 0, s, c->d);
+    hipLaunchKernelGGL((k_generic<S, Q, TRT>), dim3(if_blocks(c)), dim3(kBlock), 0, s, c->d);
   }
   static void convert(fslbm_ctx* c, hipStream_t s, int rebuild) {
     hipLaunchKernelGGL((k_convert<Q>), dim3((unsigned)c->L.tiles), dim3(kBlock), 0, s, c->d,

@@ -32,7 +32,8 @@ class Params(C.Structure):
                 ("storage", C.c_int32), ("boundary", C.c_int32 * 6), ("variant", C.c_int32),
                 ("thurey_flux", C.c_int32), ("bubble_model", C.c_int32), ("tau", C.c_double),
                 ("trt_lambda", C.c_double), ("gravity", C.c_double * 3), ("rho_gas", C.c_double),
-                ("sigma", C.c_double), ("eps_phi", C.c_double), ("tie_delta", C.c_double)]
+                ("sigma", C.c_double), ("eps_phi", C.c_double), ("tie_delta", C.c_double),
+                ("smagorinsky", C.c_double)]
 
 
 class MassReport(C.Structure):
@@ -104,6 +105,7 @@ def make_params(p) -> Params:
     for k in range(3):
         cp.gravity[k] = p.gravity[k]
     cp.rho_gas, cp.sigma, cp.eps_phi, cp.tie_delta = p.rho_gas, p.sigma, p.eps_phi, p.tie_delta
+    cp.smagorinsky = p.smagorinsky
     return cp
 
 

@@ -49,6 +49,7 @@ class Params:
     sigma: float = 0.0
     eps_phi: float = 1e-2
     tie_delta: float = 0.0
+    smagorinsky: float = 0.0
 
     @property
     def n(self) -> int:

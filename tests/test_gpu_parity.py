@@ -100,3 +100,17 @@ def test_flat_rest_all_variants():
             g.step(20)
             assert o.step(20) == 0
             compare_state(g, o, what="rest q%d v%d" % (q, v))
+
+
+@pytest.mark.parametrize("q,coll", [(19, I.TRT), (27, I.SRT)])
+def test_mini_dam_break_smagorinsky(q, coll):
+    """Dam break with the Smagorinsky model on (C_S = 0.1, as used for the
+    paper's dam breaks, Sec. 2.1) at low viscosity: 1e-12 parity, 300 steps."""
+    s = I.rect_dam_break(nx=48, ny=32, nz=16, wx=16, hy=24, g=1e-4, nu=1e-4, q=q, collision=coll,
+                         storage=I.F64, variant=I.OM)
+    s.params = s.params.with_(smagorinsky=0.1)
+    g, o = _sim(s), _oracle(s)
+    for k in range(6):
+        g.step(50)
+        assert o.step(50) == 0
+        compare_state(g, o, what="les q%d c%d step %d" % (q, coll, 50 * (k + 1)))

@@ -548,3 +548,41 @@ def test_standing_wave_frequency_and_damping():
     i = np.argmin(mid[:, 1])
     env = a0 * math.exp(-2 * nu * k * k * mid[i, 0])
     assert abs(-mid[i, 1] - env) / env < 0.2, (mid[i], env)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("coll", [I.SRT, I.TRT])
+def test_smagorinsky_reduces_to_plain_at_equilibrium(q, coll):
+    """Sec. 2.1 turbulence model: with f at equilibrium the non-equilibrium
+    momentum flux vanishes, so tau_t = 0 and the collision is the plain one."""
+    rng = np.random.default_rng(10)
+    for _ in range(10):
+        f = equilibrium(q, rng.uniform(0.9, 1.1), rng.uniform(-0.05, 0.05, 3))
+        a, ua = collide_cell(q, coll, 0.503, 3 / 16, np.zeros(3), f)
+        b, ub, tau = collide_cell(q, coll, 0.503, 3 / 16, np.zeros(3), f, cs=0.1, return_tau=True)
+        assert tau == 0.503
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_smagorinsky_relaxation_time(q):
+    """tau = tau0 + tau_t with tau_t (tau0 + tau_t) = 2 sqrt(2) C_S^2 Qbar / (4 rho c_s^4),
+    Qbar = sqrt(2 Q_ab Q_ab), Q_ab = sum c_a c_b (f - feq) computed here from
+    the populations; the second moment relaxes with 1/tau (g = 0)."""
+    c, _ = lattice(q)
+    rng = np.random.default_rng(11)
+    tau0, cs = 0.503, 0.1
+    for _ in range(20):
+        f = _random_pdf(q, rng, noise=2e-2)
+        fs, u, tau = collide_cell(q, I.SRT, tau0, 0.0, np.zeros(3), f, cs=cs, return_tau=True)
+        rho = f.sum()
+        feq = equilibrium(q, rho, u)
+        Qab = np.einsum("i,ia,ib->ab", f - feq, c, c)
+        Qbar = np.sqrt(2 * (Qab * Qab).sum())
+        tt = tau - tau0
+        assert tt > 0
+        assert abs(tt * (tau0 + tt) - 2 * np.sqrt(2) * cs * cs * Qbar / (4 * rho / 9.0)) < 1e-15
+        pi = np.einsum("i,ia,ib->ab", f, c, c)
+        pieq = np.einsum("i,ia,ib->ab", feq, c, c)
+        pis = np.einsum("i,ia,ib->ab", fs, c, c)
+        assert np.allclose(pis - pieq, (1 - 1 / tau) * (pi - pieq), atol=1e-15)
