@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--variants", default="1,2,3,4")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel-steps", type=int, default=200,
+                    help="time steps per variant run of the kernel-timing region")
+    ap.add_argument("--les", type=float, default=0.0, help="Smagorinsky constant (0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the free-surface LBM step here runs on a single "
@@ -101,53 +104,64 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     variants = [int(v) for v in args.variants.split(",")]
-    setup_fn = lambda: I.workload(args.workload)  # noqa: E731
+    setup_fn = lambda: I.workload(args.workload, **({"smagorinsky": args.les} if args.les else {}))  # noqa: E731
     base = setup_fn()
     p = base.params
-    sims = [Simulation(base, variant=v, device="cuda:0") for v in variants]
-    # warmup, in the same interleaving as the timed region
-    for s in sims:
-        s.step(args.warmup)
-    torch.cuda.synchronize()
-    before = [s.mass(check=False) for s in sims]
-    for s in sims:
-        s.set_timing(args.steps)
-    chunk = 50
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    done = 0
-    while done < args.steps:
-        n = min(chunk, args.steps - done)
+    stream = torch.cuda.Stream()  # a non-default stream: step graphs are replayed on it
+    sb = {I.F64: 8, I.F32: 4, I.F16S: 2}[p.storage]
+    with torch.cuda.stream(stream):
+        sims = [Simulation(base, variant=v, device="cuda:0", stream=stream) for v in variants]
+        # warmup, in the same interleaving as the timed region
         for s in sims:
-            s.step(n)
-        done += n
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    after = [s.mass(check=False) for s in sims]
+            s.step(args.warmup)
+        stream.synchronize()
+        before = [s.mass(check=False) for s in sims]
+        # timed region: K bench steps = K time steps of each variant run
+        chunk = 48
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream.synchronize()
+        ev0.record(stream)
+        done = 0
+        while done < args.steps:
+            n = min(chunk, args.steps - done)
+            for s in sims:
+                s.step(n)
+            done += n
+        ev1.record(stream)
+        stream.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        after = [s.mass(check=False) for s in sims]
+        # dominant kernel: the liquid stream-collide launches of a second timed
+        # region, each launch recording its own start/stop timestamps
+        ksteps = min(args.steps, args.kernel_steps)
+        for s in sims:
+            s.set_timing(ksteps)
+        kb = [s.mass(check=False) for s in sims]
+        t0 = time.perf_counter()
+        for s in sims:
+            s.step(ksteps)
+        stream.synchronize()
+        ka = [s.mass(check=False) for s in sims]
+        launches, kms, liq_bytes = 0, 0.0, 0.0
+        for s, b, a in zip(sims, kb, ka):
+            n, t = s.kernel_time()
+            launches += n
+            kms += t
+            nliq = 0.5 * (b["n_liquid"] + a["n_liquid"])
+            liq_bytes += n * (nliq * bytes_per_update(p.q, sb) + (p.n - nliq) * 1.0)
+            s.set_timing(0)
     # fluid+interface updates: average of the counts before and after the window
     updates = 0.0
     per_variant = {}
     for v, b, a in zip(variants, before, after):
         nb = b["n_liquid"] + b["n_interface"]
         na = a["n_liquid"] + a["n_interface"]
-        u = 0.5 * (nb + na) * args.steps
-        updates += u
+        updates += 0.5 * (nb + na) * args.steps
         per_variant[I.VARIANT_NAMES[v]] = dict(
             fluid_cells=int(na), interface_cells=int(a["n_interface"]),
-            mass_drift=(a["total_mass"] - before[0]["total_mass"] * 0 - b["total_mass"]) / b["total_mass"])
+            mass_drift=(a["total_mass"] - b["total_mass"]) / b["total_mass"],
+            status="ok" if a["status"] == 0 else "unstable (%d)" % a["status"])
     mlups = updates / (ms * 1e-3) / 1e6
-    # dominant kernel: liquid stream-collide
-    launches, kms = 0, 0.0
-    liq_bytes = 0.0
-    sb = {I.F64: 8, I.F32: 4, I.F16S: 2}[p.storage]
-    for s, b, a in zip(sims, before, after):
-        n, t = s.kernel_time()
-        launches += n
-        kms += t
-        nliq = 0.5 * (b["n_liquid"] + a["n_liquid"])
-        liq_bytes += n * (nliq * bytes_per_update(p.q, sb) + (p.n - nliq) * 1.0)
     avg_ms = kms / max(launches, 1)
     bytes_per_launch = liq_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
@@ -185,6 +199,8 @@ def main():
             "cells": p.n,
             "parallelism": "single GPU",
             "effective_GBps_whole_step": whole_gbs,
+            "smagorinsky": args.les,
+            "step_launches": "replayed HIP graphs of 8 steps",
             "per_variant": per_variant,
         },
         "roofline": {

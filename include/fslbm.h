@@ -146,6 +146,12 @@ int fslbm_interface_list(fslbm_ctx* ctx, int32_t* list, int64_t max, int64_t* co
 int fslbm_set_timing(fslbm_ctx* ctx, int64_t capacity);
 int fslbm_kernel_time(fslbm_ctx* ctx, int64_t* launches, double* total_ms);
 
+/* Step launches: with enable = 1 (the default) fslbm_step replays a captured
+ * HIP graph of 8 steps when the context's stream is not the NULL stream and
+ * timing is off; enable = 0 always launches kernel by kernel. Results are
+ * identical either way. Errors: FSLBM_EINVAL (NULL). */
+int fslbm_set_graphs(fslbm_ctx* ctx, int enable);
+
 /* Releases the context (NULL-safe; never fails). Does not free a caller arena. */
 void fslbm_destroy(fslbm_ctx* ctx);
 

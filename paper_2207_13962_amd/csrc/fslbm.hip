@@ -124,7 +124,7 @@ void launch_volume(fslbm_ctx* c, hipStream_t s, bool set_reference) {
   }
 }
 
-int enqueue_steps(fslbm_ctx* c, int64_t n) {
+void enqueue_plain(fslbm_ctx* c, int64_t n) {
   const Ops ops = pick(c->p);
   hipStream_t s = c->stream;
   const bool st = c->p.sigma != 0.0;
@@ -144,6 +144,38 @@ int enqueue_steps(fslbm_ctx* c, int64_t n) {
     std::swap(c->d.phiA, c->d.phiB);
     c->step += 1;
   }
+}
+
+void drop_graph(fslbm_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
+// Steps go to the stream as a replayed graph of kGraphSteps steps where
+// possible (one launch instead of ~5 per step), the rest as plain launches.
+// Timing runs (events per liquid launch) always use plain launches.
+int enqueue_steps(fslbm_ctx* c, int64_t n) {
+  hipStream_t s = c->stream;
+  const bool use_graph = c->graphs && c->ev.empty() && s != nullptr;
+  while (use_graph && n >= kGraphSteps) {
+    if (!c->graph_exec) {
+      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+      enqueue_plain(c, kGraphSteps);  // advances the host-side state
+      e = hipStreamEndCapture(s, &c->graph);
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+    } else {
+      c->step += kGraphSteps;  // pointers are back where they were captured
+    }
+    hipError_t e = hipGraphLaunch(c->graph_exec, s);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    n -= kGraphSteps;
+  }
+  enqueue_plain(c, n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return FSLBM_OK;
@@ -297,6 +329,7 @@ int fslbm_set_variant(fslbm_ctx* c, int variant) {
   if (variant < FSLBM_NBRC || variant > FSLBM_OM3) return set_err(c, FSLBM_EINVAL, "unknown variant");
   c->p.variant = variant;
   c->d.variant = variant;
+  drop_graph(c);  // the variant is a kernel argument of the captured launches
   return FSLBM_OK;
 }
 
@@ -384,6 +417,13 @@ static void release_events(fslbm_ctx* c) {
   c->ev_used = 0;
 }
 
+int fslbm_set_graphs(fslbm_ctx* c, int enable) {
+  if (!c) return FSLBM_EINVAL;
+  c->graphs = enable != 0;
+  if (!c->graphs) drop_graph(c);
+  return FSLBM_OK;
+}
+
 int fslbm_set_timing(fslbm_ctx* c, int64_t capacity) {
   if (!c || capacity < 0) return FSLBM_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -418,6 +458,7 @@ void fslbm_destroy(fslbm_ctx* c) {
     if (c->own_arena) (void)hipFree(c->arena);
   }
   release_events(c);
+  drop_graph(c);
   delete c;
 }
 

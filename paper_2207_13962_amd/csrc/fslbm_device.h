@@ -40,6 +40,9 @@ __host__ __device__ constexpr double weight(int k) {
 //   bit 4 NEW_GAS  became interface from gas in the last conversion
 //   bit 5 NEW_LIQ  became interface from liquid in the last conversion
 //   bit 6 CONV     interface cell converted to liquid or gas in the last conversion
+//   bit 7 COMPLEX  (static) the 3x3x3 neighbourhood wraps through a periodic
+//                  face, crosses a free-slip face or holds an obstacle cell; a
+//                  BORDER cell without it only meets no-slip domain faces
 // ---------------------------------------------------------------------------
 enum : uint8_t { T_GAS = 0, T_IF = 1, T_LIQ = 2, T_NOSLIP = 3, T_FREESLIP = 4 };
 constexpr uint8_t T_MASK = 7;
@@ -47,7 +50,9 @@ constexpr uint8_t F_BORDER = 8;
 constexpr uint8_t F_NEW_GAS = 16;
 constexpr uint8_t F_NEW_LIQ = 32;
 constexpr uint8_t F_CONV = 64;
+constexpr uint8_t F_COMPLEX = 128;
 constexpr uint8_t F_TRANSIENT = F_NEW_GAS | F_NEW_LIQ | F_CONV;
+constexpr uint8_t F_STATIC = F_BORDER | F_COMPLEX;
 
 __host__ __device__ inline bool is_obst(int t) { return t == T_NOSLIP || t == T_FREESLIP; }
 __host__ __device__ inline bool is_fluid(int t) { return t == T_IF || t == T_LIQ; }
@@ -84,6 +89,9 @@ struct Store;
 // its weight, so h_k carries the significant digits, and mass sums 1 + sum h
 // do not pick up the rounding of the weights. F32 stores h in binary32, F16S in
 // binary16 (round to nearest even); arithmetic is binary32 in both.
+// ld/st address element o of a grid; bld/bst go through a raw buffer
+// resource with a per-lane byte offset and a uniform (scalar) byte offset, so
+// a cell's q loads share one address register.
 template <int Q>
 struct Store<ST_F64, Q> {
   using T = double;
@@ -91,6 +99,13 @@ struct Store<ST_F64, Q> {
   static constexpr bool kShift = false;
   static __device__ __forceinline__ R ld(const T* p, int64_t o, int) { return p[o]; }
   static __device__ __forceinline__ void st(T* p, int64_t o, int, R v) { p[o] = v; }
+  static __device__ __forceinline__ R bld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, R x) {
+    using u2 = unsigned int __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, v, s, 0);
+  }
 };
 
 template <int Q>
@@ -100,6 +115,12 @@ struct Store<ST_F32, Q> {
   static constexpr bool kShift = true;
   static __device__ __forceinline__ R ld(const T* p, int64_t o, int) { return p[o]; }
   static __device__ __forceinline__ void st(T* p, int64_t o, int, R v) { p[o] = v; }
+  static __device__ __forceinline__ R bld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, R x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, v, s, 0);
+  }
 };
 
 template <int Q>
@@ -113,7 +134,21 @@ struct Store<ST_F16S, Q> {
   static __device__ __forceinline__ void st(T* p, int64_t o, int, R v) {
     p[o] = static_cast<_Float16>(v);
   }
+  static __device__ __forceinline__ R bld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return static_cast<float>(
+        __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0)));
+  }
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, R x) {
+    __builtin_amdgcn_raw_buffer_store_b16(
+        __builtin_bit_cast(unsigned short, static_cast<_Float16>(x)), r, v, s, 0);
+  }
 };
+
+// Raw buffer resource over `bytes` bytes at p (range-checked: loads beyond
+// return 0, stores beyond are dropped). Third dword as for the gfx9 family.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
 
 // ---------------------------------------------------------------------------
 // Geometry and neighbour lookup.
@@ -398,6 +433,97 @@ __device__ __forceinline__ void collide(R* f, const CollideParams<R>& cp, R& rho
   }
 #pragma unroll
   for (int k = 0; k < Q; ++k) f[k] = out[k];
+}
+
+// The same collision for the shifted binary32 formats, organised by opposite
+// pairs (k, kbar): the symmetric and antisymmetric equilibrium and source parts
+// of a pair are formed once,
+//   e+ = w (dr + rho (4.5 (c.u)^2 - 1.5 u^2)),  e- = 3 w rho (c.u),
+//   S+ = w (9 (c.u)(c.F) - 3 u.F),              S- = 3 w (c.F),
+// and f*_k = f_k + n+ + n-, f*_kbar = f_kbar + n+ - n- with
+// n+- = -omega+- (f+- - e+-) + (1 - omega+-/2) S+-. SRT is omega- = omega+.
+// Algebraically identical to collide(); about half the arithmetic.
+template <int Q, bool TRT>
+__device__ __forceinline__ void collide_pairs(float* f, const CollideParams<float>& cp, float& rho,
+                                              float& ux, float& uy, float& uz) {
+  float r = 0.f, j0 = 0.f, j1 = 0.f, j2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) r += f[k];
+#pragma unroll
+  for (int k = 1; k < Q; k += 2) {
+    const float d = f[k] - f[k + 1];  // c_k f_k + c_kbar f_kbar = c_k (f_k - f_kbar)
+    if (kCX[k] > 0) j0 += d;
+    if (kCX[k] < 0) j0 -= d;
+    if (kCY[k] > 0) j1 += d;
+    if (kCY[k] < 0) j1 -= d;
+    if (kCZ[k] > 0) j2 += d;
+    if (kCZ[k] < 0) j2 -= d;
+  }
+  const float dr = r;
+  rho = 1.f + r;
+  const float inv = 1.f / rho;
+  ux = (j0 + 0.5f * (rho * cp.gx)) * inv;
+  uy = (j1 + 0.5f * (rho * cp.gy)) * inv;
+  uz = (j2 + 0.5f * (rho * cp.gz)) * inv;
+  const float Fx = rho * cp.gx, Fy = rho * cp.gy, Fz = rho * cp.gz;
+  const float usq = ux * ux + uy * uy + uz * uz;
+  const float uF = ux * Fx + uy * Fy + uz * Fz;
+  float om = cp.omega, omm = TRT ? cp.omega_m : cp.omega;
+  if (cp.cs > 0.f) {
+    // non-equilibrium momentum flux: each pair contributes c_a c_b 2 (f+ - e+)
+    float qxx = 0.f, qyy = 0.f, qzz = 0.f, qxy = 0.f, qxz = 0.f, qyz = 0.f;
+#pragma unroll
+    for (int k = 1; k < Q; k += 2) {
+      const float cu = cdot<float>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
+      const float ep = float(weight<Q>(k)) * (dr + rho * (4.5f * cu * cu - 1.5f * usq));
+      const float nq = (f[k] + f[k + 1]) - 2.f * ep;
+      if (kCX[k] != 0) qxx += nq;
+      if (kCY[k] != 0) qyy += nq;
+      if (kCZ[k] != 0) qzz += nq;
+      if (kCX[k] * kCY[k] > 0) qxy += nq;
+      if (kCX[k] * kCY[k] < 0) qxy -= nq;
+      if (kCX[k] * kCZ[k] > 0) qxz += nq;
+      if (kCX[k] * kCZ[k] < 0) qxz -= nq;
+      if (kCY[k] * kCZ[k] > 0) qyz += nq;
+      if (kCY[k] * kCZ[k] < 0) qyz -= nq;
+    }
+    const float tau = les_tau<float>(cp.tau0, cp.cs, rho, qxx, qyy, qzz, qxy, qxz, qyz);
+    om = 1.f / tau;
+    omm = TRT ? 1.f / (0.5f + cp.lambda / (tau - 0.5f)) : om;
+  }
+  const float ap = 1.f - 0.5f * om, am = 1.f - 0.5f * omm;
+  {
+    const float w0 = float(weight<Q>(0));
+    const float ep0 = w0 * (dr - rho * 1.5f * usq);
+    const float sp0 = w0 * (-3.f * uF);
+    f[0] = f[0] - om * (f[0] - ep0) + ap * sp0;
+  }
+#pragma unroll
+  for (int k = 1; k < Q; k += 2) {
+    const float w = float(weight<Q>(k));
+    const float cu = cdot<float>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
+    const float cF = cdot<float>(kCX[k], kCY[k], kCZ[k], Fx, Fy, Fz);
+    const float ep = w * (dr + rho * (4.5f * cu * cu - 1.5f * usq));
+    const float em = w * (3.f * rho * cu);
+    const float sp = w * (9.f * cu * cF - 3.f * uF);
+    const float sm = w * (3.f * cF);
+    const float fp = 0.5f * (f[k] + f[k + 1]), fm = 0.5f * (f[k] - f[k + 1]);
+    const float np = -om * (fp - ep) + ap * sp;
+    const float nm = -omm * (fm - em) + am * sm;
+    f[k] = f[k] + np + nm;
+    f[k + 1] = f[k + 1] + np - nm;
+  }
+}
+
+// Collision dispatch: the binary64 path keeps the term-by-term form above;
+// the shifted binary32 formats use the pair form.
+template <typename R, int Q, bool TRT, bool SH>
+__device__ __forceinline__ void collide_any(R* f, const CollideParams<R>& cp, R& rho, R& ux, R& uy,
+                                            R& uz) {
+  if constexpr (SH && sizeof(R) == 4)
+    collide_pairs<Q, TRT>(f, cp, rho, ux, uy, uz);
+  else
+    collide<R, Q, TRT, SH>(f, cp, rho, ux, uy, uz);
 }
 
 // Anti-bounce-back value (Sec. 2.2): feq_k + feq_kbar at (rhoG, u) minus the

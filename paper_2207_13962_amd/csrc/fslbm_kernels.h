@@ -28,7 +28,7 @@
 namespace fslbm {
 
 constexpr int kBlock = 256;
-constexpr int kConvPer = 16;                   // cells per thread in k_convert
+constexpr int kConvPer = 64;                   // cells per thread in k_convert (one chunk)
 constexpr int kConvTile = kBlock * kConvPer;  // cells per compaction tile
 
 struct Dev {
@@ -88,28 +88,75 @@ __device__ __forceinline__ bool unstable(R rho, R ux, R uy, R uz) {
          rho > R(1e30);
 }
 
-// Liquid cell whose 3x3x3 neighbourhood is inside the domain and free of
-// obstacles: plain pull from the linear neighbour offsets, collision, store.
+// Liquid cell without the COMPLEX flag: pull from the linear neighbour
+// offsets, or - for a cell on a no-slip domain face - bounce-back of its own
+// opposite population where the source lies beyond the face; collision; store.
 // (A liquid cell never has a gas neighbour, so no free-surface logic applies.)
-template <int S, int Q, bool TRT>
-__device__ __forceinline__ void liquid_cell(const Dev& d, int64_t c) {
+// BUF: both grids fit a 32-bit byte range, so loads and stores go through
+// buffer resources; inside the domain a wave uses one per-lane offset (the
+// cell) plus a scalar offset per direction (plane start minus the neighbour
+// offset).
+template <int S, int Q, bool TRT, bool BUF>
+__device__ __forceinline__ void liquid_cell(const Dev& d, int64_t c, bool valid) {
   using St = Store<S, Q>;
   using T = typename St::T;
   using R = typename St::R;
-  const uint8_t fl = d.flags[c];
-  if ((fl & (T_MASK | F_BORDER)) != T_LIQ) return;
+  const uint8_t fl = valid ? d.flags[c] : (uint8_t)T_GAS;
+  const bool mine = (fl & (T_MASK | F_COMPLEX)) == T_LIQ;
+  const bool wall = mine && (fl & F_BORDER);
+  const bool any_wall = __ballot(wall) != 0ull;
+  if (!mine) return;
   const T* A = static_cast<const T*>(d.fA);
   T* B = static_cast<T*>(d.fB);
   const Geom& g = d.g;
   const int64_t stride = g.stride;
+  const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
   R f[Q];
-  load_plain<S, Q>(A, stride, c, g.nx, (int64_t)g.nx * g.ny, f);
+  if (any_wall) {
+    // some lane of the wave sits on a no-slip face: per-lane source offsets
+    int x, y, z;
+    coords(g, c, x, y, z);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int64_t off = kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
+      const bool in = (unsigned)(x - kCX[k]) < (unsigned)g.nx &&
+                      (unsigned)(y - kCY[k]) < (unsigned)g.ny &&
+                      (unsigned)(z - kCZ[k]) < (unsigned)g.nz;
+      const int64_t e = in ? k * stride + c - off : opp(k) * stride + c;
+      if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t ra =
+            make_rsrc(A, (uint32_t)(Q * stride * (int64_t)sizeof(T)));
+        f[k] = St::bld(ra, (uint32_t)(e * (int64_t)sizeof(T)), 0u);
+      } else {
+        f[k] = St::ld(A, e, in ? k : opp(k));
+      }
+    }
+  } else if constexpr (BUF) {
+    const uint32_t bytes = (uint32_t)(Q * stride * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(A, bytes);
+    const uint32_t vo = (uint32_t)c * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int64_t off = kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
+      f[k] = St::bld(ra, vo, (uint32_t)((k * stride - off) * (int64_t)sizeof(T)));
+    }
+  } else {
+    load_plain<S, Q>(A, stride, c, g.nx, nxy, f);
+  }
   CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
   R rho, ux, uy, uz;
-  collide<R, Q, TRT, St::kShift>(f, cp, rho, ux, uy, uz);
+  collide_any<R, Q, TRT, St::kShift>(f, cp, rho, ux, uy, uz);
   if (unstable(rho, ux, uy, uz)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
+  if constexpr (BUF) {
+    const uint32_t bytes = (uint32_t)(Q * stride * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(B, bytes);
+    const uint32_t vo = (uint32_t)c * (uint32_t)sizeof(T);
 #pragma unroll
-  for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
+    for (int k = 0; k < Q; ++k) St::bst(rb, vo, (uint32_t)(k * stride * (int64_t)sizeof(T)), f[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
+  }
 }
 
 // Parker-Youngs normal n = grad(phi) (Sec. 2.2) over the 3x3x3 neighbourhood;
@@ -236,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_generic(Dev d) {
   const Geom& g = d.g;
   const int64_t stride = g.stride;
   const int nif = d.cnt[CNT_IF];
-  const int total = nif + d.cnt[CNT_GEN];
+  const int total = nif;
   const int l = threadIdx.x & (kG - 1);
   const bool act = l < Q;
   const int k = act ? l : 0;
@@ -245,8 +292,8 @@ __global__ __launch_bounds__(kBlock) void k_generic(Dev d) {
   const int ngroups = gridDim.x * (kBlock / kG);
   CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
   for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < total; item += ngroups) {
-    const bool is_if = item < nif;
-    const int64_t c = is_if ? d.if_list[item] : d.gen_list[item - nif];
+    const bool is_if = true;
+    const int64_t c = d.if_list[item];
     int x, y, z;
     coords(g, c, x, y, z);
     // own post-collision population of this direction and of its opposite
@@ -369,9 +416,52 @@ __global__ __launch_bounds__(kBlock) void k_generic(Dev d) {
   }
 }
 
+// Liquid cell with the COMPLEX flag, one thread per cell: each direction's
+// source is resolved with periodic wrap, bounce-back at obstacles and specular
+// reflection at free-slip faces (a liquid cell never has a gas neighbour).
+template <int S, int Q, bool TRT>
+__device__ __forceinline__ void border_cell(const Dev& d, int64_t c) {
+  using St = Store<S, Q>;
+  using T = typename St::T;
+  using R = typename St::R;
+  const T* A = static_cast<const T*>(d.fA);
+  T* B = static_cast<T*>(d.fB);
+  const Geom& g = d.g;
+  const int64_t stride = g.stride;
+  int x, y, z;
+  coords(g, c, x, y, z);
+  R f[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    int64_t src;
+    int dir;
+    bool wall;
+    const int kind = resolve_source<Q>(g, d.flags, x, y, z, k, &src, &dir, &wall);
+    if (kind == SRC_GAS) atomicOr(&d.cnt[CNT_ERR], ERR_LAYER);
+    if (kind != SRC_FLUID) {
+      src = c;
+      dir = opp(k);
+    }
+    f[k] = St::ld(A, dir * stride + src, dir);
+  }
+  CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
+  R rho, ux, uy, uz;
+  collide_any<R, Q, TRT, St::kShift>(f, cp, rho, ux, uy, uz);
+  if (unstable(rho, ux, uy, uz)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
+}
+
+template <int S, int Q, bool TRT>
+__global__ __launch_bounds__(kBlock) void k_border(Dev d) {
+  const int n = d.cnt[CNT_GEN];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    border_cell<S, Q, TRT>(d, d.gen_list[i]);
+}
+
 // Each wave takes 64-cell chunks from the chunk list (chunks without liquid
 // cells are never visited), one cell per lane.
-template <int S, int Q, bool TRT>
+template <int S, int Q, bool TRT, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_liquid(Dev d) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // slot of the next step
@@ -383,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_liquid(Dev d) {
   const int waves = gridDim.x * (kBlock / 64);
   for (int w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); w < nch; w += waves) {
     const int64_t c = (int64_t)d.chunk_list[w] * 64 + lane;
-    if (c < d.g.N) liquid_cell<S, Q, TRT>(d, c);
+    liquid_cell<S, Q, TRT, BUF>(d, c, c < d.g.N);
   }
 }
 
@@ -522,7 +612,7 @@ __device__ __forceinline__ uint8_t new_flags(const Dev& d, int64_t c, uint8_t fl
       }
     }
   }
-  return (uint8_t)((fl & F_BORDER) | nt | bits);
+  return (uint8_t)((fl & F_STATIC) | nt | bits);
 }
 
 
@@ -549,14 +639,14 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
   return before + inc - v;
 }
 
-// Conversion pass. A tile is kConvTile = 4096 consecutive cells; thread t owns
-// the 16 cells [16t, 16t+16) of the tile, read as one 16-byte vector. Only
-// cells flagged as candidates (the 3x3x3 neighbourhood of a marked cell) are
-// re-typed; every cell's transient bits of an earlier conversion are cleared.
-// The interface list, the converted list, the chunk list and the list of
-// liquid cells next to walls are then compacted in ascending cell order: block
-// scan of the per-thread counts, decoupled look-back over the tiles (one wave
-// per list), each thread writing its own entries.
+// Conversion pass. A tile is kConvTile = 16384 consecutive cells; thread t
+// owns the 64 cells [64t, 64t+64) of the tile (one chunk), read as four
+// 16-byte vectors. Only cells flagged as candidates (the 3x3x3 neighbourhood
+// of a marked cell) are re-typed; every cell's transient bits of an earlier
+// conversion are cleared. The interface list, the converted list, the chunk
+// list and the list of COMPLEX liquid cells are then compacted in ascending
+// cell order: block scan of the per-thread counts, decoupled look-back over
+// the tiles (one wave per list), each thread writing its own entries.
 template <int Q>
 __global__ __launch_bounds__(kBlock) void k_convert(Dev d, int rebuild_only) {
   if (!rebuild_only && d.cnt[CNT_MARK0 + (d.step & 1)] == 0) return;
@@ -567,67 +657,75 @@ __global__ __launch_bounds__(kBlock) void k_convert(Dev d, int rebuild_only) {
   __syncthreads();
   const int tile = s_tile;
   const uint32_t epoch = (uint32_t)d.cnt[CNT_EPOCH];
-  const int64_t base = (int64_t)tile * kConvTile + 16 * threadIdx.x;
+  const int64_t base = (int64_t)tile * kConvTile + (int64_t)kConvPer * threadIdx.x;
   const bool update = !rebuild_only && d.tile_dirty[tile];
   const int64_t N = d.g.N;
-  // the 16 flag bytes (and candidate bytes) of this thread
-  union V16 {
-    uint4 v;
-    uint8_t b[16];
-  } fl, cand;
-  const bool full = base + 16 <= N;
-  fl.v = make_uint4(0, 0, 0, 0);
-  cand.v = make_uint4(0, 0, 0, 0);
-  if (full) {
-    fl.v = *reinterpret_cast<const uint4*>(d.flags + base);
-    if (update) cand.v = *reinterpret_cast<const uint4*>(d.cand + base);
-  } else {
-    for (int j = 0; j < 16 && base + j < N; ++j) {
-      fl.b[j] = d.flags[base + j];
-      if (update) cand.b[j] = d.cand[base + j];
+  uint64_t mif = 0, mcv = 0, mgn = 0, mlq = 0;
+  // the next 16-byte vectors are requested before the current ones are processed
+  auto load16 = [&](int v, uint4& f16, uint4& c16) {
+    const int64_t b0 = base + 16 * v;
+    f16 = make_uint4(0, 0, 0, 0);
+    c16 = make_uint4(0, 0, 0, 0);
+    if (v < kConvPer / 16 && b0 + 16 <= N) {
+      f16 = *reinterpret_cast<const uint4*>(d.flags + b0);
+      if (update) c16 = *reinterpret_cast<const uint4*>(d.cand + b0);
     }
-  }
-  uint32_t mif = 0, mcv = 0, mgn = 0;
-  bool changed = false, any_cand = false;
+  };
+  uint4 nf16, nc16;
+  load16(0, nf16, nc16);
+#pragma unroll 1
+  for (int v = 0; v < kConvPer / 16; ++v) {
+    const int64_t b0 = base + 16 * v;
+    union V16 {
+      uint4 v;
+      uint8_t b[16];
+    } fl, cand;
+    const bool full = b0 + 16 <= N;
+    fl.v = nf16;
+    cand.v = nc16;
+    load16(v + 1, nf16, nc16);
+    if (!full) {
+      for (int j = 0; j < 16 && b0 + j < N; ++j) {
+        fl.b[j] = d.flags[b0 + j];
+        if (update) cand.b[j] = d.cand[b0 + j];
+      }
+    }
+    bool changed = false, any_cand = false;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    if (base + j >= N) break;
-    const uint8_t f0 = fl.b[j];
-    uint8_t nf = f0 & (uint8_t)~F_TRANSIENT;
-    if (cand.b[j]) {
-      any_cand = true;
-      nf = new_flags<Q>(d, base + j, f0);
+    for (int j = 0; j < 16; ++j) {
+      if (b0 + j >= N) break;
+      const uint8_t f0 = fl.b[j];
+      uint8_t nf = f0 & (uint8_t)~F_TRANSIENT;
+      if (cand.b[j]) {
+        any_cand = true;
+        nf = new_flags<Q>(d, b0 + j, f0);
+      }
+      changed |= (nf != f0);
+      fl.b[j] = nf;
+      const uint64_t bit = 1ull << (16 * v + j);
+      if ((nf & T_MASK) == T_IF) mif |= bit;
+      if (nf & F_CONV) mcv |= bit;
+      if ((nf & (T_MASK | F_COMPLEX)) == (T_LIQ | F_COMPLEX)) mgn |= bit;
+      if ((nf & (T_MASK | F_COMPLEX)) == T_LIQ) mlq |= bit;
     }
-    changed |= (nf != f0);
-    fl.b[j] = nf;
-    const int t = nf & T_MASK;
-    mif |= (uint32_t)(t == T_IF) << j;
-    mcv |= (uint32_t)((nf & F_CONV) != 0) << j;
-    mgn |= (uint32_t)((nf & (T_MASK | F_BORDER)) == (T_LIQ | F_BORDER)) << j;
-    // chunk activity uses liquid cells away from walls
-    if ((nf & (T_MASK | F_BORDER)) == T_LIQ) mgn |= 1u << (16 + j);
-  }
-  if (changed) {
-    if (full) {
-      *reinterpret_cast<uint4*>(d.flags + base) = fl.v;
-    } else {
-      for (int j = 0; j < 16 && base + j < N; ++j) d.flags[base + j] = fl.b[j];
+    if (changed) {
+      if (full) {
+        *reinterpret_cast<uint4*>(d.flags + b0) = fl.v;
+      } else {
+        for (int j = 0; j < 16 && b0 + j < N; ++j) d.flags[b0 + j] = fl.b[j];
+      }
+    }
+    if (any_cand) {
+      if (full) {
+        *reinterpret_cast<uint4*>(d.cand + b0) = make_uint4(0, 0, 0, 0);
+      } else {
+        for (int j = 0; j < 16 && b0 + j < N; ++j) d.cand[b0 + j] = 0;
+      }
     }
   }
-  if (any_cand) {
-    if (full) {
-      *reinterpret_cast<uint4*>(d.cand + base) = make_uint4(0, 0, 0, 0);
-    } else {
-      for (int j = 0; j < 16 && base + j < N; ++j) d.cand[base + j] = 0;
-    }
-  }
-  // a 64-cell chunk is four consecutive threads
-  bool liq = (mgn >> 16) != 0u;
-  liq |= __shfl_xor(liq, 1, 64);
-  liq |= __shfl_xor(liq, 2, 64);
-  const uint32_t cch = ((threadIdx.x & 3) == 0 && liq) ? 1u : 0u;
-  const uint32_t cnts[4] = {(uint32_t)__popc(mif), (uint32_t)__popc(mcv), cch,
-                            (uint32_t)__popc(mgn & 0xffffu)};
+  const uint32_t cch = mlq ? 1u : 0u;  // this thread's cells are one chunk
+  const uint32_t cnts[4] = {(uint32_t)__popcll(mif), (uint32_t)__popcll(mcv), cch,
+                            (uint32_t)__popcll(mgn)};
   uint32_t pre[4], tot[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) pre[i] = block_excl_scan(cnts[i], s_scan[i], &tot[i]);
@@ -641,14 +739,10 @@ __global__ __launch_bounds__(kBlock) void k_convert(Dev d, int rebuild_only) {
   }
   __syncthreads();
   uint32_t o0 = s_excl[0] + pre[0], o1 = s_excl[1] + pre[1], o3 = s_excl[3] + pre[3];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int32_t c = (int32_t)(base + j);
-    if ((mif >> j) & 1u) d.if_list[o0++] = c;
-    if ((mcv >> j) & 1u) d.conv_list[o1++] = c;
-    if ((mgn >> j) & 1u) d.gen_list[o3++] = c;
-  }
-  if (cch) d.chunk_list[s_excl[2] + pre[2]] = tile * (kConvTile / 64) + (int)(threadIdx.x >> 2);
+  for (uint64_t m = mif; m; m &= m - 1) d.if_list[o0++] = (int32_t)(base + __builtin_ctzll(m));
+  for (uint64_t m = mcv; m; m &= m - 1) d.conv_list[o1++] = (int32_t)(base + __builtin_ctzll(m));
+  for (uint64_t m = mgn; m; m &= m - 1) d.gen_list[o3++] = (int32_t)(base + __builtin_ctzll(m));
+  if (cch) d.chunk_list[s_excl[2] + pre[2]] = (int32_t)(base / 64);
   if (tile == (int)gridDim.x - 1 && threadIdx.x == kBlock - 1) {
     d.cnt[CNT_IF] = (int32_t)o0;
     d.cnt[CNT_CONV] = (int32_t)o1;
@@ -1014,15 +1108,22 @@ __global__ __launch_bounds__(kBlock) void k_init_flags(Dev d) {
   int x, y, z;
   coords(g, c, x, y, z);
   bool border = (x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1);
+  bool complex_ = false;
   bool gas_nb = false;
   for (int dz = -1; dz <= 1; ++dz)
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
+        const int r[3] = {x + dx, y + dy, z + dz};
+        const int n[3] = {g.nx, g.ny, g.nz};
+        for (int a = 0; a < 3; ++a) {
+          const int face = r[a] < 0 ? 2 * a : (r[a] >= n[a] ? 2 * a + 1 : -1);
+          if (face >= 0 && g.bnd[face] != BND_NOSLIP) complex_ = true;
+        }
         int w;
         int64_t j = nb_index(g, x, y, z, dx, dy, dz, &w);
         if (j < 0) continue;
         const int tj = d.flags[j] & T_MASK;
-        if (is_obst(tj)) border = true;
+        if (is_obst(tj)) border = complex_ = true;
       }
   for (int k = 1; k < Q; ++k) {
     int w;
@@ -1031,7 +1132,7 @@ __global__ __launch_bounds__(kBlock) void k_init_flags(Dev d) {
   }
   if (t == T_LIQ && gas_nb) atomicOr(&d.cnt[CNT_ERR], ERR_LAYER);
   // the BORDER bit goes to a separate byte first (neighbours still read types)
-  d.cls[c] = border ? F_BORDER : 0;
+  d.cls[c] = (uint8_t)((border ? F_BORDER : 0) | (complex_ ? F_COMPLEX | F_BORDER : 0));
 }
 
 #ifdef FSLBM_HOST_KERNELS

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "fslbm.h"
+#include <hip/hip_ext.h>
 #include "fslbm_kernels.h"
 
 using namespace fslbm;
@@ -113,7 +114,15 @@ struct fslbm_ctx {
   // optional events around the liquid stream-collide launches
   std::vector<hipEvent_t> ev;
   int64_t ev_used = 0;
+  // captured launch sequence of kGraphSteps steps (an even number, so the
+  // grid and fill-level buffers and the counter slots return to where they
+  // started); replayed while no parameter changes
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool graphs = true;
 };
+
+constexpr int64_t kGraphSteps = 8;
 
 
 namespace fslbm_host {
@@ -127,6 +136,11 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 inline unsigned liquid_blocks(const fslbm_ctx* c) {
   const int64_t chunks = c->L.N / 64 + 1;
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((chunks + 3) / 4, 256 * 7));
+}
+
+inline unsigned border_blocks(const fslbm_ctx* c) {
+  int64_t b = grid_for(c->L.N) / 16 + 64;
+  return (unsigned)std::min<int64_t>(b, 2048);
 }
 
 inline unsigned if_blocks(const fslbm_ctx* c) {
@@ -154,10 +168,21 @@ struct Ops {
 template <int S, int Q, bool TRT>
 struct Impl {
   static void step(fslbm_ctx* c, hipStream_t s) {
+    // buffer addressing when a population grid spans less than 2 GiB
+    const bool buf = (double)Q * (double)c->L.stride * sizeof(typename Store<S, Q>::T) < 2147483648.0;
+    // with timing on, the liquid kernel's own dispatch records start/stop
+    // timestamps (no separate event packets around it)
     const bool timed = 2 * (c->ev_used + 1) <= (int64_t)c->ev.size();
-    if (timed) hipEventRecord(c->ev[2 * c->ev_used], s);
-    hipLaunchKernelGGL((k_liquid<S, Q, TRT>), dim3(liquid_blocks(c)), dim3(kBlock), 0, s, c->d);
-    if (timed) hipEventRecord(c->ev[2 * c->ev_used++ + 1], s);
+    hipEvent_t e0 = timed ? c->ev[2 * c->ev_used] : nullptr;
+    hipEvent_t e1 = timed ? c->ev[2 * c->ev_used + 1] : nullptr;
+    if (timed) c->ev_used++;
+    if (buf)
+      hipExtLaunchKernelGGL((k_liquid<S, Q, TRT, true>), dim3(liquid_blocks(c)), dim3(kBlock), 0, s,
+                            e0, e1, 0, c->d);
+    else
+      hipExtLaunchKernelGGL((k_liquid<S, Q, TRT, false>), dim3(liquid_blocks(c)), dim3(kBlock), 0, s,
+                            e0, e1, 0, c->d);
+    hipLaunchKernelGGL((k_border<S, Q, TRT>), dim3(border_blocks(c)), dim3(kBlock), 0, s, c->d);
     hipLaunchKernelGGL((k_generic<S, Q, TRT>), dim3(if_blocks(c)), dim3(kBlock), 0, s, c->d);
   }
   static void convert(fslbm_ctx* c, hipStream_t s, int rebuild) {

@@ -51,7 +51,8 @@ _lib = None
 
 EXPORTED = ["fslbm_workspace_bytes", "fslbm_create", "fslbm_set_variant", "fslbm_step",
             "fslbm_mass", "fslbm_fields", "fslbm_interface_list", "fslbm_set_timing",
-            "fslbm_kernel_time", "fslbm_destroy", "fslbm_strerror", "fslbm_last_error"]
+            "fslbm_kernel_time", "fslbm_set_graphs", "fslbm_destroy", "fslbm_strerror",
+            "fslbm_last_error"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -82,6 +83,8 @@ def load_library(path: str = LIB_PATH):
     lib.fslbm_set_timing.restype = C.c_int
     lib.fslbm_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     lib.fslbm_kernel_time.restype = C.c_int
+    lib.fslbm_set_graphs.argtypes = [vp, C.c_int]
+    lib.fslbm_set_graphs.restype = C.c_int
     lib.fslbm_destroy.argtypes = [vp]
     lib.fslbm_destroy.restype = None
     lib.fslbm_strerror.argtypes = [C.c_int]
@@ -215,6 +218,10 @@ class Simulation:
         self._check(self._lib.fslbm_interface_list(
             self._h, out.ctypes.data_as(C.POINTER(C.c_int32)), cnt.value, C.byref(cnt)))
         return out[:cnt.value]
+
+    def set_graphs(self, enable):
+        """Replay captured step graphs (default) or launch kernel by kernel."""
+        self._check(self._lib.fslbm_set_graphs(self._h, int(bool(enable))))
 
     def set_timing(self, capacity):
         """Bracket the next `capacity` liquid stream-collide launches with HIP events."""

@@ -390,17 +390,23 @@ def flat_interface_rest(nx=8, ny=12, nz=4, level=6, q=19, variant=OM, storage=F6
 # named workloads
 # ----------------------------------------------------------------------------
 
-def workload(name: str, **kw) -> Setup:
-    """The measured workloads, by name."""
+def workload(name: str, smagorinsky: float = 0.0, **kw) -> Setup:
+    """The measured workloads, by name (optionally with the Smagorinsky model)."""
     if name == "wave64":       # 64x64x1 D3Q19 SRT FP64 standing wave, OM, 1000 steps
-        return gravity_wave(**kw)
-    if name == "dam256":       # 256x128x64 D3Q19 TRT FP32 rectangular dam break, 5000 steps
-        return rect_dam_break(**kw)
-    if name == "cyl256":       # 256x256x128 D3Q27 TRT FP32 cylindrical dam break, 4000 steps
-        return cyl_dam_break(**kw)
-    if name == "taylor512":    # 64x64x512 D3Q27 TRT Taylor bubble with surface tension
-        return taylor_bubble(**kw)
-    raise KeyError(name)
+        s = gravity_wave(**kw)
+    elif name == "dam256":     # 256x128x64 D3Q19 TRT FP32 rectangular dam break, 5000 steps
+        s = rect_dam_break(**kw)
+    elif name == "cyl256":     # 256x256x128 D3Q27 TRT FP32 cylindrical dam break, 4000 steps
+        s = cyl_dam_break(**kw)
+    elif name == "taylor512":  # 64x64x512 D3Q27 TRT Taylor bubble with surface tension
+        s = taylor_bubble(**kw)
+    elif name == "dam512":     # the dam break scaled x2 per axis (HBM-resident working set)
+        s = rect_dam_break(nx=512, ny=256, nz=128, wx=128, hy=192, **kw)
+    else:
+        raise KeyError(name)
+    if smagorinsky:
+        s.params = s.params.with_(smagorinsky=smagorinsky)
+    return s
 
 
 def serving_mix(n_requests=512, seed=1234, rate=None, l_min=48, l_max=192, steps_min=2000,

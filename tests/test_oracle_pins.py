@@ -586,3 +586,20 @@ def test_smagorinsky_relaxation_time(q):
         pieq = np.einsum("i,ia,ib->ab", feq, c, c)
         pis = np.einsum("i,ia,ib->ab", fs, c, c)
         assert np.allclose(pis - pieq, (1 - 1 / tau) * (pi - pieq), atol=1e-15)
+
+
+def test_static_drop_laplace_jump():
+    """A resting drop of radius R holds the Laplace jump 2 sigma / R in the
+    lattice pressure rho/3 (Sec. 2.2: gas, Laplace pressure and curvature); this
+    pins the sign and factor reading rho^G = 3 (p^V + sigma kappa) with
+    kappa = -div(n_hat) of the K8-smoothed fill level. Within 10 % at R = 8."""
+    R, sigma = 8.0, 2e-3
+    s = I.sphere_drop_static(L=32, radius=R, sigma=sigma)
+    o = Oracle(s)
+    assert o.step(600) == 0
+    f = o.fields()
+    t = f["type"].reshape(32, 32, 32)
+    rho = f["rho"].reshape(32, 32, 32)
+    inside = rho[12:20, 12:20, 12:20][t[12:20, 12:20, 12:20] == I.LIQUID].mean()
+    dp = (inside - 1.0) / 3.0
+    assert abs(dp - 2 * sigma / R) < 0.1 * 2 * sigma / R, dp
