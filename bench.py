@@ -3,8 +3,17 @@
 Workload (default): the 3D rectangular dam break, 256 x 128 x 64 cells, D3Q19
 TRT (Lambda = 3/16), FP32 populations (stored shifted by the lattice weights),
 FP64 mass, no-slip walls, liquid column 64 x 96 x 64 at rest in the corner,
-g = 2e-5, nu = 1e-3, run with all four reconstruction variants in turn: one
-bench step advances each of the four variant runs by one time step.
+g = 2e-5, nu = 1e-3, Smagorinsky LES with C_S = 0.1 (the paper's turbulence
+model for its dam breaks, Sec. 2.1 and Sec. 4.2), run with all four
+reconstruction variants in turn: one bench step advances each of the four
+variant runs by one time step.
+
+The timed window (steps 100-1100 after the untimed warm-up, then 200 steps of
+kernel timing) lies inside the phase in which all four variants stay stable;
+later in the collapse the NBKC, OM and OM3 runs of this no-slip 3D setup
+develop velocities above the lattice speed of sound (the paper reports the
+same failure mode for NBKC, Sec. 4.2), so a longer window would time NaN
+states. The status of every variant run is reported with the result.
 
 Prints one JSON line: fluid+interface cell updates per second (MLUPS) over the
 timed steps, the roofline of the dominant kernel (the liquid stream-collide
@@ -59,6 +68,52 @@ def bytes_per_update(q, storage_bytes):
     return 2 * q * storage_bytes + 1
 
 
+# rocprofv3 FETCH_SIZE / WRITE_SIZE are in KiB per dispatch; on MI355X a plain
+# copy kernel of 1 GiB each way reads FETCH_SIZE = 512 MiB and WRITE_SIZE =
+# 1 GiB, so HBM bytes = 2.0 * 1024 * FETCH_SIZE + 1.0 * 1024 * WRITE_SIZE.
+FETCH_SCALE = 2.0
+WRITE_SCALE = 1.0
+
+
+def _counter_rows(path, counter, kernel_prefix):
+    import csv
+    vals = []
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if row["Counter_Name"] == counter and row["Kernel_Name"].startswith(kernel_prefix):
+                vals.append((int(row["Dispatch_Id"]), float(row["Counter_Value"])))
+    vals.sort()
+    return [v for _, v in vals]
+
+
+def write_traffic(fetch_csv, write_csv, last, command):
+    """Turns two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of the
+    benchmark into the traffic summary read back by measured_traffic(): the
+    mean over the last `last` liquid-kernel dispatches (the kernel-timing
+    region of the benchmark)."""
+    fe = _counter_rows(fetch_csv, "FETCH_SIZE", "void fslbm::k_liquid<")
+    wr = _counter_rows(write_csv, "WRITE_SIZE", "void fslbm::k_liquid<")
+    if not fe or not wr:
+        raise SystemExit("no k_liquid dispatches in the counter files")
+    fe, wr = fe[-last:], wr[-last:]
+    f_kib = sum(fe) / len(fe)
+    w_kib = sum(wr) / len(wr)
+    hbm = FETCH_SCALE * 1024 * f_kib + WRITE_SCALE * 1024 * w_kib
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("# HBM traffic of the liquid stream-collide kernel (k_liquid), dam256 workload\n")
+        fh.write("# commands (FETCH_SIZE run, then WRITE_SIZE run):\n")
+        for c in command:
+            fh.write("#   %s\n" % c)
+        fh.write("# dispatches averaged: the last %d of each run (kernel-timing region)\n" % len(fe))
+        fh.write("# scale: HBM bytes = %.1f*1024*FETCH_SIZE + %.1f*1024*WRITE_SIZE (plain-copy calibration)\n"
+                 % (FETCH_SCALE, WRITE_SCALE))
+        fh.write("kernel_source_sha256_16: %s\n" % kernel_source_hash())
+        fh.write("fetch_size_kib_per_launch: %.1f\n" % f_kib)
+        fh.write("write_size_kib_per_launch: %.1f\n" % w_kib)
+        fh.write("hbm_bytes_per_launch: %.0f\n" % hbm)
+    print(open(TRAFFIC_FILE).read())
+
+
 def cpu_baseline(setup_fn, steps):
     """FP64 oracle on the host: fluid+interface updates per second over `steps`
     steps of the same workload (single thread)."""
@@ -82,16 +137,26 @@ def cpu_baseline(setup_fn, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="dam256")
     ap.add_argument("--variants", default="1,2,3,4")
-    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps for the CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=24, help="oracle steps for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=200,
                     help="time steps per variant run of the kernel-timing region")
-    ap.add_argument("--les", type=float, default=0.0, help="Smagorinsky constant (0: off)")
+    ap.add_argument("--les", type=float, default=0.1, help="Smagorinsky constant (0: off)")
+    ap.add_argument("--no-graphs", action="store_true", help="launch kernel by kernel")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 counter runs into the traffic file and exit")
+    ap.add_argument("--traffic-command", action="append", default=[],
+                    help="command line recorded in the traffic file (repeat per run)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1],
+                      len(args.variants.split(",")) * min(args.steps, args.kernel_steps),
+                      args.traffic_command)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the free-surface LBM step here runs on a single "
               "MI355X (no multi-GPU path); run with --gpus 1", file=sys.stderr)
@@ -111,6 +176,8 @@ def main():
     sb = {I.F64: 8, I.F32: 4, I.F16S: 2}[p.storage]
     with torch.cuda.stream(stream):
         sims = [Simulation(base, variant=v, device="cuda:0", stream=stream) for v in variants]
+        for s in sims:
+            s.set_graphs(not args.no_graphs)
         # warmup, in the same interleaving as the timed region
         for s in sims:
             s.step(args.warmup)
@@ -148,19 +215,19 @@ def main():
             launches += n
             kms += t
             nliq = 0.5 * (b["n_liquid"] + a["n_liquid"])
-            liq_bytes += n * (nliq * bytes_per_update(p.q, sb) + (p.n - nliq) * 1.0)
+            liq_bytes += n * nliq * bytes_per_update(p.q, sb)
             s.set_timing(0)
     # fluid+interface updates: average of the counts before and after the window
     updates = 0.0
     per_variant = {}
-    for v, b, a in zip(variants, before, after):
+    for v, b, a, k in zip(variants, before, after, ka):
         nb = b["n_liquid"] + b["n_interface"]
         na = a["n_liquid"] + a["n_interface"]
         updates += 0.5 * (nb + na) * args.steps
         per_variant[I.VARIANT_NAMES[v]] = dict(
             fluid_cells=int(na), interface_cells=int(a["n_interface"]),
             mass_drift=(a["total_mass"] - b["total_mass"]) / b["total_mass"],
-            status="ok" if a["status"] == 0 else "unstable (%d)" % a["status"])
+            status="ok" if k["status"] == 0 else "unstable (%d)" % k["status"])
     mlups = updates / (ms * 1e-3) / 1e6
     avg_ms = kms / max(launches, 1)
     bytes_per_launch = liq_bytes / max(launches, 1)
@@ -200,11 +267,11 @@ def main():
             "parallelism": "single GPU",
             "effective_GBps_whole_step": whole_gbs,
             "smagorinsky": args.les,
-            "step_launches": "replayed HIP graphs of 8 steps",
+            "step_launches": "kernel by kernel" if args.no_graphs else "replayed HIP graphs of 8 steps",
             "per_variant": per_variant,
         },
         "roofline": {
-            "kernel": "k_liquid (pull stream + walls + TRT collision)",
+            "kernel": "k_liquid (pull stream + walls + TRT collision%s)" % (" + LES" if args.les else ""),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -218,6 +285,10 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+    bad = [k for k, v in per_variant.items() if v["status"] != "ok"]
+    if bad:
+        print("warning: variant runs %s became unstable inside the timed window; their later "
+              "steps ran on non-finite states" % ",".join(bad), file=sys.stderr)
 
 
 if __name__ == "__main__":

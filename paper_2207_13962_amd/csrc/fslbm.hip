@@ -96,13 +96,11 @@ void bind(fslbm_ctx* c) {
   d.conv_list = reinterpret_cast<int32_t*>(a + L.off_conv_list);
   d.chunk_list = reinterpret_cast<int32_t*>(a + L.off_chunk_list);
   d.gen_list = reinterpret_cast<int32_t*>(a + L.off_gen_list);
-  d.tile_dirty = reinterpret_cast<uint8_t*>(a + L.off_tile_dirty);
-  d.cand = reinterpret_cast<uint8_t*>(a + L.off_cand);
+  d.mark_list = reinterpret_cast<int32_t*>(a + L.off_mark_list);
+  d.ng_list = reinterpret_cast<int32_t*>(a + L.off_ng_list);
+  d.xs = reinterpret_cast<double*>(a + L.off_xs);
   d.cnt = reinterpret_cast<int32_t*>(a + L.off_cnt);
-  d.scan_if = reinterpret_cast<unsigned long long*>(a + L.off_scan_if);
-  d.scan_cv = reinterpret_cast<unsigned long long*>(a + L.off_scan_cv);
-  d.scan_ch = reinterpret_cast<unsigned long long*>(a + L.off_scan_ch);
-  d.scan_gen = reinterpret_cast<unsigned long long*>(a + L.off_scan_gen);
+  d.scan_status = reinterpret_cast<unsigned long long*>(a + L.off_scan_status);
   d.pV = reinterpret_cast<double*>(a + L.off_pv);
   d.partial = reinterpret_cast<double*>(a + L.off_partial);
 }
@@ -270,12 +268,7 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
     INITCHK(hipMemcpyAsync(c->d.cnt, cnt0, sizeof cnt0, hipMemcpyHostToDevice, s));
     INITCHK(hipStreamSynchronize(s));
   }
-  INITCHK(hipMemsetAsync(c->d.scan_if, 0, 8 * c->L.tiles, s));
-  INITCHK(hipMemsetAsync(c->d.scan_cv, 0, 8 * c->L.tiles, s));
-  INITCHK(hipMemsetAsync(c->d.scan_ch, 0, 8 * c->L.tiles, s));
-  INITCHK(hipMemsetAsync(c->d.scan_gen, 0, 8 * c->L.tiles, s));
-  INITCHK(hipMemsetAsync(c->d.tile_dirty, 0, c->L.tiles, s));
-  INITCHK(hipMemsetAsync(c->d.cand, 0, c->L.N, s));
+  INITCHK(hipMemsetAsync(c->d.scan_status, 0, 16 * c->L.tiles, s));
   INITCHK(hipMemsetAsync(c->d.fB, 0, (size_t)c->p.q * c->L.stride * storage_bytes(c->p.storage), s));
   // types go straight into the flag array, fields into buffers used as staging
   INITCHK(hipMemcpyAsync(c->d.flags, type, N, hipMemcpyHostToDevice, s));

@@ -68,9 +68,11 @@ enum {
   CNT_MARK0 = 2,   // marked cells, slot (step & 1)
   CNT_TICKET = 4,  // block tickets of the compaction scan
   CNT_ERR = 5,     // error bits (see ERR_*)
-  CNT_EPOCH = 6,   // launch epoch of the compaction scan (advanced by every k_liquid)
+  CNT_EPOCH = 6,   // epoch of the compaction scan (advanced before every compaction)
   CNT_CHUNKS = 7,  // 64-cell chunks holding at least one liquid cell
   CNT_GEN = 8,     // liquid cells next to the domain boundary or an obstacle
+  CNT_CONVP = 9,   // converted cells of the previous conversion (transient bits to clear)
+  CNT_NG = 10,     // new interface cells from gas in this step
   CNT_N = 12
 };
 enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8 };

@@ -1,21 +1,24 @@
 // HIP kernels of the free-surface LBM step for gfx950.
 //
-// One time step is four launches (plus two for surface tension, two for the
-// bubble volume):
+// One time step is six launches (plus two for surface tension, two for the
+// bubble volume); the last three run only when some cell was marked:
 //   k_liquid    chunk-list-driven : every liquid cell away from walls - pull
 //                                   streaming, collision, store (the bandwidth
 //                                   kernel)
+//   k_border    list-driven       : liquid cells next to a wall or obstacle
+//                                   (streaming with walls, collision); clears the
+//                                   transient bits of the previous conversion
 //   k_generic   list-driven       : every interface cell of the compacted list -
 //                                   streaming, free-surface condition with the
 //                                   variant's set, mass exchange, fill level,
-//                                   conversion mark, collision - and every liquid
-//                                   cell next to a wall or obstacle
-//   k_convert  every cell         : new type from the marks (to-gas marks next to
-//                                   a to-liquid mark are dropped), in place; the
-//                                   new interface list and the converted list are
-//                                   compacted in ascending order by a single-pass
-//                                   scan (wave ballot + decoupled look-back)
-//   k_finish   list-driven        : reinitialise new interface cells from gas,
+//                                   conversion mark, collision
+//   k_retype    mark-list-driven  : new types around every marked cell (to-gas
+//                                   marks next to a to-liquid mark are dropped)
+//   k_compact   every cell        : the new interface, converted, liquid-chunk
+//                                   and wall-liquid lists, compacted in ascending
+//                                   order by a single-pass scan (block scan +
+//                                   decoupled look-back)
+//   k_finish    list-driven       : reinitialise new interface cells from gas,
 //                                   mass of new interface cells from liquid,
 //                                   excess-mass gather, fill levels, flux classes
 // The state between steps is the post-collision population f* (grid A); the
@@ -28,8 +31,7 @@
 namespace fslbm {
 
 constexpr int kBlock = 256;
-constexpr int kConvPer = 64;                   // cells per thread in k_convert (one chunk)
-constexpr int kConvTile = kBlock * kConvPer;  // cells per compaction tile
+constexpr int kMaxTiles = 4096;  // compaction tiles at most (tile size grows with the domain)
 
 struct Dev {
   Geom g;
@@ -51,17 +53,15 @@ struct Dev {
   double* rhoG;  // per-cell gas density (surface tension), or null
   double* phis;  // smoothed fill level (surface tension), or null
   double* lost;  // per-cell lost excess mass
+  double* xs;    // per converted cell: its excess-mass share per interface neighbour
   int32_t* if_list;
   int32_t* conv_list;
   int32_t* chunk_list;  // 64-cell chunks with liquid cells, ascending
   int32_t* gen_list;    // liquid cells with the BORDER flag, ascending
-  uint8_t* tile_dirty;  // per compaction tile: a conversion mark lies in or next to it
-  uint8_t* cand;        // per cell: lies in the 3x3x3 neighbourhood of a marked cell
+  int32_t* mark_list;   // cells marked in this step (unordered)
+  int32_t* ng_list;     // new interface cells from gas of this step (unordered)
   int32_t* cnt;
-  unsigned long long* scan_if;
-  unsigned long long* scan_cv;
-  unsigned long long* scan_ch;
-  unsigned long long* scan_gen;
+  unsigned long long* scan_status;  // two words per compaction tile
   double* pV;  // device scalars: [0] p^V, [1] p^V(0), [2] V(0)
   double* partial;  // reduction partials
   int64_t step;  // parity selects the mark-counter slot
@@ -209,12 +209,58 @@ __device__ __forceinline__ double flux_term(int cx, int cn, double in, double ou
 // ---------------------------------------------------------------------------
 constexpr int kG = 32;
 
-// sum over the lanes k < n of the group (callers pass 0 from lanes >= n)
-template <typename T>
-__device__ __forceinline__ T gsum(T v, int) {
-#pragma unroll
-  for (int o = kG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kG);
-  return v;
+// Lane exchanges inside a 32-lane group on 32-bit words: DPP row operations
+// (xor 1 and xor 2 within a quad, mirror within 8 and within 16 lanes) and
+// one swizzle (xor 16). After the four row steps of a sum every lane of a
+// 16-lane row holds the row sum; the swizzle adds the other row of the group.
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within 8
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within 16
+constexpr int kSwzXor16 = 0x401F;      // bitmask mode: and 0x1f, xor 0x10
+
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+  return __int_as_float(dpp32<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp32<CTRL>((int)b), hi = dpp32<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float swz16f(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), kSwzXor16));
+}
+__device__ __forceinline__ double swz16d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)b, kSwzXor16);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), kSwzXor16);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 32 lanes of the group (callers pass 0 from lanes that do not
+// take part). Each step adds a lane's value to its partner's in the same
+// order on both sides (a + b and b + a round alike), so every lane ends with
+// the same, deterministic sum; it differs from a sequential sum only by
+// rounding.
+__device__ __forceinline__ float gsum(float v, int) {
+  v += dppf<kDppXor1>(v);
+  v += dppf<kDppXor2>(v);
+  v += dppf<kDppHalfMirror>(v);
+  v += dppf<kDppMirror>(v);
+  return v + swz16f(v);
+}
+__device__ __forceinline__ double gsum(double v, int) {
+  v += dppd<kDppXor1>(v);
+  v += dppd<kDppXor2>(v);
+  v += dppd<kDppHalfMirror>(v);
+  v += dppd<kDppMirror>(v);
+  return v + swz16d(v);
 }
 
 // ballot restricted to the calling lane's group (bit k = lane k of the group)
@@ -270,8 +316,13 @@ __device__ __forceinline__ R gcollide(R f, int k, const CollideParams<R>& cp, R&
          (R(1) - R(0.5) * omm) * m;
 }
 
-// Interface cells (free-surface condition, mass exchange, fill level, mark)
-// and liquid cells next to walls or obstacles (streaming with walls only).
+// Interface cells: streaming, free-surface condition, mass exchange, fill
+// level, conversion mark, collision. Lane k of the cell's group pulls
+// direction k from x - c_k; lanes below 27 also read the 3x3x3 neighbour used
+// by the normal. Every load of the cell is issued in one batch (indices of
+// neighbours beyond a wall are replaced by the cell itself and the values
+// discarded); only a source reflected at a free-slip face needs a second
+// round.
 template <int S, int Q, bool TRT>
 __global__ __launch_bounds__(kBlock) void k_generic(Dev d) {
   using St = Store<S, Q>;
@@ -283,131 +334,147 @@ __global__ __launch_bounds__(kBlock) void k_generic(Dev d) {
   const Geom& g = d.g;
   const int64_t stride = g.stride;
   const int nif = d.cnt[CNT_IF];
-  const int total = nif;
   const int l = threadIdx.x & (kG - 1);
   const bool act = l < Q;
   const int k = act ? l : 0;
   const int kb = opp(k);
   const int cx = kCX[k], cy = kCY[k], cz = kCZ[k];
   const int ngroups = gridDim.x * (kBlock / kG);
+  const int v = d.variant;
   CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
-  for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < total; item += ngroups) {
-    const bool is_if = true;
+  for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < nif; item += ngroups) {
     const int64_t c = d.if_list[item];
     int x, y, z;
     coords(g, c, x, y, z);
-    // own post-collision population of this direction and of its opposite
+    // pull source x - c_k and 3x3x3 neighbour of this lane
+    int wd = 0, wb = 0;
+    const int64_t jd = nb_index(g, x, y, z, -cx, -cy, -cz, &wd);
+    const int64_t jb = l < 27 ? nb_index(g, x, y, z, l % 3 - 1, (l / 3) % 3 - 1, l / 9 - 1, &wb) : c;
+    const int64_t js = jd >= 0 ? jd : c, jbs = jb >= 0 ? jb : c;
+    // the batch
     const R fo = act ? St::ld(A, k * stride + c, k) : R(0);
+    const R fpull = act ? St::ld(A, k * stride + js, k) : R(0);
+    const uint8_t fld = d.flags[js];
+    const uint8_t flb = d.flags[jbs];
+    const double phid = d.phiA[js];
+    const double phib = d.phiA[jbs];
+    const uint8_t clsd = d.cls[js];
+    const uint8_t cls_c = d.cls[c];
+    const double phi_c = d.phiA[c];
+    const double m_c = d.m[c];
+    const double rhoG_c = d.rhoG ? d.rhoG[c] : d.pV[0] * 3.0;
+    // own post-collision population of the opposite direction
     const R fo_b = __shfl(fo, kb, kG);
-    int64_t src;
-    int dir;
-    bool wall;
-    const int kind = resolve_source<Q>(g, d.flags, x, y, z, k, &src, &dir, &wall);
-    R in_val = R(0);
-    if (act && kind == SRC_FLUID) in_val = St::ld(A, dir * stride + src, dir);
-    R f;
-    if (!is_if) {
-      if (act && kind == SRC_GAS) atomicOr(&d.cnt[CNT_ERR], ERR_LAYER);
-      f = (kind == SRC_FLUID) ? in_val : fo_b;
+    // kind of the pull source (Sec. 2.1 walls, Sec. 2.2 gas)
+    const int st = jd >= 0 ? (fld & T_MASK) : wd;
+    const bool wall = is_obst(st);
+    int kind;
+    int64_t src = jd;
+    int dir = k;
+    R in_val = fpull;
+    uint8_t fl_src = fld, cls_src = clsd;
+    double phi_src = phid;
+    if (st == T_GAS) {
+      kind = SRC_GAS;
+    } else if (is_fluid(st)) {
+      kind = SRC_FLUID;
+    } else if (st == T_NOSLIP) {
+      kind = SRC_BOUNCE;
     } else {
-      // velocity of the collision at t, from the post-collision populations
-      // (fo is zero on lanes >= q)
-      const R r0 = gsum(fo, Q);
-      const R a0 = gsum(cx > 0 ? fo : (cx < 0 ? -fo : R(0)), Q);
-      const R a1 = gsum(cy > 0 ? fo : (cy < 0 ? -fo : R(0)), Q);
-      const R a2 = gsum(cz > 0 ? fo : (cz < 0 ? -fo : R(0)), Q);
-      const R rho_t = SH ? R(1) + r0 : r0;
-      const R ux = (a0 - R(0.5) * (rho_t * R(d.gx))) / rho_t;
-      const R uy = (a1 - R(0.5) * (rho_t * R(d.gy))) / rho_t;
-      const R uz = (a2 - R(0.5) * (rho_t * R(d.gz))) / rho_t;
-      const R usq = ux * ux + uy * uy + uz * uz;
-      // missing populations (direct gas sources) and the variant's set (Sec. 3)
-      const uint32_t gas = gballot(act && l > 0 && kind == SRC_GAS && !wall);
-      const int missing = __popc(gas);
-      const int v = d.variant;
-      const bool nb_based = (v == 1 || v == 2 || (v == 4 && missing < 3));
-      bool in_R = ((gas >> k) & 1u) != 0;
-      const double phi_c = d.phiA[c];
-      if (nb_based) {
-        // Parker-Youngs normal (Sec. 2.2): lane l holds phi at offset
-        // (l%3-1, (l/3)%3-1, l/9-1); obstacle points take the centre value
-        double vphi = phi_c;
-        if (l < 27) {
-          int64_t j;
-          const int t = nb_type(g, d.flags, x, y, z, l % 3 - 1, (l / 3) % 3 - 1, l / 9 - 1, &j);
-          vphi = is_obst(t) ? phi_c : d.phiA[j];
-        }
-        // lane stride of each axis in the 3x3x3 numbering
-        double n[3];
-#pragma unroll 1
-        for (int a = 0; a < 3; ++a) {
-          const int sa = a == 0 ? 1 : (a == 1 ? 3 : 9);
-          const int s1 = a == 0 ? 3 : (a == 1 ? 9 : 1);
-          const int s2 = a == 0 ? 9 : (a == 1 ? 1 : 3);
-          double sacc = 0.0;
-#pragma unroll 1
-          for (int b = -1; b <= 1; ++b) {
-            const double wb = b == 0 ? 2.0 : 1.0;
-#pragma unroll
-            for (int cc = -1; cc <= 1; ++cc) {
-              const int lc = 13 + b * s1 + cc * s2;
-              const double vp = __shfl(vphi, lc + sa, kG), vm = __shfl(vphi, lc - sa, kG);
-              sacc += wb * (cc == 0 ? 2.0 : 1.0) * (vp - vm);
-            }
-          }
-          n[a] = sacc;
-        }
-        double nmax = fabs(n[0]);
-        nmax = fabs(n[1]) > nmax ? fabs(n[1]) : nmax;
-        nmax = fabs(n[2]) > nmax ? fabs(n[2]) : nmax;
-        const double dot = n[0] * cx + n[1] * cy + n[2] * cz;
-        if ((k > 0 || v == 1) && dot >= -d.delta * nmax) in_R = true;
+      kind = reflect_source<Q>(g, d.flags, x, y, z, k, &src, &dir);
+      if (act && kind == SRC_FLUID) {
+        in_val = St::ld(A, dir * stride + src, dir);
+        fl_src = d.flags[src];
+        cls_src = d.cls[src];
+        phi_src = d.phiA[src];
       }
-      const R rhoG = d.rhoG ? R(d.rhoG[c]) : R(d.pV[0] * 3.0);
-      if (kind == SRC_BOUNCE)
-        f = fo_b;
-      else if (kind == SRC_GAS || (in_R && !wall))
-        f = abb_value<R, Q, SH>(k, rhoG, ux, uy, uz, usq, fo_b);
-      else
-        f = in_val;
-      // mass exchange (Sec. 2.2) along the actual streaming path of direction k
-      double term = 0.0;
-      if (act && l > 0 && kind == SRC_FLUID) {
-        const double in = (double)in_val, out = (double)fo_b;
-        if ((d.flags[src] & T_MASK) == T_LIQ) {
-          term = in - out;
-        } else {
-          const double T_ = d.thurey ? flux_term(d.cls[c], d.cls[src], in, out) : in - out;
-          term = 0.5 * (phi_c + d.phiA[src]) * T_;
-        }
+    }
+    // velocity of the collision at t, from the post-collision populations
+    // (fo is zero on lanes >= q)
+    const R r0 = gsum(fo, Q);
+    const R a0 = gsum(cx > 0 ? fo : (cx < 0 ? -fo : R(0)), Q);
+    const R a1 = gsum(cy > 0 ? fo : (cy < 0 ? -fo : R(0)), Q);
+    const R a2 = gsum(cz > 0 ? fo : (cz < 0 ? -fo : R(0)), Q);
+    const R rho_t = SH ? R(1) + r0 : r0;
+    const R ux = (a0 - R(0.5) * (rho_t * R(d.gx))) / rho_t;
+    const R uy = (a1 - R(0.5) * (rho_t * R(d.gy))) / rho_t;
+    const R uz = (a2 - R(0.5) * (rho_t * R(d.gz))) / rho_t;
+    const R usq = ux * ux + uy * uy + uz * uz;
+    // missing populations (direct gas sources) and the variant's set (Sec. 3)
+    const uint32_t gas = gballot(act && l > 0 && kind == SRC_GAS && !wall);
+    const int missing = __popc(gas);
+    const bool nb_based = (v == 1 || v == 2 || (v == 4 && missing < 3));
+    bool in_R = ((gas >> k) & 1u) != 0;
+    if (nb_based) {
+      // Parker-Youngs normal (Sec. 2.2): lane l holds phi at offset
+      // (l%3-1, (l/3)%3-1, l/9-1); obstacle points take the centre value
+      double vphi = phi_c;
+      if (l < 27) {
+        const int tb = jb >= 0 ? (flb & T_MASK) : wb;
+        vphi = is_obst(tb) ? phi_c : phib;
       }
-      const double dm = gsum(term, Q);
-      const double rho_n = (SH ? 1.0 : 0.0) + gsum(act ? (double)f : 0.0, Q);
-      const double m_new = d.m[c] + dm;
-      const double phi_n = m_new / rho_n;
-      uint8_t mk = MK_NONE;
-      if (phi_n > 1.0 + d.eps)
-        mk = MK_L;
-      else if (phi_n < -d.eps)
-        mk = MK_G;
-      if (l == 0) {
-        d.m[c] = m_new;
-        d.rho_if[c] = rho_n;
-        d.phiB[c] = phi_n;
-        d.mark[c] = mk;
-        if (mk) atomicAdd(&d.cnt[CNT_MARK0 + (d.step & 1)], 1);
-        if (!(m_new == m_new)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
+      // n_a = sum over the box of the lane's Parker-Youngs weight (offset
+      // along a times the {1,2,1} weights of the other two offsets) times
+      // phi: the terms of the weighted central differences, summed over the
+      // group
+      double wx = 0.0, wy = 0.0, wz = 0.0;
+      if (l < 27) {
+        const int ox = l % 3 - 1, oy = (l / 3) % 3 - 1, oz = l / 9 - 1;
+        const double Wx = ox == 0 ? 2.0 : 1.0, Wy = oy == 0 ? 2.0 : 1.0, Wz = oz == 0 ? 2.0 : 1.0;
+        wx = ox * Wy * Wz;
+        wy = oy * Wx * Wz;
+        wz = oz * Wx * Wy;
       }
-      if (mk && l < 27) {
-        // the conversion pass re-types the 3x3x3 neighbourhood of a marked
-        // cell (every writer stores the same value)
-        int w;
-        const int64_t j = nb_index(g, x, y, z, l % 3 - 1, (l / 3) % 3 - 1, l / 9 - 1, &w);
-        if (j >= 0) {
-          d.cand[j] = 1;
-          d.tile_dirty[j / kConvTile] = 1;
-        }
+      double n[3];
+      n[0] = gsum(wx * vphi, Q);
+      n[1] = gsum(wy * vphi, Q);
+      n[2] = gsum(wz * vphi, Q);
+      double nmax = fabs(n[0]);
+      nmax = fabs(n[1]) > nmax ? fabs(n[1]) : nmax;
+      nmax = fabs(n[2]) > nmax ? fabs(n[2]) : nmax;
+      const double dot = n[0] * cx + n[1] * cy + n[2] * cz;
+      if ((k > 0 || v == 1) && dot >= -d.delta * nmax) in_R = true;
+    }
+    const R rhoG = R(rhoG_c);
+    R f;
+    if (kind == SRC_BOUNCE)
+      f = fo_b;
+    else if (kind == SRC_GAS || (in_R && !wall))
+      f = abb_value<R, Q, SH>(k, rhoG, ux, uy, uz, usq, fo_b);
+    else
+      f = in_val;
+    // mass exchange (Sec. 2.2) along the actual streaming path of direction k
+    double term = 0.0;
+    if (act && l > 0 && kind == SRC_FLUID) {
+      const double in = (double)in_val, out = (double)fo_b;
+      if ((fl_src & T_MASK) == T_LIQ) {
+        term = in - out;
+      } else {
+        const double T_ = d.thurey ? flux_term(cls_c, cls_src, in, out) : in - out;
+        term = 0.5 * (phi_c + phi_src) * T_;
       }
+    }
+    const double dm = gsum(term, Q);
+    const double rho_n = (SH ? 1.0 : 0.0) + gsum(act ? (double)f : 0.0, Q);
+    const double m_new = m_c + dm;
+    const double phi_n = m_new / rho_n;
+    uint8_t mk = MK_NONE;
+    if (phi_n > 1.0 + d.eps)
+      mk = MK_L;
+    else if (phi_n < -d.eps)
+      mk = MK_G;
+    if (l == 0) {
+      d.m[c] = m_new;
+      d.rho_if[c] = rho_n;
+      d.phiB[c] = phi_n;
+      d.mark[c] = mk;
+      if (mk) d.mark_list[atomicAdd(&d.cnt[CNT_MARK0 + (d.step & 1)], 1)] = (int32_t)c;
+      if (!(m_new == m_new)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
+      // a new interface cell of the previous conversion loses its transient
+      // bits (readers in this kernel look at the type bits only); lane 0
+      // pulls the rest direction from the cell itself, so fld is its flag
+      const uint8_t fc = fld;
+      if (fc & F_TRANSIENT) d.flags[c] = (uint8_t)(fc & ~F_TRANSIENT);
     }
     R rho, vx, vy, vz;
     const R fs = gcollide<R, Q, TRT, SH>(f, l, cp, rho, vx, vy, vz);
@@ -452,11 +519,20 @@ __device__ __forceinline__ void border_cell(const Dev& d, int64_t c) {
   for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
 }
 
+// Also clears the transient bits of the cells converted by the previous
+// conversion (readers in this kernel look at the type bits only).
 template <int S, int Q, bool TRT>
 __global__ __launch_bounds__(kBlock) void k_border(Dev d) {
   const int n = d.cnt[CNT_GEN];
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-    border_cell<S, Q, TRT>(d, d.gen_list[i]);
+  const int ncv = d.cnt[CNT_CONVP];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n + ncv; i += gridDim.x * kBlock) {
+    if (i < n) {
+      border_cell<S, Q, TRT>(d, d.gen_list[i]);
+    } else {
+      const int32_t z = d.conv_list[i - n];
+      d.flags[z] = (uint8_t)(d.flags[z] & ~F_TRANSIENT);
+    }
+  }
 }
 
 // Each wave takes 64-cell chunks from the chunk list (chunks without liquid
@@ -465,8 +541,10 @@ template <int S, int Q, bool TRT, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_liquid(Dev d) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // slot of the next step
-    d.cnt[CNT_TICKET] = 0;
-    d.cnt[CNT_EPOCH] += 1;  // a new epoch for this step's compaction scan
+    // the converted list of the previous conversion is cleared by k_border
+    d.cnt[CNT_CONVP] = d.cnt[CNT_CONV];
+    d.cnt[CNT_CONV] = 0;
+    d.cnt[CNT_NG] = 0;
   }
   const int nch = d.cnt[CNT_CHUNKS];
   const int lane = threadIdx.x & 63;
@@ -478,143 +556,72 @@ __global__ __launch_bounds__(kBlock) void k_liquid(Dev d) {
 }
 
 // ---------------------------------------------------------------------------
-// k_convert: new types from marks, in place, plus compaction.
+// k_retype and k_compact: new types from the marks, then the lists.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long pack_status(uint32_t epoch, uint32_t flag,
-                                                          uint32_t val) {
-  return ((unsigned long long)epoch << 32) | ((unsigned long long)flag << 30) | val;
-}
-
-// Exclusive prefix of this tile's aggregate over all earlier tiles, computed by
-// one wave with decoupled look-back: each tile publishes its aggregate (flag 1)
-// at once and its inclusive prefix (flag 2) when known; a tile sums the
-// aggregates of its predecessors back to the nearest inclusive prefix, 64 tiles
-// per round. Entries carry the launch epoch, so the array never needs clearing.
-// The status word is the only datum exchanged, so relaxed device-scope atomics
-// suffice (no acquire/release: those would flush the XCD's L2 on every poll).
-// The wait on a predecessor is bounded: on expiry the scan error bit is set and
-// the kernel completes (with a wrong list, reported by the host).
-__device__ uint32_t lookback_wave(unsigned long long* status, int tile, uint32_t agg,
-                                  uint32_t epoch, int32_t* err) {
-  const int lane = threadIdx.x & 63;
-  if (lane == 0)
-    __hip_atomic_store(&status[tile], pack_status(epoch, tile == 0 ? 2u : 1u, agg),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  uint32_t excl = 0;
-  int base = tile - 1;
-  bool done = (tile == 0);
-  int spins = 0;
-  while (!done) {
-    const int t = base - lane;
-    unsigned long long v = 0;
-    uint32_t fl = 3u;  // before the first tile: acts as an inclusive prefix of 0
-    if (t >= 0) {
-      for (;;) {
-        v = __hip_atomic_load(&status[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((uint32_t)(v >> 32) == epoch) break;
-        if (++spins > (1 << 22)) {
-          atomicOr(err, ERR_SCAN);
-          v = pack_status(epoch, 2u, 0u);
-          break;
-        }
-        if (spins > 64) __builtin_amdgcn_s_sleep(1);
-      }
-      fl = (uint32_t)(v >> 30) & 3u;
-    }
-    const uint32_t val = (t >= 0) ? (uint32_t)(v & 0x3fffffffu) : 0u;
-    const unsigned long long pm = __ballot(fl >= 2u);
-    const int stop = pm ? __builtin_ctzll(pm) : 64;
-    uint32_t contrib = (lane <= stop) ? val : 0u;
-    for (int o = 32; o > 0; o >>= 1) contrib += __shfl_xor(contrib, o, 64);
-    excl += contrib;
-    if (pm)
-      done = true;
-    else
-      base -= 64;
+// Conversion of the marked cells (Sec. 2.2), one group of 32 lanes per cell
+// of the mark list, lane k looking at the neighbour x + c_k. A to-liquid mark
+// turns the cell liquid and its gas neighbours interface. A to-gas mark is
+// dropped when some neighbour carries a to-liquid mark (separating liquid from
+// gas comes first); otherwise the cell turns gas and its liquid neighbours
+// interface. A surviving to-gas cell has no to-liquid neighbour, so no cell is
+// asked to become two things; a cell reached from several marked cells gets
+// the same byte from each, whatever the order of the groups.
+// Turns the gas cell j into a new interface cell (static bits kept) by a
+// compare-and-swap on the 32-bit word holding its flag byte; true for the one
+// caller that made the change. Plain byte stores to the other bytes of the
+// word only make the exchange retry.
+__device__ __forceinline__ bool set_new_gas(uint8_t* flags, int64_t j) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(flags + (j & ~(int64_t)3));
+  const int sh = 8 * (int)(j & 3);
+  uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const uint8_t f = (uint8_t)(old >> sh);
+    if ((f & T_MASK) != T_GAS) return false;
+    const uint8_t nf = (uint8_t)((f & F_STATIC) | T_IF | F_NEW_GAS);
+    const uint32_t want = (old & ~(0xffu << sh)) | ((uint32_t)nf << sh);
+    if (__hip_atomic_compare_exchange_strong(w, &old, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return true;
   }
-  if (lane == 0 && tile > 0)
-    __hip_atomic_store(&status[tile], pack_status(epoch, 2u, excl + agg), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  return excl;
 }
 
-// Marks of the q-1 stencil neighbours of c, gathered with independent loads;
-// returns a bit set: bit 0 some neighbour is marked to-liquid, bit 1 some
-// neighbour is marked to-gas. (Only interface cells carry marks.)
+// Block 0 also starts the compaction that follows: ticket counter reset and,
+// when the compaction will run, a new epoch for its tile-status words.
 template <int Q>
-__device__ __forceinline__ int nb_marks(const Dev& d, int64_t c, bool border) {
-  const Geom& g = d.g;
-  int x = 0, y = 0, z = 0;
-  if (border) coords(g, c, x, y, z);
-  const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
-  int acc = 0;
-#pragma unroll
-  for (int k = 1; k < Q; ++k) {
-    int64_t j;
-    if (!border) {
-      j = c + kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
-    } else {
+__global__ __launch_bounds__(kBlock) void k_retype(Dev d, int rebuild_only) {
+  const int nmk = rebuild_only ? 0 : d.cnt[CNT_MARK0 + (d.step & 1)];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.cnt[CNT_TICKET] = 0;
+    if (rebuild_only || nmk > 0) d.cnt[CNT_EPOCH] += 1;
+  }
+  const int l = threadIdx.x & (kG - 1);
+  const int ngroups = gridDim.x * (kBlock / kG);
+  for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < nmk; item += ngroups) {
+    const int64_t c = d.mark_list[item];
+    const uint8_t mk = d.mark[c];
+    int x, y, z;
+    coords(d.g, c, x, y, z);
+    int64_t j = -1;
+    if (l > 0 && l < Q) {
       int w;
-      j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
+      j = nb_index(d.g, x, y, z, kCX[l], kCY[l], kCZ[l], &w);
     }
-    const uint8_t m = j >= 0 ? d.mark[j] : (uint8_t)MK_NONE;
-    acc |= m;  // MK_L = 1, MK_G = 2
-  }
-  return acc;
-}
-
-// New cell type of cell c from its flags and the marks around it.
-template <int Q>
-__device__ __forceinline__ uint8_t new_flags(const Dev& d, int64_t c, uint8_t fl) {
-  const Geom& g = d.g;
-  const int t = fl & T_MASK;
-  int nt = t;
-  uint8_t bits = 0;
-  const bool border = (fl & F_BORDER) != 0;
-  const uint8_t mk = (t == T_IF) ? d.mark[c] : (uint8_t)MK_NONE;
-  if (t == T_GAS || t == T_LIQ || (t == T_IF && mk != MK_NONE)) {
-    const int around = nb_marks<Q>(d, c, border);
-    if (t == T_IF) {
-      // a to-gas mark next to a to-liquid mark is dropped (Sec. 2.2:
-      // separation of liquid and gas has priority)
-      if (mk == MK_L) {
-        nt = T_LIQ;
-        bits = F_CONV;
-      } else if (!(around & MK_L)) {
-        nt = T_GAS;
-        bits = F_CONV;
+    const uint8_t mj = j >= 0 ? d.mark[j] : (uint8_t)MK_NONE;
+    const uint8_t fj = j >= 0 ? d.flags[j] : (uint8_t)0;
+    const bool nb_liq_mark = gballot(mj == MK_L) != 0u;
+    if (mk == MK_L) {
+      if (l == 0) d.flags[c] = (uint8_t)((d.flags[c] & F_STATIC) | T_LIQ | F_CONV);
+      if (j >= 0 && (fj & T_MASK) == T_GAS) {
+        // the one group whose exchange turns the gas byte into an interface
+        // byte lists the cell for its reinitialisation
+        if (set_new_gas(d.flags, j)) d.ng_list[atomicAdd(&d.cnt[CNT_NG], 1)] = (int32_t)j;
       }
-    } else if (t == T_GAS) {
-      if (around & MK_L) {
-        nt = T_IF;
-        bits = F_NEW_GAS;
-      }
-    } else if (around & MK_G) {
-      // liquid next to a to-gas mark: becomes interface if that mark survives
-      int x = 0, y = 0, z = 0;
-      if (border) coords(g, c, x, y, z);
-      const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
-#pragma unroll 1
-      for (int k = 1; k < Q; ++k) {
-        int64_t j;
-        if (!border) {
-          j = c + kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
-        } else {
-          int w;
-          j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
-          if (j < 0) continue;
-        }
-        if (d.mark[j] == MK_G && !(nb_marks<Q>(d, j, (d.flags[j] & F_BORDER) != 0) & MK_L)) {
-          nt = T_IF;
-          bits = F_NEW_LIQ;
-          break;
-        }
-      }
+    } else if (mk == MK_G && !nb_liq_mark) {
+      if (l == 0) d.flags[c] = (uint8_t)((d.flags[c] & F_STATIC) | T_GAS | F_CONV);
+      if (j >= 0 && (fj & T_MASK) == T_LIQ) d.flags[j] = (uint8_t)((fj & F_STATIC) | T_IF | F_NEW_LIQ);
     }
   }
-  return (uint8_t)((fl & F_STATIC) | nt | bits);
 }
-
 
 // Block-wide exclusive scan of a per-thread count (wave prefix by shuffles,
 // wave totals through LDS). Returns the prefix; *total receives the block sum.
@@ -639,146 +646,85 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
   return before + inc - v;
 }
 
-// Conversion pass. A tile is kConvTile = 16384 consecutive cells; thread t
-// owns the 64 cells [64t, 64t+64) of the tile (one chunk), read as four
-// 16-byte vectors. Only cells flagged as candidates (the 3x3x3 neighbourhood
-// of a marked cell) are re-typed; every cell's transient bits of an earlier
-// conversion are cleared. The interface list, the converted list, the chunk
-// list and the list of COMPLEX liquid cells are then compacted in ascending
-// cell order: block scan of the per-thread counts, decoupled look-back over
-// the tiles (one wave per list), each thread writing its own entries.
-template <int Q>
-__global__ __launch_bounds__(kBlock) void k_convert(Dev d, int rebuild_only) {
-  if (!rebuild_only && d.cnt[CNT_MARK0 + (d.step & 1)] == 0) return;
-  __shared__ int s_tile;
-  __shared__ uint32_t s_scan[4][kBlock / 64];
-  __shared__ uint32_t s_excl[4];
-  if (threadIdx.x == 0) s_tile = atomicAdd(&d.cnt[CNT_TICKET], 1);
-  __syncthreads();
-  const int tile = s_tile;
-  const uint32_t epoch = (uint32_t)d.cnt[CNT_EPOCH];
-  const int64_t base = (int64_t)tile * kConvTile + (int64_t)kConvPer * threadIdx.x;
-  const bool update = !rebuild_only && d.tile_dirty[tile];
-  const int64_t N = d.g.N;
-  uint64_t mif = 0, mcv = 0, mgn = 0, mlq = 0;
-  // the next 16-byte vectors are requested before the current ones are processed
-  auto load16 = [&](int v, uint4& f16, uint4& c16) {
-    const int64_t b0 = base + 16 * v;
-    f16 = make_uint4(0, 0, 0, 0);
-    c16 = make_uint4(0, 0, 0, 0);
-    if (v < kConvPer / 16 && b0 + 16 <= N) {
-      f16 = *reinterpret_cast<const uint4*>(d.flags + b0);
-      if (update) c16 = *reinterpret_cast<const uint4*>(d.cand + b0);
-    }
-  };
-  uint4 nf16, nc16;
-  load16(0, nf16, nc16);
-#pragma unroll 1
-  for (int v = 0; v < kConvPer / 16; ++v) {
-    const int64_t b0 = base + 16 * v;
-    union V16 {
-      uint4 v;
-      uint8_t b[16];
-    } fl, cand;
-    const bool full = b0 + 16 <= N;
-    fl.v = nf16;
-    cand.v = nc16;
-    load16(v + 1, nf16, nc16);
-    if (!full) {
-      for (int j = 0; j < 16 && b0 + j < N; ++j) {
-        fl.b[j] = d.flags[b0 + j];
-        if (update) cand.b[j] = d.cand[b0 + j];
-      }
-    }
-    bool changed = false, any_cand = false;
+// Counts of the four lists over the cells [b, e) of one thread, vectors of
+// 16 flag bytes (b is a multiple of 64). Chunks are the 64-cell blocks of the
+// range that hold a liquid cell away from walls.
+struct ListCounts {
+  uint32_t n[4];  // interface, converted, chunks, COMPLEX liquid
+};
+
+__device__ __forceinline__ uint32_t mask_of(const uint4& v, int64_t b0, int64_t N, int which) {
+  union {
+    uint4 v;
+    uint8_t b[16];
+  } u;
+  u.v = v;
+  uint32_t m = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      if (b0 + j >= N) break;
-      const uint8_t f0 = fl.b[j];
-      uint8_t nf = f0 & (uint8_t)~F_TRANSIENT;
-      if (cand.b[j]) {
-        any_cand = true;
-        nf = new_flags<Q>(d, b0 + j, f0);
-      }
-      changed |= (nf != f0);
-      fl.b[j] = nf;
-      const uint64_t bit = 1ull << (16 * v + j);
-      if ((nf & T_MASK) == T_IF) mif |= bit;
-      if (nf & F_CONV) mcv |= bit;
-      if ((nf & (T_MASK | F_COMPLEX)) == (T_LIQ | F_COMPLEX)) mgn |= bit;
-      if ((nf & (T_MASK | F_COMPLEX)) == T_LIQ) mlq |= bit;
-    }
-    if (changed) {
-      if (full) {
-        *reinterpret_cast<uint4*>(d.flags + b0) = fl.v;
-      } else {
-        for (int j = 0; j < 16 && b0 + j < N; ++j) d.flags[b0 + j] = fl.b[j];
-      }
-    }
-    if (any_cand) {
-      if (full) {
-        *reinterpret_cast<uint4*>(d.cand + b0) = make_uint4(0, 0, 0, 0);
-      } else {
-        for (int j = 0; j < 16 && b0 + j < N; ++j) d.cand[b0 + j] = 0;
-      }
-    }
+  for (int j = 0; j < 16; ++j) {
+    const uint8_t f = u.b[j];
+    bool hit;
+    if (which == 0) hit = (f & T_MASK) == T_IF;
+    else if (which == 1) hit = (f & F_CONV) != 0;
+    else if (which == 2) hit = (f & (T_MASK | F_COMPLEX)) == T_LIQ;
+    else hit = (f & (T_MASK | F_COMPLEX)) == (T_LIQ | F_COMPLEX);
+    if (hit && b0 + j < N) m |= 1u << j;
   }
-  const uint32_t cch = mlq ? 1u : 0u;  // this thread's cells are one chunk
-  const uint32_t cnts[4] = {(uint32_t)__popcll(mif), (uint32_t)__popcll(mcv), cch,
-                            (uint32_t)__popcll(mgn)};
-  uint32_t pre[4], tot[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) pre[i] = block_excl_scan(cnts[i], s_scan[i], &tot[i]);
-  if (threadIdx.x == 0 && update) d.tile_dirty[tile] = 0;
-  {
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    unsigned long long* st =
-        wv == 0 ? d.scan_if : (wv == 1 ? d.scan_cv : (wv == 2 ? d.scan_ch : d.scan_gen));
-    const uint32_t e = lookback_wave(st, tile, tot[wv], epoch, &d.cnt[CNT_ERR]);
-    if (lane == 0) s_excl[wv] = e;
-  }
-  __syncthreads();
-  uint32_t o0 = s_excl[0] + pre[0], o1 = s_excl[1] + pre[1], o3 = s_excl[3] + pre[3];
-  for (uint64_t m = mif; m; m &= m - 1) d.if_list[o0++] = (int32_t)(base + __builtin_ctzll(m));
-  for (uint64_t m = mcv; m; m &= m - 1) d.conv_list[o1++] = (int32_t)(base + __builtin_ctzll(m));
-  for (uint64_t m = mgn; m; m &= m - 1) d.gen_list[o3++] = (int32_t)(base + __builtin_ctzll(m));
-  if (cch) d.chunk_list[s_excl[2] + pre[2]] = (int32_t)(base / 64);
-  if (tile == (int)gridDim.x - 1 && threadIdx.x == kBlock - 1) {
-    d.cnt[CNT_IF] = (int32_t)o0;
-    d.cnt[CNT_CONV] = (int32_t)o1;
-    d.cnt[CNT_GEN] = (int32_t)o3;
-    d.cnt[CNT_CHUNKS] = (int32_t)(s_excl[2] + pre[2] + cch);
-  }
+  return m;
 }
 
-// ---------------------------------------------------------------------------
-// k_finish: list-driven completion of the conversion.
-// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 load_flags16(const uint8_t* flags, int64_t b0, int64_t N) {
+  if (b0 + 16 <= N) return *reinterpret_cast<const uint4*>(flags + b0);
+  union {
+    uint4 v;
+    uint8_t b[16];
+  } u;
+  u.v = make_uint4(0, 0, 0, 0);
+  for (int j = 0; j < 16; ++j)
+    if (b0 + j < N) u.b[j] = flags[b0 + j];
+  return u.v;
+}
+
+// A converted cell z (Sec. 2.2): its excess mass (m - rho when filled, m when
+// emptied) is split in equal shares over its interface neighbours of the new
+// types (k_finish adds them); with no interface neighbour it is booked as lost.
+// Its mark is cleared and its fill level set to 1 or 0.
 template <int Q>
-__device__ __forceinline__ int count_if_nb(const Dev& d, int64_t z) {
+__device__ __forceinline__ void finish_converted(const Dev& d, int64_t z) {
   int x, y, zz;
   coords(d.g, z, x, y, zz);
-  int n = 0;
-#pragma unroll 1
+  // every load is issued unconditionally (a wall neighbour reads the cell
+  // itself and is then ignored), so the q-1 loads share one round trip
+  uint8_t t[Q];
+#pragma unroll
   for (int k = 1; k < Q; ++k) {
     int w;
-    int64_t j = nb_index(d.g, x, y, zz, kCX[k], kCY[k], kCZ[k], &w);
-    if (j >= 0 && (d.flags[j] & T_MASK) == T_IF) ++n;
+    const int64_t j = nb_index(d.g, x, y, zz, kCX[k], kCY[k], kCZ[k], &w);
+    const uint8_t f = d.flags[j >= 0 ? j : z];
+    t[k] = j >= 0 ? (uint8_t)(f & T_MASK) : (uint8_t)T_NOSLIP;
   }
-  return n;
+  const bool liq = (d.flags[z] & T_MASK) == T_LIQ;
+  const double mz = d.m[z], rz = d.rho_if[z];
+  int n = 0;
+#pragma unroll
+  for (int k = 1; k < Q; ++k) n += (t[k] == T_IF) ? 1 : 0;
+  const double excess = liq ? mz - rz : mz;
+  if (n == 0)
+    d.lost[z] += excess;
+  else
+    d.xs[z] = excess / (double)n;
+  d.mark[z] = MK_NONE;
+  d.phiA[z] = liq ? 1.0 : 0.0;
+  d.phiB[z] = liq ? 1.0 : 0.0;
 }
 
-// Excess mass of a converted cell (Sec. 2.2): m - rho when filled, m when emptied.
-__device__ __forceinline__ double excess_of(const Dev& d, int64_t z) {
-  const int t = d.flags[z] & T_MASK;
-  return t == T_LIQ ? d.m[z] - d.rho_if[z] : d.m[z];
-}
-
-// Completion of one interface cell of the new list by a group of 32 lanes,
-// lane k looking at the neighbour x + c_k.
+// A new interface cell c from gas (Sec. 2.2), by a group of 32 lanes, lane k
+// looking at the neighbour x + c_k: the equilibrium of the mean density and
+// velocity of its liquid and old interface neighbours (post-collision moments
+// of this step), then the collision of this step; m = 0 (shares of converted
+// neighbours are added by k_finish).
 template <int S, int Q, bool TRT>
-__device__ __forceinline__ void finish_interface(const Dev& d, int64_t c, int l,
-                                                 bool classes_only) {
+__device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) {
   using St = Store<S, Q>;
   using T = typename St::T;
   using R = typename St::R;
@@ -790,106 +736,330 @@ __device__ __forceinline__ void finish_interface(const Dev& d, int64_t c, int l,
   const int k = act ? l : 0;
   int x, y, z;
   coords(g, c, x, y, z);
-  int w;
   int64_t j = -1;
   uint8_t fj = 0;
   if (act && l > 0) {
+    int w;
     j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
     if (j >= 0) fj = d.flags[j];
   }
-  const int tj = j >= 0 ? (fj & T_MASK) : -1;
-  const bool has_liq = gballot(tj == T_LIQ) != 0u;
-  const bool has_gas = gballot(tj == T_GAS) != 0u;
-  const uint8_t cls = (!has_liq && has_gas) ? CLS_NOLIQ : ((!has_gas && has_liq) ? CLS_NOGAS : CLS_STD);
-  if (classes_only) {
-    if (l == 0) d.cls[c] = cls;
-    return;
-  }
-  const uint8_t fl = d.flags[c];
-  double mass, rho_n;
-  if (fl & F_NEW_GAS) {
-    // equilibrium of the mean density and velocity of the liquid and old
-    // interface neighbours (Sec. 2.2), then the collision of this step
-    const bool use = j >= 0 && is_fluid(tj) && !(fj & F_NEW_GAS);
-    R r = R(0), a = R(0), b = R(0), cc = R(0);
-    if (use) {
-      R fj_[Q];
+  const bool use = j >= 0 && is_fluid(fj & T_MASK) && !(fj & F_NEW_GAS);
+  R r = R(0), a = R(0), b = R(0), cc = R(0);
+  if (use) {
+    R fn[Q];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) fj_[i] = St::ld(B, i * stride + j, i);
-      post_moments<R, Q, SH>(fj_, R(d.gx), R(d.gy), R(d.gz), r, a, b, cc);
-    }
-    const int cnt = __popc(gballot(use));
-    const R rb = gsum(r, Q) / R(cnt);
-    const R ub0 = gsum(a, Q) / R(cnt), ub1 = gsum(b, Q) / R(cnt), ub2 = gsum(cc, Q) / R(cnt);
-    const R usq = ub0 * ub0 + ub1 * ub1 + ub2 * ub2;
-    const R fe = feq_k<R, Q, SH>(k, rb, rb - R(1), cdot<R>(kCX[k], kCY[k], kCZ[k], ub0, ub1, ub2),
-                                 usq);
-    CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
-    R rr, vx, vy, vz;
-    const R fs = gcollide<R, Q, TRT, SH>(fe, l, cp, rr, vx, vy, vz);
-    if (act) St::st(B, k * stride + c, k, fs);
-    mass = 0.0;
-    rho_n = (double)rb;
-  } else if (fl & F_NEW_LIQ) {
-    const R fc = act ? St::ld(B, k * stride + c, k) : R(0);
-    rho_n = (SH ? 1.0 : 0.0) + gsum(act ? (double)fc : 0.0, Q);
-    mass = rho_n;
-  } else {
-    mass = d.m[c];
-    rho_n = d.rho_if[c];
+    for (int i = 0; i < Q; ++i) fn[i] = St::ld(B, i * stride + j, i);
+    post_moments<R, Q, SH>(fn, R(d.gx), R(d.gy), R(d.gz), r, a, b, cc);
   }
-  // excess mass of converted neighbours: equal shares over their interface
-  // neighbours (Sec. 2.2), added in direction order
-  double share = 0.0;
-  if (j >= 0 && (fj & F_CONV)) share = excess_of(d, j) / (double)count_if_nb<Q>(d, j);
-  for (int i = 1; i < Q; ++i) {
-    const double si = __shfl(share, i, kG);
-    if (__shfl((int)((fj & F_CONV) != 0), i, kG)) mass += si;
-  }
+  const int cnt = __popc(gballot(use));
+  const R rb = gsum(r, Q) / R(cnt);
+  const R ub0 = gsum(a, Q) / R(cnt), ub1 = gsum(b, Q) / R(cnt), ub2 = gsum(cc, Q) / R(cnt);
+  const R usq = ub0 * ub0 + ub1 * ub1 + ub2 * ub2;
+  const R fe = feq_k<R, Q, SH>(k, rb, rb - R(1), cdot<R>(kCX[k], kCY[k], kCZ[k], ub0, ub1, ub2), usq);
+  CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
+  R rr, vx, vy, vz;
+  const R fs = gcollide<R, Q, TRT, SH>(fe, l, cp, rr, vx, vy, vz);
+  if (act) St::st(B, k * stride + c, k, fs);
   if (l == 0) {
-    d.m[c] = mass;
-    d.rho_if[c] = rho_n;
-    d.phiB[c] = mass / rho_n;
-    d.cls[c] = cls;
+    d.m[c] = 0.0;
+    d.rho_if[c] = (double)rb;
   }
 }
 
-template <int Q>
-__device__ __forceinline__ void finish_converted(const Dev& d, int64_t z, int l) {
-  const bool act = l < Q;
-  int x, y, zz;
-  coords(d.g, z, x, y, zz);
-  bool nbif = false;
-  if (act && l > 0) {
+// Tile status: two 64-bit words per tile, [epoch:16 | count:24 | count:24],
+// written once per compaction by the tile and read by every later tile.
+__device__ __forceinline__ unsigned long long pack2(uint32_t epoch, uint32_t a, uint32_t b) {
+  return ((unsigned long long)(epoch & 0xffffu) << 48) | ((unsigned long long)(a & 0xffffffu) << 24) |
+         (unsigned long long)(b & 0xffffffu);
+}
+
+// List compaction. A tile is 256 threads times `per` cells (per = 16 times a
+// power of two, chosen by the host so that there are at most kMaxTiles
+// tiles); thread t owns the cells [per t, per t + per) of the tile, read as
+// 16-byte vectors. The interface list, the converted list, the chunk list
+// (64-cell chunks with liquid cells away from walls) and the list of COMPLEX
+// liquid cells are compacted in ascending cell order in one pass: each tile
+// publishes its four counts at once, then sums the published counts of all
+// earlier tiles (whole block, one load round; a tile's ticket is taken in
+// launch order, so its predecessors are already running) and writes its
+// entries at the resulting offsets. The status words carry the compaction's
+// epoch, so they never need clearing; their only payload is the counts
+// themselves, so relaxed device-scope atomics suffice. The wait for a
+// predecessor is bounded: on expiry the scan error bit is set and the kernel
+// completes (with a wrong list, reported by the host). Skipped in a step
+// without marks (the lists are unchanged then).
+// The first `workers` blocks do the other work that k_finish waits for.
+template <int S, int Q, bool TRT>
+__global__ __launch_bounds__(kBlock) void k_compact(Dev d, int rebuild_only, int per, int workers) {
+  __shared__ int s_tile, s_run;
+  __shared__ uint32_t s_epoch;
+  __shared__ uint32_t s_scan[4][kBlock / 64];
+  __shared__ uint32_t s_red[4][kBlock / 64];
+  if ((int)blockIdx.x < workers) {
+    // worker blocks, beside the compaction: the converted cells (the marked
+    // cells that carry the converted bit) get their excess-mass share, the new
+    // interface cells from gas their reinitialisation
+    if (rebuild_only) return;
+    const int nmk = d.cnt[CNT_MARK0 + (d.step & 1)];
+    const int nng = d.cnt[CNT_NG];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nmk; i += workers * kBlock) {
+      const int64_t zc = d.mark_list[i];
+      if (d.flags[zc] & F_CONV) finish_converted<Q>(d, zc);
+    }
+    const int l = threadIdx.x & (kG - 1);
+    const int ngroups = workers * (kBlock / kG);
+    for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < nng; item += ngroups)
+      reinit_from_gas<S, Q, TRT>(d, d.ng_list[item], l);
+    return;
+  }
+  if (threadIdx.x == 0) {
+    // the mark count, the epoch and the ticket in one round trip (a ticket
+    // taken in a step without marks is harmless: the counter is reset before
+    // every compaction launch)
+    const int run = rebuild_only ? 1 : d.cnt[CNT_MARK0 + (d.step & 1)];
+    const uint32_t ep = (uint32_t)d.cnt[CNT_EPOCH];
+    s_tile = atomicAdd(&d.cnt[CNT_TICKET], 1);
+    s_run = run;
+    s_epoch = ep;
+  }
+  __syncthreads();
+  if (s_run == 0) return;
+  const int tile = s_tile;
+  const uint32_t epoch = s_epoch;
+  const int64_t N = d.g.N;
+  const int64_t base = ((int64_t)tile * kBlock + threadIdx.x) * per;
+  const int nvec = per / 16;
+  // threads per 64-cell chunk (per < 64), else chunks per thread
+  const int tpc = per < 64 ? 64 / per : 1;
+  // pass 1: masks and counts, in batches of kBatch 16-byte vectors requested
+  // together; the masks of the first batch are kept for pass 2
+  constexpr int kBatch = 8;
+  uint32_t keep[4][kBatch];
+  uint32_t c[4] = {0, 0, 0, 0};
+  uint32_t own_any = 0;
+  {
+    uint32_t chunk_any = 0;
+#pragma unroll 1
+    for (int v0 = 0; v0 < nvec; v0 += kBatch) {
+      uint4 vec[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int64_t b0 = base + 16 * (v0 + u);
+        vec[u] = (v0 + u < nvec && b0 < N) ? load_flags16(d.flags, b0, N) : make_uint4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int64_t b0 = base + 16 * (v0 + u);
+        uint32_t m[4] = {0, 0, 0, 0};
+        if (v0 + u < nvec && b0 < N) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) m[i] = mask_of(vec[u], b0, N, i);
+        }
+        if (v0 == 0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) keep[i][u] = m[i];
+        }
+        c[0] += __popc(m[0]);
+        c[1] += __popc(m[1]);
+        c[3] += __popc(m[3]);
+        own_any |= m[2];
+        chunk_any |= m[2];
+        if (per >= 64 && (u & 3) == 3) {
+          c[2] += chunk_any ? 1u : 0u;
+          chunk_any = 0;
+        }
+      }
+    }
+  }
+  // chunk count: a chunk shared by tpc threads is counted by the first
+  uint32_t lead_any = own_any ? 1u : 0u;
+  if (per < 64) {
+    if (tpc >= 2) lead_any |= __shfl_xor(lead_any, 1, 64);
+    if (tpc >= 4) lead_any |= __shfl_xor(lead_any, 2, 64);
+    c[2] = ((threadIdx.x % tpc) == 0) ? lead_any : 0u;
+  }
+  uint32_t pre[4], tot[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) pre[i] = block_excl_scan(c[i], s_scan[i], &tot[i]);
+  unsigned long long* st = d.scan_status;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&st[2 * tile], pack2(epoch, tot[0], tot[1]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st[2 * tile + 1], pack2(epoch, tot[2], tot[3]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // sum of the counts of all earlier tiles
+  uint32_t acc[4] = {0, 0, 0, 0};
+  for (int t = threadIdx.x; t < tile; t += kBlock) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      unsigned long long v;
+      int spins = 0;
+      for (;;) {
+        v = __hip_atomic_load(&st[2 * t + h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 48) == (epoch & 0xffffu)) break;
+        if (++spins > (1 << 22)) {
+          atomicOr(&d.cnt[CNT_ERR], ERR_SCAN);
+          v = 0;
+          break;
+        }
+        if (spins > 64) __builtin_amdgcn_s_sleep(1);
+      }
+      acc[2 * h] += (uint32_t)(v >> 24) & 0xffffffu;
+      acc[2 * h + 1] += (uint32_t)v & 0xffffffu;
+    }
+  }
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint32_t x = acc[i];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) s_red[i][wv] = x;
+    }
+  }
+  __syncthreads();
+  uint32_t off[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    uint32_t e = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) e += s_red[i][w];
+    off[i] = e + pre[i];
+  }
+  const uint32_t chunks_end = off[2] + c[2];
+  // pass 2: the entries, in ascending order (masks of the first batch kept,
+  // later batches reloaded: the flags are still in cache)
+  {
+    uint32_t chunk_any = 0;
+#pragma unroll 1
+    for (int v0 = 0; v0 < nvec; v0 += kBatch) {
+      uint32_t m[4][kBatch];
+      if (v0 == 0) {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) m[i][u] = keep[i][u];
+      } else {
+        uint4 vec[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const int64_t b0 = base + 16 * (v0 + u);
+          vec[u] = (v0 + u < nvec && b0 < N) ? load_flags16(d.flags, b0, N) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const int64_t b0 = base + 16 * (v0 + u);
+          const bool in = v0 + u < nvec && b0 < N;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) m[i][u] = in ? mask_of(vec[u], b0, N, i) : 0u;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int64_t b0 = base + 16 * (v0 + u);
+        if (v0 + u >= nvec || b0 >= N) break;
+        for (uint32_t mm = m[0][u]; mm; mm &= mm - 1) d.if_list[off[0]++] = (int32_t)(b0 + __builtin_ctz(mm));
+        for (uint32_t mm = m[1][u]; mm; mm &= mm - 1) d.conv_list[off[1]++] = (int32_t)(b0 + __builtin_ctz(mm));
+        for (uint32_t mm = m[3][u]; mm; mm &= mm - 1) d.gen_list[off[3]++] = (int32_t)(b0 + __builtin_ctz(mm));
+        if (per >= 64) {
+          chunk_any |= m[2][u];
+          if ((u & 3) == 3 || b0 + 16 >= N) {
+            if (chunk_any) d.chunk_list[off[2]++] = (int32_t)(b0 / 64);
+            chunk_any = 0;
+          }
+        }
+      }
+    }
+  }
+  if (per < 64 && c[2]) d.chunk_list[off[2]] = (int32_t)(base / 64);
+  if (tile == (int)gridDim.x - workers - 1 && threadIdx.x == kBlock - 1) {
+    d.cnt[CNT_IF] = (int32_t)off[0];
+    d.cnt[CNT_CONV] = (int32_t)off[1];
+    d.cnt[CNT_GEN] = (int32_t)off[3];
+    d.cnt[CNT_CHUNKS] = (int32_t)chunks_end;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_finish: list-driven completion of the conversion, one thread per cell of
+// the new interface list.
+// ---------------------------------------------------------------------------
+template <int S, int Q, bool TRT>
+__device__ __forceinline__ void finish_interface(const Dev& d, int64_t c, bool classes_only) {
+  using St = Store<S, Q>;
+  using T = typename St::T;
+  using R = typename St::R;
+  constexpr bool SH = St::kShift;
+  T* B = static_cast<T*>(d.fB);
+  const Geom& g = d.g;
+  const int64_t stride = g.stride;
+  int x, y, z;
+  coords(g, c, x, y, z);
+  // neighbour indices and flags, all loads issued before the first use
+  // (unconditional loads: a wall neighbour reads the cell itself and is then
+  // ignored, so the loads share one round trip)
+  int64_t jn[Q];
+  uint8_t fn[Q];
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
     int w;
-    const int64_t j = nb_index(d.g, x, y, zz, kCX[l], kCY[l], kCZ[l], &w);
-    nbif = j >= 0 && (d.flags[j] & T_MASK) == T_IF;
+    jn[k] = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
+    const uint8_t f = d.flags[jn[k] >= 0 ? jn[k] : c];
+    fn[k] = jn[k] >= 0 ? f : (uint8_t)T_NOSLIP;
   }
-  const int nif = __popc(gballot(nbif));
-  if (l == 0) {
-    const int t = d.flags[z] & T_MASK;
-    if (nif == 0) d.lost[z] += excess_of(d, z);
-    d.mark[z] = MK_NONE;
-    const double v = (t == T_LIQ) ? 1.0 : 0.0;
-    d.phiA[z] = v;
-    d.phiB[z] = v;
+  const uint8_t fl = classes_only ? (uint8_t)0 : d.flags[c];
+  const double m_old = classes_only ? 0.0 : d.m[c];
+  const double r_old = classes_only ? 0.0 : d.rho_if[c];
+  bool has_liq = false, has_gas = false, any_conv = false;
+#pragma unroll
+  for (int k = 1; k < Q; ++k) {
+    const int t = fn[k] & T_MASK;
+    has_liq |= t == T_LIQ;
+    has_gas |= t == T_GAS;
+    any_conv |= (fn[k] & F_CONV) != 0;
   }
+  const uint8_t cls = (!has_liq && has_gas) ? CLS_NOLIQ : ((!has_gas && has_liq) ? CLS_NOGAS : CLS_STD);
+  d.cls[c] = cls;
+  if (classes_only) return;
+  if (!(fl & (F_NEW_GAS | F_NEW_LIQ)) && !any_conv) return;  // mass and fill level unchanged
+  // (a new interface cell from gas was reinitialised by the compaction kernel:
+  // m = 0 and rho_if = the reinitialisation density)
+  double mass, rho_n;
+  if (fl & F_NEW_LIQ) {
+    double r = 0.0;
+    R fc[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) fc[k] = St::ld(B, k * stride + c, k);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) r += (double)fc[k];
+    rho_n = (SH ? 1.0 : 0.0) + r;
+    mass = rho_n;
+  } else {
+    mass = m_old;
+    rho_n = r_old;
+  }
+  // excess mass of converted neighbours: their equal shares (Sec. 2.2), added
+  // in direction order
+  // (directions without a converted neighbour read the cell's own entry, one
+  // cache line, so that all loads are issued together)
+  double sh[Q];
+#pragma unroll
+  for (int k = 1; k < Q; ++k) sh[k] = d.xs[(fn[k] & F_CONV) ? jn[k] : c];
+#pragma unroll
+  for (int k = 1; k < Q; ++k)
+    if (fn[k] & F_CONV) mass += sh[k];
+  d.m[c] = mass;
+  d.rho_if[c] = rho_n;
+  d.phiB[c] = mass / rho_n;
 }
 
 template <int S, int Q, bool TRT>
 __global__ __launch_bounds__(kBlock) void k_finish(Dev d, int classes_only) {
   if (!classes_only && d.cnt[CNT_MARK0 + (d.step & 1)] == 0) return;
   const int nif = d.cnt[CNT_IF];
-  const int ncv = classes_only ? 0 : d.cnt[CNT_CONV];
-  const int total = nif + ncv;
-  const int l = threadIdx.x & (kG - 1);
-  const int ngroups = gridDim.x * (kBlock / kG);
-  for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < total; item += ngroups) {
-    if (item < nif)
-      finish_interface<S, Q, TRT>(d, d.if_list[item], l, classes_only != 0);
-    else
-      finish_converted<Q>(d, d.conv_list[item - nif], l);
-  }
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nif; i += gridDim.x * kBlock)
+    finish_interface<S, Q, TRT>(d, d.if_list[i], classes_only != 0);
 }
 
 // ---------------------------------------------------------------------------

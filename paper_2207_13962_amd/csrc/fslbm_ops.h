@@ -23,10 +23,10 @@ inline int storage_bytes(int storage) { return storage == FSLBM_F64 ? 8 : (stora
 
 // Device memory layout (one arena, 256-byte aligned sub-buffers).
 struct Layout {
-  int64_t N, stride, tiles, red_blocks;
+  int64_t N, stride, tiles, conv_per, red_blocks;
   size_t off_fA, off_fB, off_flags, off_mark, off_cls, off_phiA, off_phiB, off_m, off_rho_if,
       off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_gen_list,
-      off_tile_dirty, off_cand, off_cnt, off_scan_if, off_scan_cv, off_scan_ch, off_scan_gen,
+      off_mark_list, off_ng_list, off_xs, off_cnt, off_scan_status,
       off_pv, off_partial, off_stage, total;
 };
 
@@ -36,7 +36,10 @@ inline Layout make_layout(const fslbm_params& p) {
   Layout L{};
   L.N = (int64_t)p.nx * p.ny * p.nz;
   L.stride = round_up(L.N, 256);
-  L.tiles = (L.N + kConvTile - 1) / kConvTile;
+  // compaction: cells per thread 16 times a power of two, at most kMaxTiles tiles
+  L.conv_per = 16;
+  while (L.conv_per * kBlock * kMaxTiles < L.N) L.conv_per *= 2;
+  L.tiles = (L.N + kBlock * L.conv_per - 1) / (kBlock * L.conv_per);
   L.red_blocks = (L.N + kRedCells - 1) / kRedCells;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -61,13 +64,11 @@ inline Layout make_layout(const fslbm_params& p) {
   L.off_conv_list = take(4 * L.N);
   L.off_chunk_list = take(4 * (L.N / 64 + 1));
   L.off_gen_list = take(4 * L.N);
-  L.off_tile_dirty = take(L.tiles);
-  L.off_cand = take(L.N + 16);
+  L.off_mark_list = take(4 * L.N);
+  L.off_ng_list = take(4 * L.N);
+  L.off_xs = take(8 * L.N);
   L.off_cnt = take(4 * CNT_N);
-  L.off_scan_if = take(8 * L.tiles);
-  L.off_scan_cv = take(8 * L.tiles);
-  L.off_scan_ch = take(8 * L.tiles);
-  L.off_scan_gen = take(8 * L.tiles);
+  L.off_scan_status = take(16 * L.tiles);
   L.off_pv = take(8 * 8);
   L.off_partial = take(8 * kRedN * L.red_blocks + 8 * 16);
   L.off_stage = take(8 * L.N);
@@ -143,14 +144,24 @@ inline unsigned border_blocks(const fslbm_ctx* c) {
   return (unsigned)std::min<int64_t>(b, 2048);
 }
 
+// list kernels with one cell per 32-lane group: about one group per list
+// entry for typical interface fractions, capped at what 256 CUs hold at the
+// kernels' occupancy (four 256-thread blocks per CU)
 inline unsigned if_blocks(const fslbm_ctx* c) {
   int64_t b = grid_for(c->L.N) / 8 + 64;
-  return (unsigned)std::min<int64_t>(b, 4096);
+  return (unsigned)std::min<int64_t>(b, 1024);
 }
 
+// groups of k_retype: the marks of one step are a small part of the interface
+inline unsigned retype_blocks(const fslbm_ctx* c) {
+  int64_t b = grid_for(c->L.N) / 64 + 16;
+  return (unsigned)std::min<int64_t>(b, 512);
+}
+
+// k_finish: one thread per interface cell
 inline unsigned finish_blocks(const fslbm_ctx* c) {
-  int64_t b = grid_for(c->L.N) / 16 + 64;
-  return (unsigned)std::min<int64_t>(b, 2048);
+  int64_t b = grid_for(c->L.N) / 32 + 16;
+  return (unsigned)std::min<int64_t>(b, 512);
 }
 
 // Kernel table for one (storage, lattice, collision) combination.
@@ -186,8 +197,10 @@ struct Impl {
     hipLaunchKernelGGL((k_generic<S, Q, TRT>), dim3(if_blocks(c)), dim3(kBlock), 0, s, c->d);
   }
   static void convert(fslbm_ctx* c, hipStream_t s, int rebuild) {
-    hipLaunchKernelGGL((k_convert<Q>), dim3((unsigned)c->L.tiles), dim3(kBlock), 0, s, c->d,
-                       rebuild);
+    hipLaunchKernelGGL((k_retype<Q>), dim3(retype_blocks(c)), dim3(kBlock), 0, s, c->d, rebuild);
+    const int workers = rebuild ? 0 : (int)retype_blocks(c);
+    hipLaunchKernelGGL((k_compact<S, Q, TRT>), dim3((unsigned)(c->L.tiles + workers)), dim3(kBlock), 0,
+                       s, c->d, rebuild, (int)c->L.conv_per, workers);
   }
   static void finish(fslbm_ctx* c, hipStream_t s, int classes_only) {
     hipLaunchKernelGGL((k_finish<S, Q, TRT>), dim3(finish_blocks(c)), dim3(kBlock), 0, s, c->d,

@@ -92,6 +92,28 @@ def test_interface_list_sorted_and_complete():
         assert np.array_equal(lst, np.nonzero(t == I.INTERFACE)[0])
 
 
+def test_lists_large_ragged_domain():
+    """A domain of 8.6 M cells (more than 512 compaction tiles of 64 cells per
+    thread, so the tiles grow to 128 cells per thread; N is not a multiple of
+    the tile or of the 64-cell chunk): after conversion-heavy steps the
+    interface list equals the interface cells in ascending order and mass is
+    conserved (a chunk missing from the liquid list would leave its cells
+    unwritten)."""
+    s = I.rect_dam_break(nx=515, ny=130, nz=129, wx=160, hy=100, g=2e-4, nu=2e-3, storage=I.F32,
+                         variant=I.OM)
+    g = _sim(s)
+    m0 = g.mass()["total_mass"]
+    for _ in range(3):
+        g.step(40)
+        r = g.mass()
+        lst = g.interface_list()
+        t = g.fields(pdf=False)["type"]
+        assert np.array_equal(lst, np.nonzero(t == I.INTERFACE)[0])
+        assert r["n_interface"] == lst.size
+        assert abs(r["total_mass"] - m0) / m0 < 1e-6
+    g.close()
+
+
 def test_flat_rest_all_variants():
     for v in VARIANTS:
         for q in (19, 27):
