@@ -16,9 +16,10 @@ same failure mode for NBKC, Sec. 4.2), so a longer window would time NaN
 states. The status of every variant run is reported with the result.
 
 Prints one JSON line: fluid+interface cell updates per second (MLUPS) over the
-timed steps, the roofline of the dominant kernel (the liquid stream-collide
-kernel, HBM bound) from HIP events around its launches, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+timed steps, the roofline of the dominant kernel (the streaming kernel: pull
+streaming, walls, free-surface condition, mass exchange and collision of every
+liquid and interface cell; HBM bound) from HIP events around its launches, and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -34,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 KERNEL_SOURCES = ["paper_2207_13962_amd/csrc/fslbm_kernels.h", "paper_2207_13962_amd/csrc/fslbm_device.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_liquid_dam256_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_dam256_traffic.txt")
 
 
 def kernel_source_hash():
@@ -45,7 +46,7 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per launch of the liquid kernel from the committed rocprofv3
+    """HBM bytes per launch of the streaming kernel from the committed rocprofv3
     counter summary, or None if it is missing or was taken on other kernel code."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -63,8 +64,9 @@ def measured_traffic():
 
 
 def bytes_per_update(q, storage_bytes):
-    """Algorithmic bytes of one liquid cell update: read q populations, write q
-    populations, read the cell's flag byte."""
+    """Algorithmic bytes of one fluid cell update: read q populations, write q
+    populations, read the cell's flag byte (interface cells move a few more
+    bytes - mass, fill level, mark - which are not counted)."""
     return 2 * q * storage_bytes + 1
 
 
@@ -89,18 +91,18 @@ def _counter_rows(path, counter, kernel_prefix):
 def write_traffic(fetch_csv, write_csv, last, command):
     """Turns two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of the
     benchmark into the traffic summary read back by measured_traffic(): the
-    mean over the last `last` liquid-kernel dispatches (the kernel-timing
+    mean over the last `last` streaming-kernel dispatches (the kernel-timing
     region of the benchmark)."""
-    fe = _counter_rows(fetch_csv, "FETCH_SIZE", "void fslbm::k_liquid<")
-    wr = _counter_rows(write_csv, "WRITE_SIZE", "void fslbm::k_liquid<")
+    fe = _counter_rows(fetch_csv, "FETCH_SIZE", "void fslbm::k_stream<")
+    wr = _counter_rows(write_csv, "WRITE_SIZE", "void fslbm::k_stream<")
     if not fe or not wr:
-        raise SystemExit("no k_liquid dispatches in the counter files")
+        raise SystemExit("no k_stream dispatches in the counter files")
     fe, wr = fe[-last:], wr[-last:]
     f_kib = sum(fe) / len(fe)
     w_kib = sum(wr) / len(wr)
     hbm = FETCH_SCALE * 1024 * f_kib + WRITE_SCALE * 1024 * w_kib
     with open(TRAFFIC_FILE, "w") as fh:
-        fh.write("# HBM traffic of the liquid stream-collide kernel (k_liquid), dam256 workload\n")
+        fh.write("# HBM traffic of the streaming kernel (k_stream), dam256 workload\n")
         fh.write("# commands (FETCH_SIZE run, then WRITE_SIZE run):\n")
         for c in command:
             fh.write("#   %s\n" % c)
@@ -198,8 +200,8 @@ def main():
         stream.synchronize()
         ms = ev0.elapsed_time(ev1)
         after = [s.mass(check=False) for s in sims]
-        # dominant kernel: the liquid stream-collide launches of a second timed
-        # region, each launch recording its own start/stop timestamps
+        # dominant kernel: the streaming launches of a second timed region,
+        # each launch recording its own start/stop timestamps
         ksteps = min(args.steps, args.kernel_steps)
         for s in sims:
             s.set_timing(ksteps)
@@ -214,8 +216,8 @@ def main():
             n, t = s.kernel_time()
             launches += n
             kms += t
-            nliq = 0.5 * (b["n_liquid"] + a["n_liquid"])
-            liq_bytes += n * nliq * bytes_per_update(p.q, sb)
+            nfl = 0.5 * (b["n_liquid"] + b["n_interface"] + a["n_liquid"] + a["n_interface"])
+            liq_bytes += n * nfl * bytes_per_update(p.q, sb)
             s.set_timing(0)
     # fluid+interface updates: average of the counts before and after the window
     updates = 0.0
@@ -271,7 +273,10 @@ def main():
             "per_variant": per_variant,
         },
         "roofline": {
-            "kernel": "k_liquid (pull stream + walls + TRT collision%s)" % (" + LES" if args.les else ""),
+            "kernel": "k_stream (pull streaming, walls, free-surface condition, mass exchange, TRT%s "
+                      "collision; all fluid cells)" % (" + LES" if args.les else ""),
+            "bytes_model": "%d B per fluid cell update (read and write %d populations of %d B, one flag byte)"
+                           % (bytes_per_update(p.q, sb), p.q, sb),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

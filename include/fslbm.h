@@ -138,8 +138,9 @@ int fslbm_fields(fslbm_ctx* ctx, uint8_t* type, double* phi, double* rho, double
 int fslbm_interface_list(fslbm_ctx* ctx, int32_t* list, int64_t max, int64_t* count);
 
 /* Kernel timing for measurement. fslbm_set_timing(ctx, capacity) with
- * capacity > 0 brackets the next `capacity` launches of the liquid
- * stream-collide kernel with HIP events on the context's stream (capacity 0
+ * capacity > 0 brackets the next `capacity` launches of the streaming kernel
+ * (pull streaming, free-surface condition, mass exchange and collision of
+ * every liquid and interface cell) with HIP events on the context's stream (capacity 0
  * turns timing off and releases the events). fslbm_kernel_time syncs and
  * returns the number of timed launches and their summed duration in ms.
  * Errors: FSLBM_EINVAL (NULL, capacity < 0), FSLBM_EDEVICE. */

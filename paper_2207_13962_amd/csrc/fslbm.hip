@@ -61,7 +61,11 @@ void bind(fslbm_ctx* c) {
   d.g.nx = c->p.nx;
   d.g.ny = c->p.ny;
   d.g.nz = c->p.nz;
-  for (int f = 0; f < 6; ++f) d.g.bnd[f] = c->p.boundary[f];
+  d.g.bnd_bits = 0;
+  for (int f = 0; f < 6; ++f) {
+    d.g.bnd[f] = c->p.boundary[f];
+    d.g.bnd_bits |= (uint32_t)c->p.boundary[f] << (2 * f);
+  }
   d.g.N = L.N;
   d.g.stride = L.stride;
   const double tau = c->p.tau;
@@ -153,7 +157,7 @@ void drop_graph(fslbm_ctx* c) {
 
 // Steps go to the stream as a replayed graph of kGraphSteps steps where
 // possible (one launch instead of ~5 per step), the rest as plain launches.
-// Timing runs (events per liquid launch) always use plain launches.
+// Timing runs (events per streaming launch) always use plain launches.
 int enqueue_steps(fslbm_ctx* c, int64_t n) {
   hipStream_t s = c->stream;
   const bool use_graph = c->graphs && c->ev.empty() && s != nullptr;
@@ -249,6 +253,13 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
     c->own_arena = true;
   }
   bind(c);
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      c->cus = cus;
+    (void)hipGetLastError();
+  }
   const Ops ops = pick(c->p);
   hipStream_t s = c->stream;
   const int64_t N = c->L.N;

@@ -23,6 +23,11 @@ constexpr int kCY[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 
 constexpr int kCZ[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
                          1, -1, -1, 1, 1, -1, 1, -1};
 
+// Components of direction k (k may be a run-time value).
+__host__ __device__ constexpr int cxd(int k) { return kCX[k]; }
+__host__ __device__ constexpr int cyd(int k) { return kCY[k]; }
+__host__ __device__ constexpr int czd(int k) { return kCZ[k]; }
+
 __host__ __device__ constexpr int opp(int k) { return k == 0 ? 0 : ((k & 1) ? k + 1 : k - 1); }
 
 template <int Q>
@@ -71,8 +76,7 @@ enum {
   CNT_EPOCH = 6,   // epoch of the compaction scan (advanced before every compaction)
   CNT_CHUNKS = 7,  // 64-cell chunks holding at least one liquid cell
   CNT_GEN = 8,     // liquid cells next to the domain boundary or an obstacle
-  CNT_CONVP = 9,   // converted cells of the previous conversion (transient bits to clear)
-  CNT_NG = 10,     // new interface cells from gas in this step
+  CNT_NG = 9,      // new interface cells from gas in this step
   CNT_N = 12
 };
 enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8 };
@@ -158,9 +162,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
 struct Geom {
   int nx, ny, nz;
   int bnd[6];
+  uint32_t bnd_bits;  // bnd[f] in bits 2f, 2f+1
   int64_t N;       // nx*ny*nz
   int64_t stride;  // distance between population planes (>= N)
 };
+
+// Boundary kind of a face with a run-time face index, from the packed copy
+// (an indexed load from bnd[] would make the whole kernel-argument block a
+// private array).
+__device__ __forceinline__ int face_kind(const Geom& g, int face) {
+  return (int)((g.bnd_bits >> (2 * face)) & 3u);
+}
 
 // Cell coordinates; domains hold fewer than 2^30 cells, so 32-bit unsigned
 // arithmetic suffices.
@@ -189,7 +201,7 @@ __device__ __forceinline__ int64_t nb_index(const Geom& g, int x, int y, int z, 
     else if (c[a] >= n[a])
       face = 2 * a + 1;
     if (face < 0) continue;
-    int b = g.bnd[face];
+    const int b = face_kind(g, face);
     if (b == BND_PERIODIC) {
       int m = c[a] % n[a];
       c[a] = m < 0 ? m + n[a] : m;
@@ -224,7 +236,7 @@ enum { SRC_FLUID = 0, SRC_GAS = 1, SRC_BOUNCE = 2 };
 template <int Q>
 __device__ __forceinline__ int reflect_source(const Geom& g, const uint8_t* flags, int x, int y, int z,
                                            int k, int64_t* src, int* dir) {
-  const int c[3] = {kCX[k], kCY[k], kCZ[k]};
+  const int c[3] = {cxd(k), cyd(k), czd(k)};
   int d[3] = {-c[0], -c[1], -c[2]};
   int cj[3] = {c[0], c[1], c[2]};
   bool any = false;
@@ -247,7 +259,7 @@ __device__ __forceinline__ int reflect_source(const Geom& g, const uint8_t* flag
   *src = yi;
   int r = 0;
   for (int i = 0; i < Q; ++i)
-    if (kCX[i] == cj[0] && kCY[i] == cj[1] && kCZ[i] == cj[2]) r = i;
+    if (cxd(i) == cj[0] && cyd(i) == cj[1] && czd(i) == cj[2]) r = i;
   *dir = r;
   return SRC_FLUID;
 }
@@ -256,7 +268,7 @@ template <int Q>
 __device__ __forceinline__ int resolve_source(const Geom& g, const uint8_t* flags, int x, int y,
                                               int z, int k, int64_t* src, int* dir, bool* wall) {
   int64_t j;
-  int st = nb_type(g, flags, x, y, z, -kCX[k], -kCY[k], -kCZ[k], &j);
+  int st = nb_type(g, flags, x, y, z, -cxd(k), -cyd(k), -czd(k), &j);
   *dir = k;
   *src = j;
   *wall = is_obst(st);
@@ -308,12 +320,12 @@ __device__ __forceinline__ void moments(const R* f, R gx, R gy, R gz, R& rho, R&
   for (int k = 0; k < Q; ++k) r += f[k];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    if (kCX[k] > 0) j0 += f[k];
-    if (kCX[k] < 0) j0 += -f[k];
-    if (kCY[k] > 0) j1 += f[k];
-    if (kCY[k] < 0) j1 += -f[k];
-    if (kCZ[k] > 0) j2 += f[k];
-    if (kCZ[k] < 0) j2 += -f[k];
+    if (cxd(k) > 0) j0 += f[k];
+    if (cxd(k) < 0) j0 += -f[k];
+    if (cyd(k) > 0) j1 += f[k];
+    if (cyd(k) < 0) j1 += -f[k];
+    if (czd(k) > 0) j2 += f[k];
+    if (czd(k) < 0) j2 += -f[k];
   }
   // shifted values: sum h = rho - 1 (the weights sum to one, their first
   // moment vanishes)
@@ -334,12 +346,12 @@ __device__ __forceinline__ void post_moments(const R* fs, R gx, R gy, R gz, R& r
   for (int k = 0; k < Q; ++k) r += fs[k];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    if (kCX[k] > 0) j0 += fs[k];
-    if (kCX[k] < 0) j0 += -fs[k];
-    if (kCY[k] > 0) j1 += fs[k];
-    if (kCY[k] < 0) j1 += -fs[k];
-    if (kCZ[k] > 0) j2 += fs[k];
-    if (kCZ[k] < 0) j2 += -fs[k];
+    if (cxd(k) > 0) j0 += fs[k];
+    if (cxd(k) < 0) j0 += -fs[k];
+    if (cyd(k) > 0) j1 += fs[k];
+    if (cyd(k) < 0) j1 += -fs[k];
+    if (czd(k) > 0) j2 += fs[k];
+    if (czd(k) < 0) j2 += -fs[k];
   }
   rho = SH ? R(1) + r : r;
   ux = (j0 - R(0.5) * (rho * gx)) / rho;
@@ -390,9 +402,9 @@ __device__ __forceinline__ void collide(R* f, const CollideParams<R>& cp, R& rho
   R fe[Q], S[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    const R cu = cdot<R>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
-    const R cF = cdot<R>(kCX[k], kCY[k], kCZ[k], Fx, Fy, Fz);
-    const R cmuF = (R(kCX[k]) - ux) * Fx + (R(kCY[k]) - uy) * Fy + (R(kCZ[k]) - uz) * Fz;
+    const R cu = cdot<R>(cxd(k), cyd(k), czd(k), ux, uy, uz);
+    const R cF = cdot<R>(cxd(k), cyd(k), czd(k), Fx, Fy, Fz);
+    const R cmuF = (R(cxd(k)) - ux) * Fx + (R(cyd(k)) - uy) * Fy + (R(czd(k)) - uz) * Fz;
     fe[k] = feq_k<R, Q, SH>(k, rho, dr, cu, usq);
     S[k] = R(weight<Q>(k)) * (R(3) * cmuF + R(9) * cu * cF);
   }
@@ -403,15 +415,15 @@ __device__ __forceinline__ void collide(R* f, const CollideParams<R>& cp, R& rho
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       const R nq = f[k] - fe[k];
-      if (kCX[k] != 0) qxx += nq;
-      if (kCY[k] != 0) qyy += nq;
-      if (kCZ[k] != 0) qzz += nq;
-      if (kCX[k] * kCY[k] > 0) qxy += nq;
-      if (kCX[k] * kCY[k] < 0) qxy += -nq;
-      if (kCX[k] * kCZ[k] > 0) qxz += nq;
-      if (kCX[k] * kCZ[k] < 0) qxz += -nq;
-      if (kCY[k] * kCZ[k] > 0) qyz += nq;
-      if (kCY[k] * kCZ[k] < 0) qyz += -nq;
+      if (cxd(k) != 0) qxx += nq;
+      if (cyd(k) != 0) qyy += nq;
+      if (czd(k) != 0) qzz += nq;
+      if (cxd(k) * cyd(k) > 0) qxy += nq;
+      if (cxd(k) * cyd(k) < 0) qxy += -nq;
+      if (cxd(k) * czd(k) > 0) qxz += nq;
+      if (cxd(k) * czd(k) < 0) qxz += -nq;
+      if (cyd(k) * czd(k) > 0) qyz += nq;
+      if (cyd(k) * czd(k) < 0) qyz += -nq;
     }
     const R tau = les_tau<R>(cp.tau0, cp.cs, rho, qxx, qyy, qzz, qxy, qxz, qyz);
     om = R(1) / tau;
@@ -454,12 +466,12 @@ __device__ __forceinline__ void collide_pairs(float* f, const CollideParams<floa
 #pragma unroll
   for (int k = 1; k < Q; k += 2) {
     const float d = f[k] - f[k + 1];  // c_k f_k + c_kbar f_kbar = c_k (f_k - f_kbar)
-    if (kCX[k] > 0) j0 += d;
-    if (kCX[k] < 0) j0 -= d;
-    if (kCY[k] > 0) j1 += d;
-    if (kCY[k] < 0) j1 -= d;
-    if (kCZ[k] > 0) j2 += d;
-    if (kCZ[k] < 0) j2 -= d;
+    if (cxd(k) > 0) j0 += d;
+    if (cxd(k) < 0) j0 -= d;
+    if (cyd(k) > 0) j1 += d;
+    if (cyd(k) < 0) j1 -= d;
+    if (czd(k) > 0) j2 += d;
+    if (czd(k) < 0) j2 -= d;
   }
   const float dr = r;
   rho = 1.f + r;
@@ -476,18 +488,18 @@ __device__ __forceinline__ void collide_pairs(float* f, const CollideParams<floa
     float qxx = 0.f, qyy = 0.f, qzz = 0.f, qxy = 0.f, qxz = 0.f, qyz = 0.f;
 #pragma unroll
     for (int k = 1; k < Q; k += 2) {
-      const float cu = cdot<float>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
+      const float cu = cdot<float>(cxd(k), cyd(k), czd(k), ux, uy, uz);
       const float ep = float(weight<Q>(k)) * (dr + rho * (4.5f * cu * cu - 1.5f * usq));
       const float nq = (f[k] + f[k + 1]) - 2.f * ep;
-      if (kCX[k] != 0) qxx += nq;
-      if (kCY[k] != 0) qyy += nq;
-      if (kCZ[k] != 0) qzz += nq;
-      if (kCX[k] * kCY[k] > 0) qxy += nq;
-      if (kCX[k] * kCY[k] < 0) qxy -= nq;
-      if (kCX[k] * kCZ[k] > 0) qxz += nq;
-      if (kCX[k] * kCZ[k] < 0) qxz -= nq;
-      if (kCY[k] * kCZ[k] > 0) qyz += nq;
-      if (kCY[k] * kCZ[k] < 0) qyz -= nq;
+      if (cxd(k) != 0) qxx += nq;
+      if (cyd(k) != 0) qyy += nq;
+      if (czd(k) != 0) qzz += nq;
+      if (cxd(k) * cyd(k) > 0) qxy += nq;
+      if (cxd(k) * cyd(k) < 0) qxy -= nq;
+      if (cxd(k) * czd(k) > 0) qxz += nq;
+      if (cxd(k) * czd(k) < 0) qxz -= nq;
+      if (cyd(k) * czd(k) > 0) qyz += nq;
+      if (cyd(k) * czd(k) < 0) qyz -= nq;
     }
     const float tau = les_tau<float>(cp.tau0, cp.cs, rho, qxx, qyy, qzz, qxy, qxz, qyz);
     om = 1.f / tau;
@@ -503,8 +515,8 @@ __device__ __forceinline__ void collide_pairs(float* f, const CollideParams<floa
 #pragma unroll
   for (int k = 1; k < Q; k += 2) {
     const float w = float(weight<Q>(k));
-    const float cu = cdot<float>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
-    const float cF = cdot<float>(kCX[k], kCY[k], kCZ[k], Fx, Fy, Fz);
+    const float cu = cdot<float>(cxd(k), cyd(k), czd(k), ux, uy, uz);
+    const float cF = cdot<float>(cxd(k), cyd(k), czd(k), Fx, Fy, Fz);
     const float ep = w * (dr + rho * (4.5f * cu * cu - 1.5f * usq));
     const float em = w * (3.f * rho * cu);
     const float sp = w * (9.f * cu * cF - 3.f * uF);
@@ -533,7 +545,7 @@ __device__ __forceinline__ void collide_any(R* f, const CollideParams<R>& cp, R&
 // h_k = 2 w_k (rhoG - 1 + rhoG (4.5 (c.u)^2 - 1.5 u^2)) - h*_kbar.
 template <typename R, int Q, bool SH>
 __device__ __forceinline__ R abb_value(int k, R rhoG, R ux, R uy, R uz, R usq, R fs_kbar) {
-  const R cu = cdot<R>(kCX[k], kCY[k], kCZ[k], ux, uy, uz);
+  const R cu = cdot<R>(cxd(k), cyd(k), czd(k), ux, uy, uz);
   if (SH)
     return R(2) * R(weight<Q>(k)) * ((rhoG - R(1)) + rhoG * (R(4.5) * cu * cu - R(1.5) * usq)) -
            fs_kbar;

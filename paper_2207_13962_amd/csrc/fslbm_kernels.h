@@ -1,25 +1,25 @@
 // HIP kernels of the free-surface LBM step for gfx950.
 //
-// One time step is six launches (plus two for surface tension, two for the
-// bubble volume); the last three run only when some cell was marked:
-//   k_liquid    chunk-list-driven : every liquid cell away from walls - pull
-//                                   streaming, collision, store (the bandwidth
-//                                   kernel)
-//   k_border    list-driven       : liquid cells next to a wall or obstacle
-//                                   (streaming with walls, collision); clears the
-//                                   transient bits of the previous conversion
-//   k_generic   list-driven       : every interface cell of the compacted list -
-//                                   streaming, free-surface condition with the
-//                                   variant's set, mass exchange, fill level,
-//                                   conversion mark, collision
+// One time step is four launches (plus two for surface tension, two for the
+// bubble volume); the last three do their work only when some cell was marked:
+//   k_stream    three roles       : every liquid cell away from walls (chunk
+//                                   list; pull streaming, collision - the
+//                                   bandwidth part), every liquid cell next to
+//                                   a wall or obstacle, and every interface cell
+//                                   of the compacted list (streaming, free-
+//                                   surface condition with the variant's set,
+//                                   mass exchange, fill level, conversion mark,
+//                                   collision)
 //   k_retype    mark-list-driven  : new types around every marked cell (to-gas
 //                                   marks next to a to-liquid mark are dropped)
 //   k_compact   every cell        : the new interface, converted, liquid-chunk
 //                                   and wall-liquid lists, compacted in ascending
 //                                   order by a single-pass scan (block scan +
-//                                   decoupled look-back)
-//   k_finish    list-driven       : reinitialise new interface cells from gas,
-//                                   mass of new interface cells from liquid,
+//                                   published tile counts); beside it, worker
+//                                   blocks reinitialise the new interface cells
+//                                   from gas and split the excess mass of the
+//                                   converted cells
+//   k_finish    list-driven       : mass of new interface cells from liquid,
 //                                   excess-mass gather, fill levels, flux classes
 // The state between steps is the post-collision population f* (grid A); the
 // step writes grid B and the host swaps A/B. Marks, counters and lists stay on the
@@ -32,6 +32,7 @@ namespace fslbm {
 
 constexpr int kBlock = 256;
 constexpr int kMaxTiles = 4096;  // compaction tiles at most (tile size grows with the domain)
+constexpr int kCompBlock = 1024;  // threads of a compaction block
 
 struct Dev {
   Geom g;
@@ -76,7 +77,7 @@ __device__ __forceinline__ void load_plain(const typename Store<S, Q>::T* A, int
                                            typename Store<S, Q>::R* f) {
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    const int64_t off = kCX[k] + (int64_t)kCY[k] * nx + (int64_t)kCZ[k] * nxy;
+    const int64_t off = cxd(k) + (int64_t)cyd(k) * nx + (int64_t)czd(k) * nxy;
     f[k] = Store<S, Q>::ld(A, k * stride + c - off, k);
   }
 }
@@ -118,10 +119,10 @@ __device__ __forceinline__ void liquid_cell(const Dev& d, int64_t c, bool valid)
     coords(g, c, x, y, z);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      const int64_t off = kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
-      const bool in = (unsigned)(x - kCX[k]) < (unsigned)g.nx &&
-                      (unsigned)(y - kCY[k]) < (unsigned)g.ny &&
-                      (unsigned)(z - kCZ[k]) < (unsigned)g.nz;
+      const int64_t off = cxd(k) + cyd(k) * nx + czd(k) * nxy;
+      const bool in = (unsigned)(x - cxd(k)) < (unsigned)g.nx &&
+                      (unsigned)(y - cyd(k)) < (unsigned)g.ny &&
+                      (unsigned)(z - czd(k)) < (unsigned)g.nz;
       const int64_t e = in ? k * stride + c - off : opp(k) * stride + c;
       if constexpr (BUF) {
         const __amdgpu_buffer_rsrc_t ra =
@@ -137,7 +138,7 @@ __device__ __forceinline__ void liquid_cell(const Dev& d, int64_t c, bool valid)
     const uint32_t vo = (uint32_t)c * (uint32_t)sizeof(T);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      const int64_t off = kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
+      const int64_t off = cxd(k) + cyd(k) * nx + czd(k) * nxy;
       f[k] = St::bld(ra, vo, (uint32_t)((k * stride - off) * (int64_t)sizeof(T)));
     }
   } else {
@@ -275,7 +276,7 @@ __device__ __forceinline__ R gcollide(R f, int k, const CollideParams<R>& cp, R&
                                       R& uz) {
   const bool act = k < Q;
   const int kk = act ? k : 0;
-  const int cx = kCX[kk], cy = kCY[kk], cz = kCZ[kk];
+  const int cx = cxd(kk), cy = cyd(kk), cz = czd(kk);
   const R fv = act ? f : R(0);
   const R r = gsum(fv, Q);
   const R j0 = gsum(cx > 0 ? fv : (cx < 0 ? -fv : R(0)), Q);
@@ -324,7 +325,7 @@ __device__ __forceinline__ R gcollide(R f, int k, const CollideParams<R>& cp, R&
 // discarded); only a source reflected at a free-slip face needs a second
 // round.
 template <int S, int Q, bool TRT>
-__global__ __launch_bounds__(kBlock) void k_generic(Dev d) {
+__device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk) {
   using St = Store<S, Q>;
   using T = typename St::T;
   using R = typename St::R;
@@ -338,11 +339,11 @@ __global__ __launch_bounds__(kBlock) void k_generic(Dev d) {
   const bool act = l < Q;
   const int k = act ? l : 0;
   const int kb = opp(k);
-  const int cx = kCX[k], cy = kCY[k], cz = kCZ[k];
-  const int ngroups = gridDim.x * (kBlock / kG);
+  const int cx = cxd(k), cy = cyd(k), cz = czd(k);
+  const int ngroups = nblk * (kBlock / kG);
   const int v = d.variant;
   CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
-  for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < nif; item += ngroups) {
+  for (int item = blk * (kBlock / kG) + threadIdx.x / kG; item < nif; item += ngroups) {
     const int64_t c = d.if_list[item];
     int x, y, z;
     coords(g, c, x, y, z);
@@ -519,13 +520,14 @@ __device__ __forceinline__ void border_cell(const Dev& d, int64_t c) {
   for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
 }
 
-// Also clears the transient bits of the cells converted by the previous
-// conversion (readers in this kernel look at the type bits only).
+// Also clears the transient bits of the cells of the last converted list
+// (every transient bit is stale by now; readers in this kernel look at the
+// type bits only).
 template <int S, int Q, bool TRT>
-__global__ __launch_bounds__(kBlock) void k_border(Dev d) {
+__device__ __forceinline__ void border_role(const Dev& d, int blk, int nblk) {
   const int n = d.cnt[CNT_GEN];
-  const int ncv = d.cnt[CNT_CONVP];
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n + ncv; i += gridDim.x * kBlock) {
+  const int ncv = d.cnt[CNT_CONV];
+  for (int i = blk * kBlock + threadIdx.x; i < n + ncv; i += nblk * kBlock) {
     if (i < n) {
       border_cell<S, Q, TRT>(d, d.gen_list[i]);
     } else {
@@ -538,21 +540,34 @@ __global__ __launch_bounds__(kBlock) void k_border(Dev d) {
 // Each wave takes 64-cell chunks from the chunk list (chunks without liquid
 // cells are never visited), one cell per lane.
 template <int S, int Q, bool TRT, bool BUF>
-__global__ __launch_bounds__(kBlock) void k_liquid(Dev d) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // slot of the next step
-    // the converted list of the previous conversion is cleared by k_border
-    d.cnt[CNT_CONVP] = d.cnt[CNT_CONV];
-    d.cnt[CNT_CONV] = 0;
-    d.cnt[CNT_NG] = 0;
-  }
+__device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk) {
   const int nch = d.cnt[CNT_CHUNKS];
   const int lane = threadIdx.x & 63;
-  const int waves = gridDim.x * (kBlock / 64);
-  for (int w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); w < nch; w += waves) {
+  const int waves = nblk * (kBlock / 64);
+  for (int w = blk * (kBlock / 64) + (threadIdx.x >> 6); w < nch; w += waves) {
     const int64_t c = (int64_t)d.chunk_list[w] * 64 + lane;
     liquid_cell<S, Q, TRT, BUF>(d, c, c < d.g.N);
   }
+}
+
+// The streaming half of a step in one launch: the three cell classes read
+// grid A and write disjoint cells of grid B, so their blocks run side by side
+// (the ALU-heavy interface groups overlap the bandwidth-bound liquid waves).
+// Blocks [0, gen) take interface cells, [gen, gen + bord) the liquid cells
+// next to walls or obstacles, the rest the liquid chunks.
+template <int S, int Q, bool TRT, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_stream(Dev d, int gen, int bord) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // mark slot of the next step
+    d.cnt[CNT_NG] = 0;                          // new-gas list of this step
+  }
+  const int b = (int)blockIdx.x;
+  if (b < gen)
+    generic_role<S, Q, TRT>(d, b, gen);
+  else if (b < gen + bord)
+    border_role<S, Q, TRT>(d, b - gen, bord);
+  else
+    liquid_role<S, Q, TRT, BUF>(d, b - gen - bord, (int)gridDim.x - gen - bord);
 }
 
 // ---------------------------------------------------------------------------
@@ -604,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void k_retype(Dev d, int rebuild_only) {
     int64_t j = -1;
     if (l > 0 && l < Q) {
       int w;
-      j = nb_index(d.g, x, y, z, kCX[l], kCY[l], kCZ[l], &w);
+      j = nb_index(d.g, x, y, z, cxd(l), cyd(l), czd(l), &w);
     }
     const uint8_t mj = j >= 0 ? d.mark[j] : (uint8_t)MK_NONE;
     const uint8_t fj = j >= 0 ? d.flags[j] : (uint8_t)0;
@@ -625,6 +640,7 @@ __global__ __launch_bounds__(kBlock) void k_retype(Dev d, int rebuild_only) {
 
 // Block-wide exclusive scan of a per-thread count (wave prefix by shuffles,
 // wave totals through LDS). Returns the prefix; *total receives the block sum.
+template <int NT>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t inc = v;
@@ -637,7 +653,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
   __syncthreads();
   uint32_t before = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) {
+  for (int w = 0; w < NT / 64; ++w) {
     if (w < wv) before += sh[w];
     tot += sh[w];
   }
@@ -773,7 +789,7 @@ __device__ __forceinline__ unsigned long long pack2(uint32_t epoch, uint32_t a, 
          (unsigned long long)(b & 0xffffffu);
 }
 
-// List compaction. A tile is 256 threads times `per` cells (per = 16 times a
+// List compaction. A tile is 1024 threads times `per` cells (per = 16 times a
 // power of two, chosen by the host so that there are at most kMaxTiles
 // tiles); thread t owns the cells [per t, per t + per) of the tile, read as
 // 16-byte vectors. The interface list, the converted list, the chunk list
@@ -790,11 +806,11 @@ __device__ __forceinline__ unsigned long long pack2(uint32_t epoch, uint32_t a, 
 // without marks (the lists are unchanged then).
 // The first `workers` blocks do the other work that k_finish waits for.
 template <int S, int Q, bool TRT>
-__global__ __launch_bounds__(kBlock) void k_compact(Dev d, int rebuild_only, int per, int workers) {
+__global__ __launch_bounds__(kCompBlock) void k_compact(Dev d, int rebuild_only, int per, int workers) {
   __shared__ int s_tile, s_run;
   __shared__ uint32_t s_epoch;
-  __shared__ uint32_t s_scan[4][kBlock / 64];
-  __shared__ uint32_t s_red[4][kBlock / 64];
+  __shared__ uint32_t s_scan[4][kCompBlock / 64];
+  __shared__ uint32_t s_red[4][kCompBlock / 64];
   if ((int)blockIdx.x < workers) {
     // worker blocks, beside the compaction: the converted cells (the marked
     // cells that carry the converted bit) get their excess-mass share, the new
@@ -802,13 +818,13 @@ __global__ __launch_bounds__(kBlock) void k_compact(Dev d, int rebuild_only, int
     if (rebuild_only) return;
     const int nmk = d.cnt[CNT_MARK0 + (d.step & 1)];
     const int nng = d.cnt[CNT_NG];
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nmk; i += workers * kBlock) {
+    for (int i = blockIdx.x * kCompBlock + threadIdx.x; i < nmk; i += workers * kCompBlock) {
       const int64_t zc = d.mark_list[i];
       if (d.flags[zc] & F_CONV) finish_converted<Q>(d, zc);
     }
     const int l = threadIdx.x & (kG - 1);
-    const int ngroups = workers * (kBlock / kG);
-    for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < nng; item += ngroups)
+    const int ngroups = workers * (kCompBlock / kG);
+    for (int item = blockIdx.x * (kCompBlock / kG) + threadIdx.x / kG; item < nng; item += ngroups)
       reinit_from_gas<S, Q, TRT>(d, d.ng_list[item], l);
     return;
   }
@@ -827,13 +843,13 @@ __global__ __launch_bounds__(kBlock) void k_compact(Dev d, int rebuild_only, int
   const int tile = s_tile;
   const uint32_t epoch = s_epoch;
   const int64_t N = d.g.N;
-  const int64_t base = ((int64_t)tile * kBlock + threadIdx.x) * per;
+  const int64_t base = ((int64_t)tile * kCompBlock + threadIdx.x) * per;
   const int nvec = per / 16;
   // threads per 64-cell chunk (per < 64), else chunks per thread
   const int tpc = per < 64 ? 64 / per : 1;
   // pass 1: masks and counts, in batches of kBatch 16-byte vectors requested
   // together; the masks of the first batch are kept for pass 2
-  constexpr int kBatch = 8;
+  constexpr int kBatch = 4;
   uint32_t keep[4][kBatch];
   uint32_t c[4] = {0, 0, 0, 0};
   uint32_t own_any = 0;
@@ -880,7 +896,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(Dev d, int rebuild_only, int
   }
   uint32_t pre[4], tot[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) pre[i] = block_excl_scan(c[i], s_scan[i], &tot[i]);
+  for (int i = 0; i < 4; ++i) pre[i] = block_excl_scan<kCompBlock>(c[i], s_scan[i], &tot[i]);
   unsigned long long* st = d.scan_status;
   if (threadIdx.x == 0) {
     __hip_atomic_store(&st[2 * tile], pack2(epoch, tot[0], tot[1]), __ATOMIC_RELAXED,
@@ -890,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(Dev d, int rebuild_only, int
   }
   // sum of the counts of all earlier tiles
   uint32_t acc[4] = {0, 0, 0, 0};
-  for (int t = threadIdx.x; t < tile; t += kBlock) {
+  for (int t = threadIdx.x; t < tile; t += kCompBlock) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       unsigned long long v;
@@ -924,7 +940,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(Dev d, int rebuild_only, int
   for (int i = 0; i < 4; ++i) {
     uint32_t e = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) e += s_red[i][w];
+    for (int w = 0; w < kCompBlock / 64; ++w) e += s_red[i][w];
     off[i] = e + pre[i];
   }
   const uint32_t chunks_end = off[2] + c[2];
@@ -973,7 +989,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(Dev d, int rebuild_only, int
     }
   }
   if (per < 64 && c[2]) d.chunk_list[off[2]] = (int32_t)(base / 64);
-  if (tile == (int)gridDim.x - workers - 1 && threadIdx.x == kBlock - 1) {
+  if (tile == (int)gridDim.x - workers - 1 && threadIdx.x == kCompBlock - 1) {
     d.cnt[CNT_IF] = (int32_t)off[0];
     d.cnt[CNT_CONV] = (int32_t)off[1];
     d.cnt[CNT_GEN] = (int32_t)off[3];
@@ -1287,7 +1303,7 @@ __global__ __launch_bounds__(kBlock) void k_init_flags(Dev d) {
         const int n[3] = {g.nx, g.ny, g.nz};
         for (int a = 0; a < 3; ++a) {
           const int face = r[a] < 0 ? 2 * a : (r[a] >= n[a] ? 2 * a + 1 : -1);
-          if (face >= 0 && g.bnd[face] != BND_NOSLIP) complex_ = true;
+          if (face >= 0 && face_kind(g, face) != BND_NOSLIP) complex_ = true;
         }
         int w;
         int64_t j = nb_index(g, x, y, z, dx, dy, dz, &w);
@@ -1297,7 +1313,7 @@ __global__ __launch_bounds__(kBlock) void k_init_flags(Dev d) {
       }
   for (int k = 1; k < Q; ++k) {
     int w;
-    int64_t j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
+    int64_t j = nb_index(g, x, y, z, cxd(k), cyd(k), czd(k), &w);
     if (j >= 0 && (d.flags[j] & T_MASK) == T_GAS) gas_nb = true;
   }
   if (t == T_LIQ && gas_nb) atomicOr(&d.cnt[CNT_ERR], ERR_LAYER);
@@ -1339,7 +1355,7 @@ __global__ __launch_bounds__(kBlock) void k_init_state(Dev d, int resume) {
 #pragma unroll
       for (int k = 0; k < Q; ++k)
         f[k] = feq_k<R, Q, St::kShift>(k, R(rho), R(rho - 1.0),
-                                       cdot<R>(kCX[k], kCY[k], kCZ[k], R(ux), R(uy), R(uz)), usq);
+                                       cdot<R>(cxd(k), cyd(k), czd(k), R(ux), R(uy), R(uz)), usq);
       CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
       R rr, vx, vy, vz;
       collide<R, Q, TRT, St::kShift>(f, cp, rr, vx, vy, vz);

@@ -38,8 +38,8 @@ inline Layout make_layout(const fslbm_params& p) {
   L.stride = round_up(L.N, 256);
   // compaction: cells per thread 16 times a power of two, at most kMaxTiles tiles
   L.conv_per = 16;
-  while (L.conv_per * kBlock * kMaxTiles < L.N) L.conv_per *= 2;
-  L.tiles = (L.N + kBlock * L.conv_per - 1) / (kBlock * L.conv_per);
+  while (L.conv_per * kCompBlock * kMaxTiles < L.N) L.conv_per *= 2;
+  L.tiles = (L.N + kCompBlock * L.conv_per - 1) / (kCompBlock * L.conv_per);
   L.red_blocks = (L.N + kRedCells - 1) / kRedCells;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -121,6 +121,7 @@ struct fslbm_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool graphs = true;
+  int cus = 256;  // compute units of the device
 };
 
 constexpr int64_t kGraphSteps = 8;
@@ -181,26 +182,31 @@ struct Impl {
   static void step(fslbm_ctx* c, hipStream_t s) {
     // buffer addressing when a population grid spans less than 2 GiB
     const bool buf = (double)Q * (double)c->L.stride * sizeof(typename Store<S, Q>::T) < 2147483648.0;
-    // with timing on, the liquid kernel's own dispatch records start/stop
+    // with timing on, the streaming kernel's own dispatch records start/stop
     // timestamps (no separate event packets around it)
     const bool timed = 2 * (c->ev_used + 1) <= (int64_t)c->ev.size();
     hipEvent_t e0 = timed ? c->ev[2 * c->ev_used] : nullptr;
     hipEvent_t e1 = timed ? c->ev[2 * c->ev_used + 1] : nullptr;
     if (timed) c->ev_used++;
+    // role split of the streaming launch, within what the GPU holds at once
+    // (four 256-thread blocks per CU at the kernel's occupancy)
+    const int64_t cap = 4 * (int64_t)c->cus;
+    const int gen = (int)std::max<int64_t>(1, std::min<int64_t>(if_blocks(c), cap * 3 / 8));
+    const int bord = (int)std::max<int64_t>(1, std::min<int64_t>(border_blocks(c), cap / 8));
+    const int liq = (int)std::max<int64_t>(1, std::min<int64_t>(liquid_blocks(c), cap / 2));
+    const dim3 grid((unsigned)(gen + bord + liq));
     if (buf)
-      hipExtLaunchKernelGGL((k_liquid<S, Q, TRT, true>), dim3(liquid_blocks(c)), dim3(kBlock), 0, s,
-                            e0, e1, 0, c->d);
+      hipExtLaunchKernelGGL((k_stream<S, Q, TRT, true>), grid, dim3(kBlock), 0, s, e0, e1, 0, c->d, gen,
+                            bord);
     else
-      hipExtLaunchKernelGGL((k_liquid<S, Q, TRT, false>), dim3(liquid_blocks(c)), dim3(kBlock), 0, s,
-                            e0, e1, 0, c->d);
-    hipLaunchKernelGGL((k_border<S, Q, TRT>), dim3(border_blocks(c)), dim3(kBlock), 0, s, c->d);
-    hipLaunchKernelGGL((k_generic<S, Q, TRT>), dim3(if_blocks(c)), dim3(kBlock), 0, s, c->d);
+      hipExtLaunchKernelGGL((k_stream<S, Q, TRT, false>), grid, dim3(kBlock), 0, s, e0, e1, 0, c->d, gen,
+                            bord);
   }
   static void convert(fslbm_ctx* c, hipStream_t s, int rebuild) {
     hipLaunchKernelGGL((k_retype<Q>), dim3(retype_blocks(c)), dim3(kBlock), 0, s, c->d, rebuild);
-    const int workers = rebuild ? 0 : (int)retype_blocks(c);
-    hipLaunchKernelGGL((k_compact<S, Q, TRT>), dim3((unsigned)(c->L.tiles + workers)), dim3(kBlock), 0,
-                       s, c->d, rebuild, (int)c->L.conv_per, workers);
+    const int workers = rebuild ? 0 : (int)(retype_blocks(c) + 3) / 4;
+    hipLaunchKernelGGL((k_compact<S, Q, TRT>), dim3((unsigned)(c->L.tiles + workers)), dim3(kCompBlock),
+                       0, s, c->d, rebuild, (int)c->L.conv_per, workers);
   }
   static void finish(fslbm_ctx* c, hipStream_t s, int classes_only) {
     hipLaunchKernelGGL((k_finish<S, Q, TRT>), dim3(finish_blocks(c)), dim3(kBlock), 0, s, c->d,

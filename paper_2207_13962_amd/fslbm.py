@@ -224,11 +224,11 @@ class Simulation:
         self._check(self._lib.fslbm_set_graphs(self._h, int(bool(enable))))
 
     def set_timing(self, capacity):
-        """Bracket the next `capacity` liquid stream-collide launches with HIP events."""
+        """Bracket the next `capacity` streaming-kernel launches (one per step) with HIP events."""
         self._check(self._lib.fslbm_set_timing(self._h, int(capacity)))
 
     def kernel_time(self):
-        """(timed launches, summed duration in ms) of the liquid stream-collide kernel."""
+        """(timed launches, summed duration in ms) of the streaming kernel."""
         n, ms = C.c_int64(), C.c_double()
         self._check(self._lib.fslbm_kernel_time(self._h, C.byref(n), C.byref(ms)))
         return n.value, ms.value
