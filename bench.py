@@ -70,11 +70,11 @@ def bytes_per_update(q, storage_bytes):
     return 2 * q * storage_bytes + 1
 
 
-# rocprofv3 FETCH_SIZE / WRITE_SIZE are in KiB per dispatch; on MI355X a plain
-# copy kernel of 1 GiB each way reads FETCH_SIZE = 512 MiB and WRITE_SIZE =
-# 1 GiB, so HBM bytes = 2.0 * 1024 * FETCH_SIZE + 1.0 * 1024 * WRITE_SIZE.
-FETCH_SCALE = 2.0
-WRITE_SCALE = 1.0
+# rocprofv3 FETCH_SIZE / WRITE_SIZE are in KiB per dispatch and count L2
+# traffic in units that differ from bytes moved; each is scaled by what the
+# same counter reads for a plain copy kernel of known size (--copy-calibration
+# run under the same counters).
+COPY_BYTES = 1 << 30  # bytes read and bytes written by one calibration copy
 
 
 def _counter_rows(path, counter, kernel_prefix):
@@ -88,11 +88,21 @@ def _counter_rows(path, counter, kernel_prefix):
     return [v for _, v in vals]
 
 
-def write_traffic(fetch_csv, write_csv, last, command):
+def _copy_counter(path, counter):
+    """Counter value (KiB) of the calibration copies: the median of the five
+    largest dispatches (the 1 GiB copies) of the calibration run."""
+    import csv
+    vals = sorted(float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                  if r["Counter_Name"] == counter)
+    top = vals[-5:]
+    return top[len(top) // 2]
+
+
+def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, last, command):
     """Turns two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of the
-    benchmark into the traffic summary read back by measured_traffic(): the
-    mean over the last `last` streaming-kernel dispatches (the kernel-timing
-    region of the benchmark)."""
+    benchmark, and the same two counters over the copy calibration, into the
+    traffic summary read back by measured_traffic(): the mean over the last
+    `last` streaming-kernel dispatches (the kernel-timing region)."""
     fe = _counter_rows(fetch_csv, "FETCH_SIZE", "void fslbm::k_stream<")
     wr = _counter_rows(write_csv, "WRITE_SIZE", "void fslbm::k_stream<")
     if not fe or not wr:
@@ -100,20 +110,63 @@ def write_traffic(fetch_csv, write_csv, last, command):
     fe, wr = fe[-last:], wr[-last:]
     f_kib = sum(fe) / len(fe)
     w_kib = sum(wr) / len(wr)
-    hbm = FETCH_SCALE * 1024 * f_kib + WRITE_SCALE * 1024 * w_kib
+    cf, cw = _copy_counter(cfetch_csv, "FETCH_SIZE"), _copy_counter(cwrite_csv, "WRITE_SIZE")
+    fscale, wscale = COPY_BYTES / (1024.0 * cf), COPY_BYTES / (1024.0 * cw)
+    hbm = fscale * 1024 * f_kib + wscale * 1024 * w_kib
     with open(TRAFFIC_FILE, "w") as fh:
-        fh.write("# HBM traffic of the streaming kernel (k_stream), dam256 workload\n")
-        fh.write("# commands (FETCH_SIZE run, then WRITE_SIZE run):\n")
+        fh.write("# HBM traffic of the streaming kernel (k_stream), dam256 workload (D3Q19 TRT + LES,\n")
+        fh.write("# FP32 populations), from rocprofv3 counters. Commands (run from the repository root):\n")
         for c in command:
             fh.write("#   %s\n" % c)
-        fh.write("# dispatches averaged: the last %d of each run (kernel-timing region)\n" % len(fe))
-        fh.write("# scale: HBM bytes = %.1f*1024*FETCH_SIZE + %.1f*1024*WRITE_SIZE (plain-copy calibration)\n"
-                 % (FETCH_SCALE, WRITE_SCALE))
+        fh.write("# dispatches averaged: the last %d of each benchmark run (kernel-timing region)\n" % len(fe))
+        fh.write("# calibration: a 1 GiB copy reads FETCH_SIZE = %.0f KiB and writes WRITE_SIZE = %.0f KiB,\n"
+                 % (cf, cw))
+        fh.write("# so HBM bytes = %.3f*1024*FETCH_SIZE + %.3f*1024*WRITE_SIZE\n" % (fscale, wscale))
         fh.write("kernel_source_sha256_16: %s\n" % kernel_source_hash())
         fh.write("fetch_size_kib_per_launch: %.1f\n" % f_kib)
         fh.write("write_size_kib_per_launch: %.1f\n" % w_kib)
+        fh.write("fetch_scale: %.4f\n" % fscale)
+        fh.write("write_scale: %.4f\n" % wscale)
         fh.write("hbm_bytes_per_launch: %.0f\n" % hbm)
     print(open(TRAFFIC_FILE).read())
+
+
+def write_trace_summary(trace_dir, out_path, last, command):
+    """Short text summary of a rocprofv3 --kernel-trace --stats run of the
+    benchmark: per-kernel calls and mean duration, plus the streaming kernel's
+    mean over the last `last` launches (the kernel-timing region)."""
+    import csv
+    import glob
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(trace_dir, "*_kernel_stats.csv"))[0])))
+    trace = list(csv.DictReader(open(glob.glob(os.path.join(trace_dir, "*_kernel_trace.csv"))[0])))
+    ks = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
+          if r["Kernel_Name"].startswith("void fslbm::k_stream<")]
+    with open(out_path, "w") as fh:
+        fh.write("# rocprofv3 kernel trace of the benchmark, dam256 workload (4 variant runs).\n")
+        fh.write("# command (from the repository root):\n")
+        for c in command:
+            fh.write("#   %s\n" % c)
+        fh.write("%-72s %8s %12s %7s\n" % ("kernel", "calls", "mean_us", "pct"))
+        for r in stats:
+            fh.write("%-72s %8s %12.2f %7.2f\n" % (r["Name"][:72], r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                   float(r["Percentage"])))
+        if ks:
+            tail = ks[-last:]
+            fh.write("k_stream mean over the last %d launches (kernel-timing region): %.2f us\n"
+                     % (len(tail), sum(tail) / len(tail)))
+    print(open(out_path).read())
+
+
+def copy_calibration():
+    """A plain device copy of COPY_BYTES, five times (run under rocprofv3
+    counters to calibrate FETCH_SIZE and WRITE_SIZE)."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 5}))
 
 
 def cpu_baseline(setup_fn, steps):
@@ -149,15 +202,27 @@ def main():
                     help="time steps per variant run of the kernel-timing region")
     ap.add_argument("--les", type=float, default=0.1, help="Smagorinsky constant (0: off)")
     ap.add_argument("--no-graphs", action="store_true", help="launch kernel by kernel")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="summarise two rocprofv3 counter runs into the traffic file and exit")
-    ap.add_argument("--traffic-command", action="append", default=[],
-                    help="command line recorded in the traffic file (repeat per run)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 1 GiB copy used to calibrate the HBM counters")
+    ap.add_argument("--write-traffic", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="summarise rocprofv3 counter runs into the traffic file and exit")
+    ap.add_argument("--write-trace-summary", metavar="TRACE_DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--profile-command", action="append", default=[],
+                    help="command line recorded in a profile summary (repeat per run)")
     args = ap.parse_args()
+    last = len(args.variants.split(",")) * min(args.steps, args.kernel_steps)
     if args.write_traffic:
-        write_traffic(args.write_traffic[0], args.write_traffic[1],
-                      len(args.variants.split(",")) * min(args.steps, args.kernel_steps),
-                      args.traffic_command)
+        write_traffic(*args.write_traffic, last, args.profile_command)
+        return
+    if args.write_trace_summary:
+        write_trace_summary(args.write_trace_summary,
+                            os.path.join(ROOT, "profiles", "k_stream_dam256_trace.txt"), last,
+                            args.profile_command)
+        return
+    if args.copy_calibration:
+        copy_calibration()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the free-surface LBM step here runs on a single "

@@ -269,6 +269,27 @@ __device__ __forceinline__ uint32_t gballot(bool p) {
   return (uint32_t)(__ballot(p) >> (threadIdx.x & 32));
 }
 
+// Work items [0, n) of a role split over the XCDs: consecutive blocks of a
+// launch run on consecutive XCDs (round robin), each with its own L2, so
+// block blk (blk mod kXcds is its XCD when the role starts at a multiple of
+// kXcds) takes a slice of a contiguous range of the items: neighbouring cells,
+// whose populations share cache lines, are processed under one L2.
+constexpr int kXcds = 8;
+struct XcdRange {
+  int begin, end, first, step;  // items [begin, end), this unit's first item and stride
+};
+__device__ __forceinline__ XcdRange xcd_range(int n, int blk, int nblk, int unit, int units_per_block) {
+  const int x = blk % kXcds;
+  const int blocks_x = (nblk - x + kXcds - 1) / kXcds;  // blocks of this role on XCD x
+  const int r = blk / kXcds;
+  XcdRange q;
+  q.begin = (int)((int64_t)n * x / kXcds);
+  q.end = (int)((int64_t)n * (x + 1) / kXcds);
+  q.first = q.begin + r * units_per_block + unit;
+  q.step = blocks_x * units_per_block;
+  return q;
+}
+
 // Collision of one cell held one direction per lane (f = population of this
 // lane's direction k); same arithmetic as collide().
 template <typename R, int Q, bool TRT, bool SH>
@@ -340,10 +361,10 @@ __device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk) {
   const int k = act ? l : 0;
   const int kb = opp(k);
   const int cx = cxd(k), cy = cyd(k), cz = czd(k);
-  const int ngroups = nblk * (kBlock / kG);
   const int v = d.variant;
   CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
-  for (int item = blk * (kBlock / kG) + threadIdx.x / kG; item < nif; item += ngroups) {
+  const XcdRange q = xcd_range(nif, blk, nblk, threadIdx.x / kG, kBlock / kG);
+  for (int item = q.first; item < q.end; item += q.step) {
     const int64_t c = d.if_list[item];
     int x, y, z;
     coords(g, c, x, y, z);
@@ -543,8 +564,8 @@ template <int S, int Q, bool TRT, bool BUF>
 __device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk) {
   const int nch = d.cnt[CNT_CHUNKS];
   const int lane = threadIdx.x & 63;
-  const int waves = nblk * (kBlock / 64);
-  for (int w = blk * (kBlock / 64) + (threadIdx.x >> 6); w < nch; w += waves) {
+  const XcdRange q = xcd_range(nch, blk, nblk, threadIdx.x >> 6, kBlock / 64);
+  for (int w = q.first; w < q.end; w += q.step) {
     const int64_t c = (int64_t)d.chunk_list[w] * 64 + lane;
     liquid_cell<S, Q, TRT, BUF>(d, c, c < d.g.N);
   }

@@ -190,10 +190,13 @@ struct Impl {
     if (timed) c->ev_used++;
     // role split of the streaming launch, within what the GPU holds at once
     // (four 256-thread blocks per CU at the kernel's occupancy)
+    // (role sizes are multiples of the XCD count, so that a role's block index
+    // modulo kXcds is the XCD the block runs on)
     const int64_t cap = 4 * (int64_t)c->cus;
-    const int gen = (int)std::max<int64_t>(1, std::min<int64_t>(if_blocks(c), cap * 3 / 8));
-    const int bord = (int)std::max<int64_t>(1, std::min<int64_t>(border_blocks(c), cap / 8));
-    const int liq = (int)std::max<int64_t>(1, std::min<int64_t>(liquid_blocks(c), cap / 2));
+    auto xr = [](int64_t b) { return (int)std::max<int64_t>(kXcds, (b + kXcds - 1) / kXcds * kXcds); };
+    const int gen = xr(std::min<int64_t>(if_blocks(c), cap * 3 / 8));
+    const int bord = xr(std::min<int64_t>(border_blocks(c), cap / 8));
+    const int liq = xr(std::min<int64_t>(liquid_blocks(c), cap / 2));
     const dim3 grid((unsigned)(gen + bord + liq));
     if (buf)
       hipExtLaunchKernelGGL((k_stream<S, Q, TRT, true>), grid, dim3(kBlock), 0, s, e0, e1, 0, c->d, gen,
