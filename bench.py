@@ -189,6 +189,46 @@ def cpu_baseline(setup_fn, steps):
     return upd / dt / 1e6, dt
 
 
+def serving_section(args):
+    """Batched serving against one-at-a-time solves on a request mix shaped
+    like the serving workload (drop impacts and wave slabs, variants uniform,
+    FP32): a closed batch (every run arriving at t = 0) gives the batched
+    capacity; then Poisson arrivals at `load` times that capacity are served
+    both ways. Runs/s over the makespan, p50/p99 time to solution (queueing
+    included); the fill levels of every run must agree bitwise between the
+    two modes."""
+    import numpy as np
+    from paper_2207_13962_amd import serving as SV
+
+    reqs = SV.make_mix(n_requests=args.requests, l_min=args.l_min, l_max=args.l_max,
+                       steps_min=args.steps_min, steps_max=args.steps_max)
+    budget = int(args.budget_gb * (1 << 30))
+    zero = [0.0] * len(reqs)
+    SV.run_batched(reqs[:4], zero[:4], budget, max_slots=args.slots)  # warm-up (code load)
+    closed, _ = SV.run_batched(reqs, zero, budget, max_slots=args.slots)
+    rate = args.load * closed["runs_per_s"]
+    arrival = SV.poisson_arrivals(reqs, rate)
+    batched, rb = SV.run_batched(reqs, arrival, budget, max_slots=args.slots, keep_phi=True)
+    single, rs = SV.run_sequential(reqs, arrival, keep_phi=True)
+    same = all(a[0] == b[0] and np.array_equal(a[2], b[2]) for a, b in zip(rb, rs))
+    cells = [r["L"] ** 3 if r["kind"] == "drop" else r["L"] * (r["L"] // 2) * max(r["L"] // 4, 1)
+             for r in reqs]
+    return {
+        "workload": "%d runs: drop impacts (L^3) and wave slabs (L x L/2 x L/4), L in [%d, %d], "
+                    "%d-%d steps, D3Q19 SRT FP32, variants uniform" % (
+                        len(reqs), args.l_min, args.l_max, args.steps_min, args.steps_max),
+        "cells_total": int(sum(cells)),
+        "steps_total": int(sum(r["steps"] for r in reqs)),
+        "closed_batch_runs_per_s": closed["runs_per_s"],
+        "poisson_rate_runs_per_s": rate,
+        "batched": batched,
+        "one_at_a_time": single,
+        "speedup_runs_per_s": batched["runs_per_s"] / single["runs_per_s"],
+        "identical_results": bool(same),
+        "unstable_runs": int(sum(1 for r in rb if r[0] != 0)),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +251,17 @@ def main():
                     help="summarise a rocprofv3 --kernel-trace --stats run and exit")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in a profile summary (repeat per run)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
+    ap.add_argument("--requests", type=int, default=48, help="serving: runs in the mix")
+    ap.add_argument("--l-min", type=int, default=32, help="serving: smallest domain edge")
+    ap.add_argument("--l-max", type=int, default=64, help="serving: largest domain edge")
+    ap.add_argument("--steps-min", type=int, default=200, help="serving: fewest steps of a run")
+    ap.add_argument("--steps-max", type=int, default=800, help="serving: most steps of a run")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device pool (GiB)")
+    ap.add_argument("--slots", type=int, default=64, help="serving: resident runs at most")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="serving: Poisson rate as a fraction of the batched capacity")
     args = ap.parse_args()
     last = len(args.variants.split(",")) * min(args.steps, args.kernel_steps)
     if args.write_traffic:
@@ -235,6 +286,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.serving_only:
+        print(json.dumps(serving_section(args)))
+        return
     variants = [int(v) for v in args.variants.split(",")]
     setup_fn = lambda: I.workload(args.workload, **({"smagorinsky": args.les} if args.les else {}))  # noqa: E731
     base = setup_fn()
@@ -354,6 +408,11 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if not args.no_serving:
+        try:
+            out["serving"] = serving_section(args)
+        except Exception as e:  # the serving figures must never hide the step result
+            out["serving"] = {"error": repr(e)}
     print(json.dumps(out))
     bad = [k for k, v in per_variant.items() if v["status"] != "ok"]
     if bad:

@@ -162,6 +162,69 @@ const char* fslbm_strerror(int status);
  * when ctx is NULL). The pointer stays valid until the next call on ctx. */
 const char* fslbm_last_error(const fslbm_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Serving: many independent runs batched on one GPU.
+ *
+ * A server owns one device pool of hbm_budget_bytes (allocated at create) and
+ * up to max_slots resident runs. Submitted runs wait in a FIFO queue and are
+ * admitted, in order, while a slot is free and the pool has room for their
+ * workspace (fslbm_workspace_bytes); a run that can never fit is rejected at
+ * submit. Every resident run keeps its whole state in its part of the pool;
+ * each step phase is one launch covering all resident runs of the same
+ * population format, lattice and collision (one block range per run), so
+ * runs of different sizes, variants and parameters advance together. A run
+ * leaves when it has taken its steps: its mass report and fill levels are kept
+ * for fslbm_server_result, its memory and slot go to the next queued run.
+ * A run's results do not depend on which other runs share the launches (each
+ * run's cells are computed by the same code as in a single context).
+ * Runs with surface tension (sigma > 0) or the bubble model are not served
+ * (FSLBM_EINVAL at submit). The server is not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct fslbm_server fslbm_server;
+
+typedef struct {
+  int64_t queued, resident, completed, ticks;
+  uint64_t bytes_in_use, peak_bytes_in_use, budget_bytes;
+} fslbm_server_stats;
+
+/* hbm_budget_bytes: device pool size (hipMalloc'ed once); max_slots: resident
+ * runs at most (1..4096); hip_stream: stream of all server work (borrowed,
+ * NULL = default stream). Errors: FSLBM_EINVAL, FSLBM_ENOMEM. */
+int fslbm_server_create(size_t hbm_budget_bytes, int max_slots, void* hip_stream, fslbm_server** out);
+
+/* Queues one run of nsteps steps (> 0) from the given initial fields (the
+ * arrays of fslbm_create, copied: the caller may free them on return).
+ * req_id receives the run's id (increasing from 1). Errors: FSLBM_EINVAL
+ * (parameters, sigma > 0, bubble model, nsteps <= 0, workspace above the
+ * budget), FSLBM_ENOMEM (host memory). */
+int fslbm_server_submit(fslbm_server* srv, const fslbm_params* p, const uint8_t* type,
+                        const double* phi, const double* rho, const double* ux, const double* uy,
+                        const double* uz, int64_t nsteps, uint64_t* req_id);
+
+/* Runs up to `ticks` batched steps (a tick advances every resident run by one
+ * step), retiring finished runs and admitting queued ones between ticks as
+ * slots and pool memory free up; returns early when nothing is resident or
+ * queued. Waits for the device only where a run finishes. Errors:
+ * FSLBM_EDEVICE (the server is unusable afterwards). */
+int fslbm_server_advance(fslbm_server* srv, int64_t ticks);
+
+/* Ids and statuses (FSLBM_OK, or FSLBM_EUNSTABLE for a run that became
+ * unstable) of runs finished since the last poll, at most max; n_done
+ * receives the number written. */
+int fslbm_server_poll(fslbm_server* srv, uint64_t* done_ids, int* statuses, int max, int* n_done);
+
+/* Mass report and, if phi_out is not NULL, the N fill levels of a finished
+ * run; releases the stored result. Errors: FSLBM_EINVAL (unknown or not yet
+ * finished id). */
+int fslbm_server_result(fslbm_server* srv, uint64_t req_id, fslbm_mass_report* report,
+                        double* phi_out);
+
+/* Counters of the server (queue length, resident runs, pool use). */
+int fslbm_server_stats_get(const fslbm_server* srv, fslbm_server_stats* out);
+
+/* Releases every run and the pool (NULL-safe). */
+void fslbm_server_destroy(fslbm_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

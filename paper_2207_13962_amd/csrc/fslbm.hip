@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -482,6 +484,412 @@ const char* fslbm_strerror(int status) {
 const char* fslbm_last_error(const fslbm_ctx* c) {
   if (!c) return g_create_error;
   return c->last_error.c_str();
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving: runs of a batch share each step launch (see include/fslbm.h).
+// ===========================================================================
+namespace {
+
+// First-fit allocator over the server's device pool, 256-byte granules.
+class Pool {
+ public:
+  explicit Pool(size_t size) : size_(size) { free_.push_back({0, size}); }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = (size_t)round_up((int64_t)bytes, 256);
+    for (size_t i = 0; i < free_.size(); ++i) {
+      if (free_[i].size < bytes) continue;
+      *off = free_[i].off;
+      free_[i].off += bytes;
+      free_[i].size -= bytes;
+      if (free_[i].size == 0) free_.erase(free_.begin() + (long)i);
+      used_ += bytes;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (size_t)round_up((int64_t)bytes, 256);
+    used_ -= bytes;
+    auto it = std::lower_bound(free_.begin(), free_.end(), off,
+                               [](const Span& a, size_t o) { return a.off < o; });
+    it = free_.insert(it, {off, bytes});
+    // coalesce with the neighbours
+    const size_t i = (size_t)(it - free_.begin());
+    if (i + 1 < free_.size() && free_[i].off + free_[i].size == free_[i + 1].off) {
+      free_[i].size += free_[i + 1].size;
+      free_.erase(free_.begin() + (long)i + 1);
+    }
+    if (i > 0 && free_[i - 1].off + free_[i - 1].size == free_[i].off) {
+      free_[i - 1].size += free_[i].size;
+      free_.erase(free_.begin() + (long)i);
+    }
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  struct Span {
+    size_t off, size;
+  };
+  size_t size_, used_ = 0;
+  std::vector<Span> free_;
+};
+
+struct PendingRun {
+  uint64_t id;
+  fslbm_params p;
+  std::vector<uint8_t> type;
+  std::vector<double> phi, rho, ux, uy, uz;
+  int64_t nsteps;
+  size_t bytes;
+};
+
+struct ResidentRun {
+  uint64_t id;
+  fslbm_ctx* ctx;
+  size_t off, bytes;
+  int64_t tick0, nsteps;
+  int slot, group;
+};
+
+struct DoneRun {
+  int status;
+  fslbm_mass_report rep;
+  std::vector<double> phi;
+};
+
+// launch groups: storage (3) x lattice (2) x collision (2) x addressing (2)
+constexpr int kGroups = 24;
+
+int group_of(const fslbm_params& p, bool buf) {
+  return ((p.storage * 2 + (p.q == 27 ? 1 : 0)) * 2 + (p.collision == FSLBM_TRT ? 1 : 0)) * 2 + (buf ? 1 : 0);
+}
+
+bool grid_fits_buffer(const fslbm_ctx* c) {
+  return (double)c->p.q * (double)c->L.stride * storage_bytes(c->p.storage) < 2147483648.0;
+}
+
+int round8(int64_t b) { return (int)std::max<int64_t>(kXcds, (b + kXcds - 1) / kXcds * kXcds); }
+
+}  // namespace
+
+struct fslbm_server {
+  size_t budget = 0;
+  int max_slots = 0;
+  hipStream_t stream = nullptr;
+  char* pool_mem = nullptr;
+  Pool* pool = nullptr;
+  Dev* d_devs = nullptr;          // max_slots Dev records
+  BatchEntry* d_tab = nullptr;    // kGroups x 4 x max_slots entries
+  BatchEntry* h_tab = nullptr;    // pinned staging of the same
+  std::vector<int> free_slots;
+  std::deque<PendingRun> queue;
+  std::vector<ResidentRun> resident;
+  std::map<uint64_t, DoneRun> done;
+  std::vector<std::pair<uint64_t, int>> unpolled;
+  BatchLaunch launch[kGroups];
+  bool dirty = true;
+  uint64_t next_id = 1;
+  int64_t tick = 0, completed = 0;
+  size_t peak = 0;
+  int status = FSLBM_OK;
+};
+
+namespace {
+
+int srv_fail(fslbm_server* s, hipError_t e) {
+  (void)e;
+  s->status = FSLBM_EDEVICE;
+  return FSLBM_EDEVICE;
+}
+
+// Block ranges of one run in the four launches of a batched step.
+void run_blocks(const fslbm_ctx* c, int nb[4], int stream_split[2], int compact_args[2]) {
+  const int gen = round8(std::min<int64_t>(if_blocks(c), 192));
+  const int bord = round8(std::min<int64_t>(border_blocks(c), 64));
+  const int liq = round8(std::min<int64_t>(liquid_blocks(c), 256));
+  stream_split[0] = gen;
+  stream_split[1] = bord;
+  nb[0] = gen + bord + liq;
+  // (only the streaming launch needs XCD-aligned ranges; the compaction needs
+  // exactly one block per tile beside its workers)
+  nb[1] = (int)std::min<int64_t>(retype_blocks(c), 64);
+  const int workers = (int)(std::min<int64_t>(retype_blocks(c), 64) + 3) / 4;
+  compact_args[0] = (int)c->L.conv_per;
+  compact_args[1] = workers;
+  nb[2] = (int)c->L.tiles + workers;
+  nb[3] = (int)std::min<int64_t>(finish_blocks(c), 128);
+}
+
+// Tables of every group from the resident runs.
+int rebuild_plan(fslbm_server* s) {
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return srv_fail(s, hipErrorUnknown);
+  for (int g = 0; g < kGroups; ++g) {
+    BatchLaunch& bl = s->launch[g];
+    bl = BatchLaunch{};
+    bl.devs = s->d_devs;
+    bl.buf = (g & 1) != 0;
+    int cursor[4] = {0, 0, 0, 0};
+    for (const ResidentRun& r : s->resident) {
+      if (r.group != g) continue;
+      int nb[4], split[2], cargs[2];
+      run_blocks(r.ctx, nb, split, cargs);
+      for (int k = 0; k < 4; ++k) {
+        BatchEntry& e = s->h_tab[((size_t)g * 4 + k) * s->max_slots + bl.n];
+        e.slot = r.slot;
+        e.blk0 = cursor[k];
+        e.nblk = nb[k];
+        e.a = k == 0 ? split[0] : (k == 2 ? cargs[0] : 0);
+        e.b = k == 0 ? split[1] : (k == 2 ? cargs[1] : 0);
+        e.pad = 0;
+        e.tick0 = r.tick0;
+        e.nsteps = r.nsteps;
+        cursor[k] += nb[k];
+      }
+      ++bl.n;
+    }
+    for (int k = 0; k < 4; ++k) {
+      bl.blocks[k] = cursor[k];
+      bl.tab[k] = s->d_tab + ((size_t)g * 4 + k) * s->max_slots;
+      if (bl.n > 0 &&
+          hipMemcpyAsync(const_cast<BatchEntry*>(bl.tab[k]), s->h_tab + ((size_t)g * 4 + k) * s->max_slots,
+                         sizeof(BatchEntry) * bl.n, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        return srv_fail(s, hipErrorUnknown);
+    }
+  }
+  s->dirty = false;
+  return FSLBM_OK;
+}
+
+// Runs that have taken all their steps: results out, memory and slot back.
+int retire_finished(fslbm_server* s) {
+  bool any = false;
+  for (const ResidentRun& r : s->resident) any |= s->tick >= r.tick0 + r.nsteps;
+  if (!any) return FSLBM_OK;
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return srv_fail(s, hipErrorUnknown);
+  std::vector<ResidentRun> keep;
+  for (ResidentRun& r : s->resident) {
+    if (s->tick < r.tick0 + r.nsteps) {
+      keep.push_back(r);
+      continue;
+    }
+    fslbm_ctx* c = r.ctx;
+    // the host view of a single run after nsteps steps
+    c->step = r.nsteps;
+    if (r.nsteps & 1) {
+      std::swap(c->d.fA, c->d.fB);
+      std::swap(c->d.phiA, c->d.phiB);
+    }
+    DoneRun dr;
+    dr.status = fslbm_mass(c, &dr.rep);
+    if (dr.status == FSLBM_EDEVICE) return srv_fail(s, hipErrorUnknown);
+    dr.phi.resize((size_t)c->L.N);
+    const int fs = fslbm_fields(c, nullptr, dr.phi.data(), nullptr, nullptr, nullptr, nullptr, nullptr,
+                                nullptr);
+    if (fs == FSLBM_EDEVICE) return srv_fail(s, hipErrorUnknown);
+    if (dr.status == FSLBM_OK) dr.status = fs;
+    fslbm_destroy(c);
+    s->pool->release(r.off, r.bytes);
+    s->free_slots.push_back(r.slot);
+    s->unpolled.push_back({r.id, dr.status});
+    s->done[r.id] = std::move(dr);
+    ++s->completed;
+  }
+  s->resident.swap(keep);
+  s->dirty = true;
+  return FSLBM_OK;
+}
+
+// Queued runs, in order, while a slot and pool memory are free.
+int admit_queued(fslbm_server* s) {
+  while (!s->queue.empty() && !s->free_slots.empty()) {
+    PendingRun& q = s->queue.front();
+    size_t off;
+    if (!s->pool->alloc(q.bytes, &off)) break;
+    fslbm_ctx* c = nullptr;
+    const int st = fslbm_create(&q.p, q.type.data(), q.phi.data(), q.rho.data(), q.ux.data(), q.uy.data(),
+                                q.uz.data(), nullptr, nullptr, s->pool_mem + off, q.bytes, s->stream, &c);
+    if (st != FSLBM_OK) {
+      s->pool->release(off, q.bytes);
+      // a run whose initial state is rejected finishes at once with the error
+      DoneRun dr;
+      dr.status = st;
+      std::memset(&dr.rep, 0, sizeof dr.rep);
+      s->unpolled.push_back({q.id, st});
+      s->done[q.id] = std::move(dr);
+      ++s->completed;
+      s->queue.pop_front();
+      continue;
+    }
+    ResidentRun r;
+    r.id = q.id;
+    r.ctx = c;
+    r.off = off;
+    r.bytes = q.bytes;
+    r.tick0 = s->tick;
+    r.nsteps = q.nsteps;
+    r.slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    r.group = group_of(c->p, grid_fits_buffer(c));
+    if (hipMemcpyAsync(s->d_devs + r.slot, &c->d, sizeof(Dev), hipMemcpyHostToDevice, s->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return srv_fail(s, hipErrorUnknown);
+    s->resident.push_back(r);
+    s->queue.pop_front();
+    s->peak = std::max(s->peak, s->pool->used());
+    s->dirty = true;
+  }
+  return FSLBM_OK;
+}
+
+void free_server(fslbm_server* s) {
+  for (ResidentRun& r : s->resident) fslbm_destroy(r.ctx);
+  if (s->d_devs) (void)hipFree(s->d_devs);
+  if (s->d_tab) (void)hipFree(s->d_tab);
+  if (s->h_tab) (void)hipHostFree(s->h_tab);
+  if (s->pool_mem) (void)hipFree(s->pool_mem);
+  delete s->pool;
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fslbm_server_create(size_t hbm_budget_bytes, int max_slots, void* hip_stream, fslbm_server** out) {
+  if (!out) return FSLBM_EINVAL;
+  *out = nullptr;
+  if (hbm_budget_bytes < 4096 || max_slots < 1 || max_slots > 4096) return FSLBM_EINVAL;
+  fslbm_server* s = new (std::nothrow) fslbm_server();
+  if (!s) return FSLBM_ENOMEM;
+  s->budget = hbm_budget_bytes;
+  s->max_slots = max_slots;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  const size_t tab = sizeof(BatchEntry) * (size_t)kGroups * 4 * (size_t)max_slots;
+  if (hipMalloc(reinterpret_cast<void**>(&s->pool_mem), hbm_budget_bytes) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&s->d_devs), sizeof(Dev) * (size_t)max_slots) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&s->d_tab), tab) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&s->h_tab), tab, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    free_server(s);
+    return FSLBM_ENOMEM;
+  }
+  s->pool = new (std::nothrow) Pool(hbm_budget_bytes);
+  if (!s->pool) {
+    free_server(s);
+    return FSLBM_ENOMEM;
+  }
+  for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+  *out = s;
+  return FSLBM_OK;
+}
+
+int fslbm_server_submit(fslbm_server* s, const fslbm_params* p, const uint8_t* type, const double* phi,
+                        const double* rho, const double* ux, const double* uy, const double* uz,
+                        int64_t nsteps, uint64_t* req_id) {
+  if (!s || !req_id || !type || !phi || !rho || !ux || !uy || !uz || nsteps <= 0) return FSLBM_EINVAL;
+  if (validate(p)) return FSLBM_EINVAL;
+  if (p->sigma != 0.0 || p->bubble_model != 0) return FSLBM_EINVAL;
+  const size_t bytes = make_layout(*p).total;
+  if ((size_t)round_up((int64_t)bytes, 256) > s->budget) return FSLBM_EINVAL;
+  PendingRun q;
+  try {
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    q.type.assign(type, type + N);
+    q.phi.assign(phi, phi + N);
+    q.rho.assign(rho, rho + N);
+    q.ux.assign(ux, ux + N);
+    q.uy.assign(uy, uy + N);
+    q.uz.assign(uz, uz + N);
+  } catch (...) {
+    return FSLBM_ENOMEM;
+  }
+  q.id = s->next_id++;
+  q.p = *p;
+  q.nsteps = nsteps;
+  q.bytes = bytes;
+  *req_id = q.id;
+  s->queue.push_back(std::move(q));
+  return FSLBM_OK;
+}
+
+int fslbm_server_advance(fslbm_server* s, int64_t ticks) {
+  if (!s || ticks < 0) return FSLBM_EINVAL;
+  if (s->status != FSLBM_OK) return s->status;
+  int64_t left = ticks;
+  for (;;) {
+    int st = retire_finished(s);
+    if (st != FSLBM_OK) return st;
+    st = admit_queued(s);
+    if (st != FSLBM_OK) return st;
+    if (s->resident.empty() || left <= 0) return FSLBM_OK;
+    if (s->dirty && (st = rebuild_plan(s)) != FSLBM_OK) return st;
+    // ticks until the next run finishes
+    int64_t chunk = left;
+    for (const ResidentRun& r : s->resident) chunk = std::min(chunk, r.tick0 + r.nsteps - s->tick);
+    for (int64_t i = 0; i < chunk; ++i) {
+      for (int g = 0; g < kGroups; ++g) {
+        const BatchLaunch& bl = s->launch[g];
+        if (bl.n == 0) continue;
+        const fslbm_params* p = nullptr;
+        for (const ResidentRun& r : s->resident)
+          if (r.group == g) {
+            p = &r.ctx->p;
+            break;
+          }
+        pick(*p).batch_step(bl, s->stream, s->tick);
+      }
+      ++s->tick;
+    }
+    if (hipGetLastError() != hipSuccess) return srv_fail(s, hipErrorUnknown);
+    left -= chunk;
+  }
+}
+
+int fslbm_server_poll(fslbm_server* s, uint64_t* done_ids, int* statuses, int max, int* n_done) {
+  if (!s || !n_done || max < 0 || (max > 0 && (!done_ids || !statuses))) return FSLBM_EINVAL;
+  const int n = (int)std::min<size_t>((size_t)max, s->unpolled.size());
+  for (int i = 0; i < n; ++i) {
+    done_ids[i] = s->unpolled[(size_t)i].first;
+    statuses[i] = s->unpolled[(size_t)i].second;
+  }
+  s->unpolled.erase(s->unpolled.begin(), s->unpolled.begin() + n);
+  *n_done = n;
+  return FSLBM_OK;
+}
+
+int fslbm_server_result(fslbm_server* s, uint64_t req_id, fslbm_mass_report* report, double* phi_out) {
+  if (!s) return FSLBM_EINVAL;
+  auto it = s->done.find(req_id);
+  if (it == s->done.end()) return FSLBM_EINVAL;
+  if (report) *report = it->second.rep;
+  if (phi_out && !it->second.phi.empty())
+    std::memcpy(phi_out, it->second.phi.data(), sizeof(double) * it->second.phi.size());
+  s->done.erase(it);
+  return FSLBM_OK;
+}
+
+int fslbm_server_stats_get(const fslbm_server* s, fslbm_server_stats* out) {
+  if (!s || !out) return FSLBM_EINVAL;
+  out->queued = (int64_t)s->queue.size();
+  out->resident = (int64_t)s->resident.size();
+  out->completed = s->completed;
+  out->ticks = s->tick;
+  out->bytes_in_use = s->pool->used();
+  out->peak_bytes_in_use = s->peak;
+  out->budget_bytes = s->budget;
+  return FSLBM_OK;
+}
+
+void fslbm_server_destroy(fslbm_server* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  else (void)hipDeviceSynchronize();
+  free_server(s);
 }
 
 }  // extern "C"

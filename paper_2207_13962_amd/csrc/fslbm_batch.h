@@ -1,0 +1,96 @@
+// Batched launches for serving: one launch of each step kernel covers every
+// resident run of a batch. Run r owns the blocks [blk0, blk0 + nblk) of the
+// launch (blk0 a multiple of the XCD count), and its own device arena, Dev
+// record and counters; a block finds its run in a table sorted by blk0. A
+// run admitted at tick tick0 is at its own step tick - tick0: the parity of
+// that step picks which of its two population grids and fill-level buffers
+// is read, exactly as the host-side pointer swap does for a single run, so a
+// run's arithmetic does not depend on what else shares the launch. Runs past
+// their last step return at once (the host retires them between ticks).
+#pragma once
+
+#include "fslbm_kernels.h"
+
+namespace fslbm {
+
+struct BatchEntry {
+  int32_t slot;    // index of the run's Dev record
+  int32_t blk0;    // first block of the run in this launch
+  int32_t nblk;    // blocks of the run in this launch
+  int32_t a, b;    // per kernel: stream (gen, bord); compact (per, workers)
+  int32_t pad;
+  int64_t tick0;   // tick of the run's step 0
+  int64_t nsteps;  // steps the run takes
+};
+
+// The table entry of this block (binary search over blk0).
+__device__ __forceinline__ BatchEntry batch_entry(const BatchEntry* tab, int n) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].blk0 <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return tab[lo];
+}
+
+// The run's Dev at this tick (grids and fill levels swapped on odd steps);
+// false when the block lies past the run's range or the run is done.
+__device__ __forceinline__ bool batch_dev(const Dev* devs, const BatchEntry& e, int64_t tick, Dev& d) {
+  const int b = (int)blockIdx.x - e.blk0;
+  if (b < 0 || b >= e.nblk) return false;
+  const int64_t step = tick - e.tick0;
+  if (step < 0 || step >= e.nsteps) return false;
+  d = devs[e.slot];
+  if (step & 1) {
+    void* t = d.fA;
+    d.fA = d.fB;
+    d.fB = t;
+    double* p = d.phiA;
+    d.phiA = d.phiB;
+    d.phiB = p;
+  }
+  d.step = step;
+  return true;
+}
+
+template <int S, int Q, bool TRT, bool BUF>
+__global__ __launch_bounds__(kBlock) void kb_stream(const Dev* devs, const BatchEntry* tab, int n,
+                                                    int64_t tick) {
+  const BatchEntry e = batch_entry(tab, n);
+  Dev d;
+  if (!batch_dev(devs, e, tick, d)) return;
+  stream_body<S, Q, TRT, BUF>(d, (int)blockIdx.x - e.blk0, e.nblk, e.a, e.b);
+}
+
+template <int Q>
+__global__ __launch_bounds__(kBlock) void kb_retype(const Dev* devs, const BatchEntry* tab, int n,
+                                                    int64_t tick) {
+  const BatchEntry e = batch_entry(tab, n);
+  Dev d;
+  if (!batch_dev(devs, e, tick, d)) return;
+  retype_body<Q>(d, (int)blockIdx.x - e.blk0, e.nblk, 0);
+}
+
+template <int S, int Q, bool TRT>
+__global__ __launch_bounds__(kCompBlock) void kb_compact(const Dev* devs, const BatchEntry* tab, int n,
+                                                         int64_t tick) {
+  const BatchEntry e = batch_entry(tab, n);
+  Dev d;
+  if (!batch_dev(devs, e, tick, d)) return;
+  compact_body<S, Q, TRT>(d, (int)blockIdx.x - e.blk0, e.nblk, 0, e.a, e.b);
+}
+
+template <int S, int Q, bool TRT>
+__global__ __launch_bounds__(kBlock) void kb_finish(const Dev* devs, const BatchEntry* tab, int n,
+                                                    int64_t tick) {
+  const BatchEntry e = batch_entry(tab, n);
+  Dev d;
+  if (!batch_dev(devs, e, tick, d)) return;
+  finish_body<S, Q, TRT>(d, (int)blockIdx.x - e.blk0, e.nblk, 0);
+}
+
+}  // namespace fslbm

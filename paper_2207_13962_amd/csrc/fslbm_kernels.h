@@ -576,19 +576,25 @@ __device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk) {
 // (the ALU-heavy interface groups overlap the bandwidth-bound liquid waves).
 // Blocks [0, gen) take interface cells, [gen, gen + bord) the liquid cells
 // next to walls or obstacles, the rest the liquid chunks.
+// (Block b of nb blocks of one run; the kernels below are written this way so
+// that one launch can also serve many runs, each with its own block range.)
 template <int S, int Q, bool TRT, bool BUF>
-__global__ __launch_bounds__(kBlock) void k_stream(Dev d, int gen, int bord) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+__device__ __forceinline__ void stream_body(const Dev& d, int b, int nb, int gen, int bord) {
+  if (b == 0 && threadIdx.x == 0) {
     d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // mark slot of the next step
     d.cnt[CNT_NG] = 0;                          // new-gas list of this step
   }
-  const int b = (int)blockIdx.x;
   if (b < gen)
     generic_role<S, Q, TRT>(d, b, gen);
   else if (b < gen + bord)
     border_role<S, Q, TRT>(d, b - gen, bord);
   else
-    liquid_role<S, Q, TRT, BUF>(d, b - gen - bord, (int)gridDim.x - gen - bord);
+    liquid_role<S, Q, TRT, BUF>(d, b - gen - bord, nb - gen - bord);
+}
+
+template <int S, int Q, bool TRT, bool BUF>
+__global__ __launch_bounds__(kBlock) void k_stream(Dev d, int gen, int bord) {
+  stream_body<S, Q, TRT, BUF>(d, (int)blockIdx.x, (int)gridDim.x, gen, bord);
 }
 
 // ---------------------------------------------------------------------------
@@ -624,15 +630,15 @@ __device__ __forceinline__ bool set_new_gas(uint8_t* flags, int64_t j) {
 // Block 0 also starts the compaction that follows: ticket counter reset and,
 // when the compaction will run, a new epoch for its tile-status words.
 template <int Q>
-__global__ __launch_bounds__(kBlock) void k_retype(Dev d, int rebuild_only) {
+__device__ __forceinline__ void retype_body(const Dev& d, int b, int nb, int rebuild_only) {
   const int nmk = rebuild_only ? 0 : d.cnt[CNT_MARK0 + (d.step & 1)];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (b == 0 && threadIdx.x == 0) {
     d.cnt[CNT_TICKET] = 0;
     if (rebuild_only || nmk > 0) d.cnt[CNT_EPOCH] += 1;
   }
   const int l = threadIdx.x & (kG - 1);
-  const int ngroups = gridDim.x * (kBlock / kG);
-  for (int item = blockIdx.x * (kBlock / kG) + threadIdx.x / kG; item < nmk; item += ngroups) {
+  const int ngroups = nb * (kBlock / kG);
+  for (int item = b * (kBlock / kG) + threadIdx.x / kG; item < nmk; item += ngroups) {
     const int64_t c = d.mark_list[item];
     const uint8_t mk = d.mark[c];
     int x, y, z;
@@ -657,6 +663,11 @@ __global__ __launch_bounds__(kBlock) void k_retype(Dev d, int rebuild_only) {
       if (j >= 0 && (fj & T_MASK) == T_LIQ) d.flags[j] = (uint8_t)((fj & F_STATIC) | T_IF | F_NEW_LIQ);
     }
   }
+}
+
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_retype(Dev d, int rebuild_only) {
+  retype_body<Q>(d, (int)blockIdx.x, (int)gridDim.x, rebuild_only);
 }
 
 // Block-wide exclusive scan of a per-thread count (wave prefix by shuffles,
@@ -827,25 +838,26 @@ __device__ __forceinline__ unsigned long long pack2(uint32_t epoch, uint32_t a, 
 // without marks (the lists are unchanged then).
 // The first `workers` blocks do the other work that k_finish waits for.
 template <int S, int Q, bool TRT>
-__global__ __launch_bounds__(kCompBlock) void k_compact(Dev d, int rebuild_only, int per, int workers) {
+__device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int rebuild_only, int per,
+                                             int workers) {
   __shared__ int s_tile, s_run;
   __shared__ uint32_t s_epoch;
   __shared__ uint32_t s_scan[4][kCompBlock / 64];
   __shared__ uint32_t s_red[4][kCompBlock / 64];
-  if ((int)blockIdx.x < workers) {
+  if (b < workers) {
     // worker blocks, beside the compaction: the converted cells (the marked
     // cells that carry the converted bit) get their excess-mass share, the new
     // interface cells from gas their reinitialisation
     if (rebuild_only) return;
     const int nmk = d.cnt[CNT_MARK0 + (d.step & 1)];
     const int nng = d.cnt[CNT_NG];
-    for (int i = blockIdx.x * kCompBlock + threadIdx.x; i < nmk; i += workers * kCompBlock) {
+    for (int i = b * kCompBlock + threadIdx.x; i < nmk; i += workers * kCompBlock) {
       const int64_t zc = d.mark_list[i];
       if (d.flags[zc] & F_CONV) finish_converted<Q>(d, zc);
     }
     const int l = threadIdx.x & (kG - 1);
     const int ngroups = workers * (kCompBlock / kG);
-    for (int item = blockIdx.x * (kCompBlock / kG) + threadIdx.x / kG; item < nng; item += ngroups)
+    for (int item = b * (kCompBlock / kG) + threadIdx.x / kG; item < nng; item += ngroups)
       reinit_from_gas<S, Q, TRT>(d, d.ng_list[item], l);
     return;
   }
@@ -1010,12 +1022,17 @@ __global__ __launch_bounds__(kCompBlock) void k_compact(Dev d, int rebuild_only,
     }
   }
   if (per < 64 && c[2]) d.chunk_list[off[2]] = (int32_t)(base / 64);
-  if (tile == (int)gridDim.x - workers - 1 && threadIdx.x == kCompBlock - 1) {
+  if (tile == nb - workers - 1 && threadIdx.x == kCompBlock - 1) {
     d.cnt[CNT_IF] = (int32_t)off[0];
     d.cnt[CNT_CONV] = (int32_t)off[1];
     d.cnt[CNT_GEN] = (int32_t)off[3];
     d.cnt[CNT_CHUNKS] = (int32_t)chunks_end;
   }
+}
+
+template <int S, int Q, bool TRT>
+__global__ __launch_bounds__(kCompBlock) void k_compact(Dev d, int rebuild_only, int per, int workers) {
+  compact_body<S, Q, TRT>(d, (int)blockIdx.x, (int)gridDim.x, rebuild_only, per, workers);
 }
 
 // ---------------------------------------------------------------------------
@@ -1092,11 +1109,16 @@ __device__ __forceinline__ void finish_interface(const Dev& d, int64_t c, bool c
 }
 
 template <int S, int Q, bool TRT>
-__global__ __launch_bounds__(kBlock) void k_finish(Dev d, int classes_only) {
+__device__ __forceinline__ void finish_body(const Dev& d, int b, int nb, int classes_only) {
   if (!classes_only && d.cnt[CNT_MARK0 + (d.step & 1)] == 0) return;
   const int nif = d.cnt[CNT_IF];
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nif; i += gridDim.x * kBlock)
+  for (int i = b * kBlock + threadIdx.x; i < nif; i += nb * kBlock)
     finish_interface<S, Q, TRT>(d, d.if_list[i], classes_only != 0);
+}
+
+template <int S, int Q, bool TRT>
+__global__ __launch_bounds__(kBlock) void k_finish(Dev d, int classes_only) {
+  finish_body<S, Q, TRT>(d, (int)blockIdx.x, (int)gridDim.x, classes_only);
 }
 
 // ---------------------------------------------------------------------------

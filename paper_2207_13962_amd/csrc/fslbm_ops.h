@@ -12,6 +12,7 @@
 #include "fslbm.h"
 #include <hip/hip_ext.h>
 #include "fslbm_kernels.h"
+#include "fslbm_batch.h"
 
 using namespace fslbm;
 
@@ -165,12 +166,23 @@ inline unsigned finish_blocks(const fslbm_ctx* c) {
   return (unsigned)std::min<int64_t>(b, 512);
 }
 
+// One batched step over the resident runs of one (storage, lattice,
+// collision, addressing) group: device tables of the four launches.
+struct BatchLaunch {
+  const Dev* devs = nullptr;
+  const BatchEntry* tab[4] = {nullptr, nullptr, nullptr, nullptr};  // stream, retype, compact, finish
+  int n = 0;                       // entries of each table (one per run)
+  int blocks[4] = {0, 0, 0, 0};    // blocks of each launch
+  bool buf = true;                 // buffer addressing (every grid below 2 GiB)
+};
+
 // Kernel table for one (storage, lattice, collision) combination.
 struct Ops {
   void (*step)(fslbm_ctx*, hipStream_t);
   void (*convert)(fslbm_ctx*, hipStream_t, int rebuild_only);
   void (*finish)(fslbm_ctx*, hipStream_t, int classes_only);
   void (*reduce_mass)(fslbm_ctx*, hipStream_t);
+  void (*batch_step)(const BatchLaunch&, hipStream_t, int64_t tick);
   void (*init_state)(fslbm_ctx*, hipStream_t, int resume);
   void (*init_flags)(fslbm_ctx*, hipStream_t);
   void (*import_plane)(fslbm_ctx*, hipStream_t, const double*, int);
@@ -215,6 +227,21 @@ struct Impl {
     hipLaunchKernelGGL((k_finish<S, Q, TRT>), dim3(finish_blocks(c)), dim3(kBlock), 0, s, c->d,
                        classes_only);
   }
+  static void batch_step(const BatchLaunch& bl, hipStream_t s, int64_t tick) {
+    if (bl.n == 0) return;
+    if (bl.buf)
+      hipLaunchKernelGGL((kb_stream<S, Q, TRT, true>), dim3((unsigned)bl.blocks[0]), dim3(kBlock), 0, s,
+                         bl.devs, bl.tab[0], bl.n, tick);
+    else
+      hipLaunchKernelGGL((kb_stream<S, Q, TRT, false>), dim3((unsigned)bl.blocks[0]), dim3(kBlock), 0, s,
+                         bl.devs, bl.tab[0], bl.n, tick);
+    hipLaunchKernelGGL((kb_retype<Q>), dim3((unsigned)bl.blocks[1]), dim3(kBlock), 0, s, bl.devs, bl.tab[1],
+                       bl.n, tick);
+    hipLaunchKernelGGL((kb_compact<S, Q, TRT>), dim3((unsigned)bl.blocks[2]), dim3(kCompBlock), 0, s,
+                       bl.devs, bl.tab[2], bl.n, tick);
+    hipLaunchKernelGGL((kb_finish<S, Q, TRT>), dim3((unsigned)bl.blocks[3]), dim3(kBlock), 0, s, bl.devs,
+                       bl.tab[3], bl.n, tick);
+  }
   static void reduce_mass(fslbm_ctx* c, hipStream_t s) {
     hipLaunchKernelGGL((k_reduce_mass<S, Q>), dim3((unsigned)c->L.red_blocks), dim3(kBlock), 0, s,
                        c->d, kRedCells);
@@ -235,7 +262,7 @@ struct Impl {
                        what);
   }
   static constexpr Ops ops() {
-    return Ops{&step, &convert, &finish, &reduce_mass, &init_state, &init_flags, &import_plane,
+    return Ops{&step, &convert, &finish, &reduce_mass, &batch_step, &init_state, &init_flags, &import_plane,
                &export_field};
   }
 };

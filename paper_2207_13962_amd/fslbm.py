@@ -52,7 +52,15 @@ _lib = None
 EXPORTED = ["fslbm_workspace_bytes", "fslbm_create", "fslbm_set_variant", "fslbm_step",
             "fslbm_mass", "fslbm_fields", "fslbm_interface_list", "fslbm_set_timing",
             "fslbm_kernel_time", "fslbm_set_graphs", "fslbm_destroy", "fslbm_strerror",
-            "fslbm_last_error"]
+            "fslbm_last_error", "fslbm_server_create", "fslbm_server_submit",
+            "fslbm_server_advance", "fslbm_server_poll", "fslbm_server_result",
+            "fslbm_server_stats_get", "fslbm_server_destroy"]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("resident", C.c_int64), ("completed", C.c_int64),
+                ("ticks", C.c_int64), ("bytes_in_use", C.c_uint64),
+                ("peak_bytes_in_use", C.c_uint64), ("budget_bytes", C.c_uint64)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -91,6 +99,22 @@ def load_library(path: str = LIB_PATH):
     lib.fslbm_strerror.restype = C.c_char_p
     lib.fslbm_last_error.argtypes = [vp]
     lib.fslbm_last_error.restype = C.c_char_p
+    lib.fslbm_server_create.argtypes = [C.c_size_t, C.c_int, vp, C.POINTER(vp)]
+    lib.fslbm_server_create.restype = C.c_int
+    lib.fslbm_server_submit.argtypes = [vp, C.POINTER(Params), u8p, dp, dp, dp, dp, dp, C.c_int64,
+                                        C.POINTER(C.c_uint64)]
+    lib.fslbm_server_submit.restype = C.c_int
+    lib.fslbm_server_advance.argtypes = [vp, C.c_int64]
+    lib.fslbm_server_advance.restype = C.c_int
+    lib.fslbm_server_poll.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_int), C.c_int,
+                                      C.POINTER(C.c_int)]
+    lib.fslbm_server_poll.restype = C.c_int
+    lib.fslbm_server_result.argtypes = [vp, C.c_uint64, C.POINTER(MassReport), dp]
+    lib.fslbm_server_result.restype = C.c_int
+    lib.fslbm_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.fslbm_server_stats_get.restype = C.c_int
+    lib.fslbm_server_destroy.argtypes = [vp]
+    lib.fslbm_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -235,3 +259,83 @@ class Simulation:
 
     def synchronize(self):
         self._stream.synchronize()
+
+
+class Server:
+    """Batched serving of many independent runs on one GPU (fslbm_server_*).
+
+    budget_bytes: device pool for the resident runs; max_slots: resident runs
+    at most. All work goes to torch's current stream of `device` (or `stream`).
+    """
+
+    def __init__(self, budget_bytes, max_slots=64, device="cuda:0", stream=None):
+        import torch
+
+        self._lib = load_library()
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = self._lib.fslbm_server_create(int(budget_bytes), int(max_slots),
+                                           C.c_void_p(self._stream.cuda_stream), C.byref(h))
+        if st != OK:
+            raise FslbmError(st, "fslbm_server_create failed")
+        self._h = h
+        self._n = {}
+
+    def submit(self, setup, nsteps):
+        """Queue one run; returns its id."""
+        p = setup.params
+        arrays = [np.ascontiguousarray(setup.type, dtype=np.uint8)]
+        arrays += [np.ascontiguousarray(a, dtype=np.float64) for a in
+                   (setup.phi, setup.rho, setup.ux, setup.uy, setup.uz)]
+        rid = C.c_uint64()
+        st = self._lib.fslbm_server_submit(self._h, C.byref(make_params(p)), _u8(arrays[0]),
+                                           *[_dp(a) for a in arrays[1:]], int(nsteps), C.byref(rid))
+        if st != OK:
+            raise FslbmError(st, "fslbm_server_submit rejected the run")
+        self._n[rid.value] = p.n
+        return rid.value
+
+    def advance(self, ticks):
+        """Run up to `ticks` batched steps (admitting and retiring runs)."""
+        st = self._lib.fslbm_server_advance(self._h, int(ticks))
+        if st != OK:
+            raise FslbmError(st, "fslbm_server_advance failed")
+
+    def poll(self, max_n=4096):
+        """[(id, status)] of runs finished since the last poll."""
+        ids = (C.c_uint64 * max_n)()
+        sts = (C.c_int * max_n)()
+        n = C.c_int()
+        st = self._lib.fslbm_server_poll(self._h, ids, sts, max_n, C.byref(n))
+        if st != OK:
+            raise FslbmError(st, "fslbm_server_poll failed")
+        return [(ids[i], sts[i]) for i in range(n.value)]
+
+    def result(self, rid, phi=True):
+        """(mass report dict, fill levels or None) of a finished run; frees it."""
+        r = MassReport()
+        out = np.zeros(self._n[rid]) if phi else None
+        st = self._lib.fslbm_server_result(self._h, int(rid), C.byref(r), _dp(out))
+        if st != OK:
+            raise FslbmError(st, "no finished run %d" % rid)
+        del self._n[rid]
+        return r.as_dict(), out
+
+    def stats(self):
+        s = ServerStats()
+        self._lib.fslbm_server_stats_get(self._h, C.byref(s))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None:
+            self._lib.fslbm_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -412,7 +412,8 @@ def workload(name: str, smagorinsky: float = 0.0, **kw) -> Setup:
 def serving_mix(n_requests=512, seed=1234, rate=None, l_min=48, l_max=192, steps_min=2000,
                 steps_max=10000):
     """Request mix of the serving workload: half drop impacts (cubic edge L,
-    lognormal around 96 clipped to [l_min, l_max], drop L/5, pool L/20, impact
+    lognormal around sqrt(l_min l_max) (96 for the default range), clipped to
+    [l_min, l_max], drop L/5, pool L/20, impact
     speed 0.02-0.05), half standing-wave slabs L x L/2 x L/4 with amplitude
     0.005-0.02 L; variant uniform over the four; FP32 populations; 2000-10000
     steps; Poisson arrivals. Returns a list of dicts (kind, L, variant, steps,
@@ -421,7 +422,7 @@ def serving_mix(n_requests=512, seed=1234, rate=None, l_min=48, l_max=192, steps
     reqs = []
     t = 0.0
     for r in range(n_requests):
-        L = float(np.exp(rng.normal(math.log(96.0), math.log(2.0) / 2.0)))
+        L = float(np.exp(rng.normal(0.5 * math.log(l_min * l_max), math.log(2.0) / 2.0)))
         L = int(min(max(round(L / 4) * 4, l_min), l_max))
         kind = "drop" if r % 2 == 0 else "wave"
         variant = int(rng.integers(1, 5))

@@ -71,3 +71,21 @@ def test_create_rejects_bad_arguments_without_gpu():
     st = lib.fslbm_create(C.byref(cp), None, None, None, None, None, None, None, None, None, 0,
                           None, C.byref(h))
     assert st == fs.EINVAL and not h.value
+
+
+def test_server_rejects_bad_arguments_without_gpu():
+    """fslbm_server_create / _submit / _poll validate on the host first."""
+    fs = _lib()
+    lib = fs.load_library()
+    h = C.c_void_p()
+    assert lib.fslbm_server_create(0, 4, None, C.byref(h)) == fs.EINVAL and not h.value
+    assert lib.fslbm_server_create(1 << 30, 0, None, C.byref(h)) == fs.EINVAL and not h.value
+    assert lib.fslbm_server_create(1 << 30, 1 << 20, None, C.byref(h)) == fs.EINVAL
+    rid = C.c_uint64()
+    cp = fs.make_params(I.Params(8, 8, 8))
+    assert lib.fslbm_server_submit(None, C.byref(cp), None, None, None, None, None, None, 10,
+                                   C.byref(rid)) == fs.EINVAL
+    n = C.c_int()
+    assert lib.fslbm_server_poll(None, None, None, 0, C.byref(n)) == fs.EINVAL
+    assert lib.fslbm_server_advance(None, 1) == fs.EINVAL
+    lib.fslbm_server_destroy(None)

@@ -1,0 +1,130 @@
+"""Serving through the C ABI (fslbm_server_*): a run's results are the same
+alone, in a mix and in a single context; the FP64 served run matches the
+oracle; admission respects the pool budget; an unstable run is retired with
+its error while the others finish unaffected."""
+import numpy as np
+import pytest
+
+from paper_2207_13962_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+MB = 1 << 20
+
+
+def _mix():
+    """Small runs of both kinds, all four variants, different sizes."""
+    reqs = [
+        I.droplet_impact(L=24, velocity=0.03, variant=I.NBRC),
+        I.wave_slab(L=32, amp_frac=0.02, variant=I.NBKC),
+        I.droplet_impact(L=28, velocity=0.04, variant=I.OM),
+        I.wave_slab(L=40, amp_frac=0.01, variant=I.OM3),
+        I.droplet_impact(L=20, velocity=0.02, variant=I.OM3),
+    ]
+    steps = [90, 60, 75, 50, 110]
+    return reqs, steps
+
+
+def _serve(setups, steps, budget=512 * MB, max_slots=8, ticks=7, order=None):
+    from paper_2207_13962_amd.fslbm import Server
+    srv = Server(budget, max_slots=max_slots)
+    order = list(range(len(setups))) if order is None else order
+    ids = {}
+    for i in order:
+        ids[srv.submit(setups[i], steps[i])] = i
+    out = {}
+    peak = 0
+    budget_calls = 10 * sum(steps) // ticks + 100
+    while len(out) < len(setups):
+        budget_calls -= 1
+        assert budget_calls > 0, "runs did not finish"
+        srv.advance(ticks)
+        st = srv.stats()
+        peak = max(peak, st["resident"])
+        assert st["bytes_in_use"] <= st["budget_bytes"]
+        for rid, status in srv.poll():
+            rep, phi = srv.result(rid)
+            out[ids[rid]] = (status, rep, phi)
+    stats = srv.stats()
+    srv.close()
+    return out, peak, stats
+
+
+def test_same_alone_in_mix_and_single_context():
+    from paper_2207_13962_amd.fslbm import Simulation
+    setups, steps = _mix()
+    mixed, peak, _ = _serve(setups, steps)
+    assert peak == len(setups)  # every run resident at once
+    for i, s in enumerate(setups):
+        alone, _, _ = _serve([s], [steps[i]])
+        st_m, rep_m, phi_m = mixed[i]
+        st_a, rep_a, phi_a = alone[0]
+        assert st_m == st_a == 0
+        assert np.array_equal(phi_m, phi_a), i
+        assert rep_m["total_mass"] == rep_a["total_mass"]
+        sim = Simulation(s)
+        sim.step(steps[i])
+        r = sim.mass()
+        phi_s = sim.fields(pdf=False)["phi"]
+        sim.close()
+        assert np.array_equal(phi_m, phi_s), i
+        assert rep_m["total_mass"] == r["total_mass"]
+        assert rep_m["n_interface"] == r["n_interface"]
+
+
+def test_served_fp64_run_matches_oracle():
+    from oracle import Oracle
+    setups = [I.droplet_impact(L=20, velocity=0.03, variant=v, storage=I.F64) for v in (I.OM, I.NBKC)]
+    setups.append(I.wave_slab(L=24, amp_frac=0.02, variant=I.NBRC, storage=I.F64))
+    steps = [40, 33, 25]
+    out, _, _ = _serve(setups, steps, ticks=5)
+    for i, s in enumerate(setups):
+        o = Oracle(s)
+        assert o.step(steps[i]) == 0
+        f = o.fields()
+        st, rep, phi = out[i]
+        assert st == 0
+        assert np.allclose(phi, f["phi"], rtol=0, atol=1e-12), i
+        r = o.mass()
+        assert abs(rep["total_mass"] - r.total_mass) <= 1e-12 * r.total_mass
+        assert rep["n_interface"] == r.n_interface
+
+
+def test_budget_limits_residency():
+    from paper_2207_13962_amd.fslbm import workspace_bytes
+    setups, steps = _mix()
+    need = sorted(workspace_bytes(s.params) for s in setups)
+    budget = need[-1] + need[-2] + 4096  # room for two of the largest at most
+    out, peak, stats = _serve(setups, steps, budget=budget)
+    assert 1 <= peak <= 3
+    assert stats["peak_bytes_in_use"] <= budget
+    assert all(out[i][0] == 0 for i in range(len(setups)))
+    # same results as with a large pool (admission order does not change a run)
+    ref, _, _ = _serve(setups, steps)
+    for i in range(len(setups)):
+        assert np.array_equal(out[i][2], ref[i][2])
+
+
+def test_rejects_what_it_cannot_serve():
+    from paper_2207_13962_amd.fslbm import FslbmError, Server
+    srv = Server(8 * MB, max_slots=2)
+    with pytest.raises(FslbmError):
+        srv.submit(I.wave_slab(L=96), 10)  # workspace above the budget
+    s = I.wave_slab(L=16)
+    s.params = s.params.with_(sigma=1e-3)
+    with pytest.raises(FslbmError):
+        srv.submit(s, 10)  # surface tension is not served
+    with pytest.raises(FslbmError):
+        srv.submit(I.wave_slab(L=16), 0)
+    srv.close()
+
+
+def test_unstable_run_is_retired_others_unaffected():
+    setups, steps = _mix()
+    bad = I.droplet_impact(L=24, velocity=0.6, variant=I.OM)  # drop faster than c_s
+    ref, _, _ = _serve(setups, steps)
+    out, _, _ = _serve(setups + [bad], steps + [120], order=[5, 0, 1, 2, 3, 4])
+    assert out[5][0] == -4  # FSLBM_EUNSTABLE
+    for i in range(len(setups)):
+        assert out[i][0] == 0
+        assert np.array_equal(out[i][2], ref[i][2])
