@@ -189,37 +189,47 @@ def cpu_baseline(setup_fn, steps):
     return upd / dt / 1e6, dt
 
 
-def serving_section(args):
+def serving_section(args, reqs=None):
     """Batched serving against one-at-a-time solves on a request mix shaped
     like the serving workload (drop impacts and wave slabs, variants uniform,
-    FP32): a closed batch (every run arriving at t = 0) gives the batched
-    capacity; then Poisson arrivals at `load` times that capacity are served
-    both ways. Runs/s over the makespan, p50/p99 time to solution (queueing
-    included); the fill levels of every run must agree bitwise between the
-    two modes."""
+    FP32): closed batches (every run arriving at t = 0) give each mode's
+    capacity in runs/s; then Poisson arrivals at `load` times the batched
+    capacity are served both ways: runs/s over the makespan, p50/p99 time to
+    solution (queueing included). The fill levels of every run must agree
+    bitwise between the two modes."""
     import numpy as np
     from paper_2207_13962_amd import serving as SV
 
-    reqs = SV.make_mix(n_requests=args.requests, l_min=args.l_min, l_max=args.l_max,
-                       steps_min=args.steps_min, steps_max=args.steps_max)
+    if reqs is None:
+        reqs = SV.make_mix(n_requests=args.requests, l_min=args.l_min, l_max=args.l_max,
+                           steps_min=args.steps_min, steps_max=args.steps_max)
     budget = int(args.budget_gb * (1 << 30))
     zero = [0.0] * len(reqs)
     SV.run_batched(reqs[:4], zero[:4], budget, max_slots=args.slots)  # warm-up (code load)
     closed, _ = SV.run_batched(reqs, zero, budget, max_slots=args.slots)
+    print("serving: closed batch %.1f runs/s" % closed["runs_per_s"], file=sys.stderr, flush=True)
+    closed_single, _ = SV.run_sequential(reqs, zero)
+    print("serving: closed, one at a time %.1f runs/s" % closed_single["runs_per_s"], file=sys.stderr,
+          flush=True)
     rate = args.load * closed["runs_per_s"]
     arrival = SV.poisson_arrivals(reqs, rate)
     batched, rb = SV.run_batched(reqs, arrival, budget, max_slots=args.slots, keep_phi=True)
+    print("serving: batched %.1f runs/s" % batched["runs_per_s"], file=sys.stderr, flush=True)
     single, rs = SV.run_sequential(reqs, arrival, keep_phi=True)
-    same = all(a[0] == b[0] and np.array_equal(a[2], b[2]) for a, b in zip(rb, rs))
+    print("serving: one at a time %.1f runs/s" % single["runs_per_s"], file=sys.stderr, flush=True)
+    # (a run that became unstable holds non-finite fill levels; NaN == NaN here)
+    same = all(a[0] == b[0] and np.array_equal(a[2], b[2], equal_nan=True) for a, b in zip(rb, rs))
     cells = [r["L"] ** 3 if r["kind"] == "drop" else r["L"] * (r["L"] // 2) * max(r["L"] // 4, 1)
              for r in reqs]
     return {
         "workload": "%d runs: drop impacts (L^3) and wave slabs (L x L/2 x L/4), L in [%d, %d], "
-                    "%d-%d steps, D3Q19 SRT FP32, variants uniform" % (
+                    "%d-%d steps, D3Q19 FP32 (drops TRT, waves SRT), variants uniform" % (
                         len(reqs), args.l_min, args.l_max, args.steps_min, args.steps_max),
         "cells_total": int(sum(cells)),
         "steps_total": int(sum(r["steps"] for r in reqs)),
-        "closed_batch_runs_per_s": closed["runs_per_s"],
+        "capacity_runs_per_s": {"batched": closed["runs_per_s"],
+                                "one_at_a_time": closed_single["runs_per_s"],
+                                "speedup": closed["runs_per_s"] / closed_single["runs_per_s"]},
         "poisson_rate_runs_per_s": rate,
         "batched": batched,
         "one_at_a_time": single,
@@ -227,6 +237,79 @@ def serving_section(args):
         "identical_results": bool(same),
         "unstable_runs": int(sum(1 for r in rb if r[0] != 0)),
     }
+
+
+def precision_study(args):
+    """FP32 and FP16-shifted population storage against FP64 (the FP64 mode is
+    parity-checked against the oracle): front position and mass drift on the
+    rectangular dam break (all four variants), rise velocity and mass drift of
+    the Taylor bubble (surface tension, bubble model)."""
+    import numpy as np
+    from paper_2207_13962_amd import inputs as I
+    from paper_2207_13962_amd.fslbm import Simulation
+
+    names = {I.F64: "f64", I.F32: "f32", I.F16S: "f16s"}
+    out = {"dam_break": {}, "taylor_bubble": {}}
+    every = 100
+    for v in (1, 2, 3, 4):
+        res = {}
+        for st in (I.F64, I.F32, I.F16S):
+            s = I.workload("dam256", smagorinsky=args.les, storage=st, variant=v)
+            sim = Simulation(s)
+            m0 = sim.mass()["total_mass"]
+            fronts, status = [], 0
+            for n in range(0, args.dam_steps + 1, every):
+                if n:
+                    sim.step(every)
+                r = sim.mass(check=False)
+                if r["status"] != 0:
+                    status = r["status"]
+                    break
+                t = sim.fields(pdf=False, check=False)["type"].reshape(s.params.nz, s.params.ny, s.params.nx)
+                floor = ((t[:, 0, :] == 1) | (t[:, 0, :] == 2)).any(axis=0)
+                fronts.append(int(np.nonzero(floor)[0].max()))
+            res[names[st]] = dict(front=fronts, status=status,
+                                  mass_drift=(r["total_mass"] - m0) / m0)
+            sim.close()
+            print("precision: dam break %s %s done" % (I.VARIANT_NAMES[v], names[st]), file=sys.stderr,
+                  flush=True)
+        ref = res["f64"]["front"]
+        for k in ("f32", "f16s"):
+            f = res[k]["front"]
+            n = min(len(f), len(ref))
+            res[k]["max_front_diff_cells"] = int(max(abs(a - b) for a, b in zip(f[:n], ref[:n]))) if n else None
+        out["dam_break"][I.VARIANT_NAMES[v]] = res
+    # Taylor bubble: centroid of the gas (1 - phi over gas and interface cells)
+    every = args.taylor_steps // 10
+    for st in (I.F64, I.F32, I.F16S):
+        s = I.workload("taylor512", storage=st)
+        p = s.params
+        zc = np.repeat(np.arange(p.nz) + 0.5, p.nx * p.ny)
+        sim = Simulation(s)
+        m0 = sim.mass()["total_mass"]
+        cz, status = [], 0
+        for n in range(0, args.taylor_steps + 1, every):
+            if n:
+                sim.step(every)
+            r = sim.mass(check=False)
+            if r["status"] != 0:
+                status = r["status"]
+                break
+            f = sim.fields(pdf=False, check=False)
+            w = np.where((f["type"] == 0) | (f["type"] == 1), 1.0 - f["phi"], 0.0)
+            cz.append(float((w * zc).sum() / w.sum()))
+        half = len(cz) // 2
+        vel = (cz[-1] - cz[half]) / ((len(cz) - 1 - half) * every) if len(cz) > 2 else None
+        out["taylor_bubble"][names[st]] = dict(centroid_z=cz, rise_velocity=vel, status=status,
+                                                 mass_drift=(r["total_mass"] - m0) / m0,
+                                                 bubble_volume=r["bubble_volume"])
+        sim.close()
+        print("precision: Taylor bubble %s done" % names[st], file=sys.stderr, flush=True)
+    ref = out["taylor_bubble"]["f64"]["rise_velocity"]
+    for k in ("f32", "f16s"):
+        v = out["taylor_bubble"][k]["rise_velocity"]
+        out["taylor_bubble"][k]["rise_velocity_rel_err"] = (v - ref) / ref if (v and ref) else None
+    return out
 
 
 def main():
@@ -251,6 +334,10 @@ def main():
                     help="summarise a rocprofv3 --kernel-trace --stats run and exit")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in a profile summary (repeat per run)")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="only the storage-precision study (FP32/FP16-shifted against FP64)")
+    ap.add_argument("--dam-steps", type=int, default=1500, help="precision study: dam-break steps")
+    ap.add_argument("--taylor-steps", type=int, default=10000, help="precision study: Taylor-bubble steps")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
     ap.add_argument("--requests", type=int, default=48, help="serving: runs in the mix")
@@ -260,6 +347,8 @@ def main():
     ap.add_argument("--steps-max", type=int, default=800, help="serving: most steps of a run")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device pool (GiB)")
     ap.add_argument("--slots", type=int, default=64, help="serving: resident runs at most")
+    ap.add_argument("--build-workers", type=int, default=1,
+                    help="serving: host processes building the request setups")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving: Poisson rate as a fraction of the batched capacity")
     args = ap.parse_args()
@@ -280,6 +369,15 @@ def main():
               "MI355X (no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    reqs = None
+    if args.serving_only:
+        # the request setups are built on the host before the GPU is touched
+        # (worker processes are forked from a process without GPU state)
+        from paper_2207_13962_amd import serving as SV
+        reqs = SV.make_mix(n_requests=args.requests, l_min=args.l_min, l_max=args.l_max,
+                           steps_min=args.steps_min, steps_max=args.steps_max,
+                           workers=args.build_workers)
+
     import torch
     from paper_2207_13962_amd import inputs as I
     from paper_2207_13962_amd.fslbm import Simulation
@@ -287,7 +385,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.serving_only:
-        print(json.dumps(serving_section(args)))
+        print(json.dumps(serving_section(args, reqs)))
+        return
+    if args.precision_study:
+        print(json.dumps(precision_study(args)))
         return
     variants = [int(v) for v in args.variants.split(",")]
     setup_fn = lambda: I.workload(args.workload, **({"smagorinsky": args.les} if args.les else {}))  # noqa: E731

@@ -77,6 +77,7 @@ enum {
   CNT_CHUNKS = 7,  // 64-cell chunks holding at least one liquid cell
   CNT_GEN = 8,     // liquid cells next to the domain boundary or an obstacle
   CNT_NG = 9,      // new interface cells from gas in this step
+  CNT_HALT0 = 10,  // halt words, slot (step & 1): the run stopped after an instability
   CNT_N = 12
 };
 enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8 };

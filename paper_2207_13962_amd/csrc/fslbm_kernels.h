@@ -578,8 +578,15 @@ __device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk) {
 // next to walls or obstacles, the rest the liquid chunks.
 // (Block b of nb blocks of one run; the kernels below are written this way so
 // that one launch can also serve many runs, each with its own block range.)
+// After a step that flagged an instability, the run stops: every step kernel
+// of the later steps returns at once (halt word of the step's slot, written
+// only by the previous step's k_finish, so all blocks of a launch see the same
+// value), and the state stays that of the failing step.
+__device__ __forceinline__ bool halted(const Dev& d) { return d.cnt[CNT_HALT0 + (d.step & 1)] != 0; }
+
 template <int S, int Q, bool TRT, bool BUF>
 __device__ __forceinline__ void stream_body(const Dev& d, int b, int nb, int gen, int bord) {
+  if (halted(d)) return;
   if (b == 0 && threadIdx.x == 0) {
     d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // mark slot of the next step
     d.cnt[CNT_NG] = 0;                          // new-gas list of this step
@@ -631,6 +638,7 @@ __device__ __forceinline__ bool set_new_gas(uint8_t* flags, int64_t j) {
 // when the compaction will run, a new epoch for its tile-status words.
 template <int Q>
 __device__ __forceinline__ void retype_body(const Dev& d, int b, int nb, int rebuild_only) {
+  if (!rebuild_only && halted(d)) return;
   const int nmk = rebuild_only ? 0 : d.cnt[CNT_MARK0 + (d.step & 1)];
   if (b == 0 && threadIdx.x == 0) {
     d.cnt[CNT_TICKET] = 0;
@@ -844,6 +852,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   __shared__ uint32_t s_epoch;
   __shared__ uint32_t s_scan[4][kCompBlock / 64];
   __shared__ uint32_t s_red[4][kCompBlock / 64];
+  if (!rebuild_only && halted(d)) return;
   if (b < workers) {
     // worker blocks, beside the compaction: the converted cells (the marked
     // cells that carry the converted bit) get their excess-mass share, the new
@@ -1110,6 +1119,12 @@ __device__ __forceinline__ void finish_interface(const Dev& d, int64_t c, bool c
 
 template <int S, int Q, bool TRT>
 __device__ __forceinline__ void finish_body(const Dev& d, int b, int nb, int classes_only) {
+  // the next step's halt word: this step's, or set by an instability flagged
+  // in this step (written before any early return, read from the next step on)
+  if (b == 0 && threadIdx.x == 0)
+    d.cnt[CNT_HALT0 + ((d.step + 1) & 1)] =
+        (d.cnt[CNT_HALT0 + (d.step & 1)] != 0 || (d.cnt[CNT_ERR] & ERR_UNSTABLE) != 0) ? 1 : 0;
+  if (!classes_only && halted(d)) return;
   if (!classes_only && d.cnt[CNT_MARK0 + (d.step & 1)] == 0) return;
   const int nif = d.cnt[CNT_IF];
   for (int i = b * kBlock + threadIdx.x; i < nif; i += nb * kBlock)

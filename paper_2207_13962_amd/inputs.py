@@ -435,8 +435,10 @@ def serving_mix(n_requests=512, seed=1234, rate=None, l_min=48, l_max=192, steps
 
 
 def build_request(req: dict, storage=F32) -> Setup:
+    """Setup of one serving request: drops run TRT (tau = 1/1.989, the drop
+    case's relaxation rate, is close to 1/2), waves SRT."""
     if req["kind"] == "drop":
         return droplet_impact(L=req["L"], velocity=req["extra"], variant=req["variant"],
-                              storage=storage, steps=req["steps"])
+                              storage=storage, steps=req["steps"], collision=TRT)
     return wave_slab(L=req["L"], amp_frac=req["extra"], variant=req["variant"], storage=storage,
                      steps=req["steps"])

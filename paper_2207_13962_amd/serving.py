@@ -10,6 +10,7 @@ collects results.
 """
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -17,14 +18,26 @@ import numpy as np
 from . import inputs as I
 
 
-def make_mix(n_requests=48, seed=1234, l_min=32, l_max=64, steps_min=200, steps_max=800):
+def _build(r):
+    return I.build_request(r)
+
+
+def make_mix(n_requests=48, seed=1234, l_min=32, l_max=64, steps_min=200, steps_max=800, workers=1):
     """A request mix shaped like the serving workload (drop impacts and
     standing-wave slabs, variant uniform, FP32 populations), with setups built
-    up front; arrival times are assigned by `poisson_arrivals`."""
+    up front (in `workers` processes); arrival times are assigned by
+    `poisson_arrivals`."""
     reqs = I.serving_mix(n_requests=n_requests, seed=seed, l_min=l_min, l_max=l_max,
                          steps_min=steps_min, steps_max=steps_max)
-    for r in reqs:
-        r["setup"] = I.build_request(r)
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            setups = pool.map(_build, reqs, chunksize=1)
+    else:
+        setups = [_build(r) for r in reqs]
+    for r, st in zip(reqs, setups):
+        r["setup"] = st
+    print("serving mix: %d setups built" % len(reqs), file=sys.stderr, flush=True)
     return reqs
 
 
@@ -54,7 +67,8 @@ def _summary(arrival, done, t_end, label):
     }
 
 
-def run_batched(reqs, arrival, budget_bytes, max_slots=64, ticks=16, device="cuda:0", keep_phi=False):
+def run_batched(reqs, arrival, budget_bytes, max_slots=64, ticks=16, device="cuda:0", keep_phi=False,
+                progress=32):
     """Serve the requests with one fslbm server. Returns (summary, results):
     results[i] = (status, mass report, phi or None)."""
     import torch
@@ -91,6 +105,9 @@ def run_batched(reqs, arrival, budget_bytes, max_slots=64, ticks=16, device="cud
             done_t[i] = time.perf_counter() - t0
             results[i] = (status, rep, phi)
             finished += 1
+            if progress and finished % progress == 0:
+                print("batched: %d of %d done at %.1f s" % (finished, n, done_t[i]), file=sys.stderr,
+                      flush=True)
     t_end = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
@@ -100,7 +117,7 @@ def run_batched(reqs, arrival, budget_bytes, max_slots=64, ticks=16, device="cud
     return out, results
 
 
-def run_sequential(reqs, arrival, device="cuda:0", keep_phi=False):
+def run_sequential(reqs, arrival, device="cuda:0", keep_phi=False, progress=32):
     """One run at a time, in arrival order, each alone in its own context."""
     import torch
     from .fslbm import Simulation
@@ -125,5 +142,8 @@ def run_sequential(reqs, arrival, device="cuda:0", keep_phi=False):
             sim.close()
             done_t[i] = time.perf_counter() - t0
             results[i] = (rep["status"], rep, phi)
+            if progress and sum(r is not None for r in results) % progress == 0:
+                print("one at a time: %d of %d done" % (sum(r is not None for r in results), n),
+                      file=sys.stderr, flush=True)
     t_end = time.perf_counter() - t0
     return _summary(arrival, done_t, t_end, "one-at-a-time"), results

@@ -128,3 +128,29 @@ def test_unstable_run_is_retired_others_unaffected():
     for i in range(len(setups)):
         assert out[i][0] == 0
         assert np.array_equal(out[i][2], ref[i][2])
+    # the failed run itself: the same state as in a single context
+    from paper_2207_13962_amd.fslbm import Simulation
+    sim = Simulation(bad)
+    sim.step(120)
+    f = sim.fields(pdf=False, check=False)
+    sim.close()
+    assert f["status"] == -4
+    assert np.array_equal(out[5][2], f["phi"], equal_nan=True)
+
+
+def test_unstable_run_stops_advancing():
+    """After the step that flags an instability no step kernel changes the
+    state (two further steps bring back the same buffers)."""
+    from paper_2207_13962_amd.fslbm import Simulation
+    sim = Simulation(I.droplet_impact(L=24, velocity=0.6, variant=I.OM))
+    sim.step(10)
+    a = sim.fields(pdf=True, check=False)
+    sim.step(2)
+    b = sim.fields(pdf=True, check=False)
+    sim.step(30)
+    c = sim.fields(pdf=True, check=False)
+    sim.close()
+    assert a["status"] == b["status"] == -4
+    for k in ("type", "phi", "mass", "pdf"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+        assert np.array_equal(a[k], c[k], equal_nan=True), k
