@@ -413,6 +413,7 @@ int fslbm_interface_list(fslbm_ctx* c, int32_t* list, int64_t max, int64_t* coun
     const int64_t n = std::min<int64_t>(max, cnt[CNT_IF]);
     HIPCHK(c, hipMemcpyAsync(list, c->d.if_list, 4 * n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; ++i) list[i] &= 0x7fffffff;  // drop the BORDER bit
   }
   return FSLBM_OK;
 }

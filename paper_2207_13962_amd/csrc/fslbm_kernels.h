@@ -68,6 +68,14 @@ struct Dev {
   int64_t step;  // parity selects the mark-counter slot
 };
 
+// Entries of the interface list: the cell index, with bit 31 set when the
+// cell has the BORDER bit (its neighbourhood needs wall/wrap handling).
+__device__ __forceinline__ int32_t list_entry(int64_t c, bool border) {
+  return (int32_t)((uint32_t)c | (border ? 0x80000000u : 0u));
+}
+__device__ __forceinline__ int64_t list_cell(int32_t e) { return (int64_t)((uint32_t)e & 0x7fffffffu); }
+__device__ __forceinline__ bool list_border(int32_t e) { return e < 0; }
+
 // ---------------------------------------------------------------------------
 // k_liquid and k_generic
 // ---------------------------------------------------------------------------
@@ -363,15 +371,28 @@ __device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk) {
   const int cx = cxd(k), cy = cyd(k), cz = czd(k);
   const int v = d.variant;
   CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
+  // linear offsets of this lane's pull source and box neighbour (cells
+  // without the BORDER bit: their whole 3x3x3 box lies inside the domain and
+  // holds no obstacle)
+  const int64_t gnx = g.nx, gnxy = (int64_t)g.nx * g.ny;
+  const int64_t offd = cx + cy * gnx + cz * gnxy;
+  const int64_t offb = l < 27 ? (l % 3 - 1) + ((l / 3) % 3 - 1) * gnx + (l / 9 - 1) * gnxy : 0;
   const XcdRange q = xcd_range(nif, blk, nblk, threadIdx.x / kG, kBlock / kG);
   for (int item = q.first; item < q.end; item += q.step) {
-    const int64_t c = d.if_list[item];
-    int x, y, z;
-    coords(g, c, x, y, z);
+    const int32_t e = d.if_list[item];
+    const int64_t c = list_cell(e);
+    int x = 0, y = 0, z = 0;
     // pull source x - c_k and 3x3x3 neighbour of this lane
     int wd = 0, wb = 0;
-    const int64_t jd = nb_index(g, x, y, z, -cx, -cy, -cz, &wd);
-    const int64_t jb = l < 27 ? nb_index(g, x, y, z, l % 3 - 1, (l / 3) % 3 - 1, l / 9 - 1, &wb) : c;
+    int64_t jd, jb;
+    if (list_border(e)) {
+      coords(g, c, x, y, z);
+      jd = nb_index(g, x, y, z, -cx, -cy, -cz, &wd);
+      jb = l < 27 ? nb_index(g, x, y, z, l % 3 - 1, (l / 3) % 3 - 1, l / 9 - 1, &wb) : c;
+    } else {
+      jd = c - offd;
+      jb = c + offb;
+    }
     const int64_t js = jd >= 0 ? jd : c, jbs = jb >= 0 ? jb : c;
     // the batch
     const R fo = act ? St::ld(A, k * stride + c, k) : R(0);
@@ -723,7 +744,8 @@ __device__ __forceinline__ uint32_t mask_of(const uint4& v, int64_t b0, int64_t 
     if (which == 0) hit = (f & T_MASK) == T_IF;
     else if (which == 1) hit = (f & F_CONV) != 0;
     else if (which == 2) hit = (f & (T_MASK | F_COMPLEX)) == T_LIQ;
-    else hit = (f & (T_MASK | F_COMPLEX)) == (T_LIQ | F_COMPLEX);
+    else if (which == 3) hit = (f & (T_MASK | F_COMPLEX)) == (T_LIQ | F_COMPLEX);
+    else hit = (f & (T_MASK | F_BORDER)) == (T_IF | F_BORDER);
     if (hit && b0 + j < N) m |= 1u << j;
   }
   return m;
@@ -892,7 +914,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   // pass 1: masks and counts, in batches of kBatch 16-byte vectors requested
   // together; the masks of the first batch are kept for pass 2
   constexpr int kBatch = 4;
-  uint32_t keep[4][kBatch];
+  uint32_t keep[5][kBatch];  // the four lists, and interface cells with the BORDER bit
   uint32_t c[4] = {0, 0, 0, 0};
   uint32_t own_any = 0;
   {
@@ -908,14 +930,14 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         const int64_t b0 = base + 16 * (v0 + u);
-        uint32_t m[4] = {0, 0, 0, 0};
+        uint32_t m[5] = {0, 0, 0, 0, 0};
         if (v0 + u < nvec && b0 < N) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) m[i] = mask_of(vec[u], b0, N, i);
+          for (int i = 0; i < 5; ++i) m[i] = mask_of(vec[u], b0, N, i);
         }
         if (v0 == 0) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) keep[i][u] = m[i];
+          for (int i = 0; i < 5; ++i) keep[i][u] = m[i];
         }
         c[0] += __popc(m[0]);
         c[1] += __popc(m[1]);
@@ -992,12 +1014,12 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
     uint32_t chunk_any = 0;
 #pragma unroll 1
     for (int v0 = 0; v0 < nvec; v0 += kBatch) {
-      uint32_t m[4][kBatch];
+      uint32_t m[5][kBatch];
       if (v0 == 0) {
 #pragma unroll
         for (int u = 0; u < kBatch; ++u)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) m[i][u] = keep[i][u];
+          for (int i = 0; i < 5; ++i) m[i][u] = keep[i][u];
       } else {
         uint4 vec[kBatch];
 #pragma unroll
@@ -1010,14 +1032,17 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
           const int64_t b0 = base + 16 * (v0 + u);
           const bool in = v0 + u < nvec && b0 < N;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) m[i][u] = in ? mask_of(vec[u], b0, N, i) : 0u;
+          for (int i = 0; i < 5; ++i) m[i][u] = in ? mask_of(vec[u], b0, N, i) : 0u;
         }
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         const int64_t b0 = base + 16 * (v0 + u);
         if (v0 + u >= nvec || b0 >= N) break;
-        for (uint32_t mm = m[0][u]; mm; mm &= mm - 1) d.if_list[off[0]++] = (int32_t)(b0 + __builtin_ctz(mm));
+        for (uint32_t mm = m[0][u]; mm; mm &= mm - 1) {
+          const int j = __builtin_ctz(mm);
+          d.if_list[off[0]++] = list_entry(b0 + j, ((m[4][u] >> j) & 1u) != 0);
+        }
         for (uint32_t mm = m[1][u]; mm; mm &= mm - 1) d.conv_list[off[1]++] = (int32_t)(b0 + __builtin_ctz(mm));
         for (uint32_t mm = m[3][u]; mm; mm &= mm - 1) d.gen_list[off[3]++] = (int32_t)(b0 + __builtin_ctz(mm));
         if (per >= 64) {
@@ -1049,7 +1074,7 @@ __global__ __launch_bounds__(kCompBlock) void k_compact(Dev d, int rebuild_only,
 // the new interface list.
 // ---------------------------------------------------------------------------
 template <int S, int Q, bool TRT>
-__device__ __forceinline__ void finish_interface(const Dev& d, int64_t c, bool classes_only) {
+__device__ __forceinline__ void finish_interface(const Dev& d, int32_t e, bool classes_only) {
   using St = Store<S, Q>;
   using T = typename St::T;
   using R = typename St::R;
@@ -1057,17 +1082,28 @@ __device__ __forceinline__ void finish_interface(const Dev& d, int64_t c, bool c
   T* B = static_cast<T*>(d.fB);
   const Geom& g = d.g;
   const int64_t stride = g.stride;
-  int x, y, z;
-  coords(g, c, x, y, z);
+  const int64_t c = list_cell(e);
   // neighbour indices and flags, all loads issued before the first use
   // (unconditional loads: a wall neighbour reads the cell itself and is then
-  // ignored, so the loads share one round trip)
+  // ignored, so the loads share one round trip); a cell without the BORDER
+  // bit takes linear offsets
   int64_t jn[Q];
   uint8_t fn[Q];
+  if (list_border(e)) {
+    int x, y, z;
+    coords(g, c, x, y, z);
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      int w;
+      jn[k] = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
+    }
+  } else {
+    const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) jn[k] = c + kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
+  }
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
-    int w;
-    jn[k] = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
     const uint8_t f = d.flags[jn[k] >= 0 ? jn[k] : c];
     fn[k] = jn[k] >= 0 ? f : (uint8_t)T_NOSLIP;
   }
@@ -1206,7 +1242,7 @@ __device__ __forceinline__ void unit_normal_s(const Dev& d, int64_t j, double nh
 __global__ __launch_bounds__(kBlock) void k_curvature(Dev d) {
   const int nif = d.cnt[CNT_IF];
   for (int k = blockIdx.x * kBlock + threadIdx.x; k < nif; k += gridDim.x * kBlock) {
-    const int64_t c = d.if_list[k];
+    const int64_t c = list_cell(d.if_list[k]);
     int x, y, z;
     coords(d.g, c, x, y, z);
     double nc[3];
