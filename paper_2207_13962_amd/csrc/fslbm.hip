@@ -104,7 +104,7 @@ void bind(fslbm_ctx* c) {
   d.gen_list = reinterpret_cast<int32_t*>(a + L.off_gen_list);
   d.mark_list = reinterpret_cast<int32_t*>(a + L.off_mark_list);
   d.ng_list = reinterpret_cast<int32_t*>(a + L.off_ng_list);
-  d.xs = reinterpret_cast<double*>(a + L.off_xs);
+  d.nl_list = reinterpret_cast<int32_t*>(a + L.off_nl_list);
   d.cnt = reinterpret_cast<int32_t*>(a + L.off_cnt);
   d.scan_status = reinterpret_cast<unsigned long long*>(a + L.off_scan_status);
   d.pV = reinterpret_cast<double*>(a + L.off_pv);
@@ -138,11 +138,10 @@ void enqueue_plain(fslbm_ctx* c, int64_t n) {
       hipLaunchKernelGGL(k_smooth, dim3((unsigned)(((c->p.nx + 63) / 64) * ((c->p.ny + 3) / 4) *
                                                    c->p.nz)),
                          dim3(kBlock), 0, s, c->d);
-      hipLaunchKernelGGL(k_curvature, dim3(finish_blocks(c)), dim3(kBlock), 0, s, c->d);
+      hipLaunchKernelGGL(k_curvature, dim3(list_blocks(c)), dim3(kBlock), 0, s, c->d);
     }
     ops.step(c, s);
     ops.convert(c, s, 0);
-    ops.finish(c, s, 0);
     if (c->p.bubble_model) launch_volume(c, s, false);
     std::swap(c->d.fA, c->d.fB);
     std::swap(c->d.phiA, c->d.phiB);
@@ -318,7 +317,7 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   // interface list, flux classes, volume pressure
   c->d.step = 0;
   ops.convert(c, s, 1);
-  ops.finish(c, s, 1);
+  ops.classes(c, s);
   const double pv0[3] = {c->p.rho_gas / 3.0, c->p.rho_gas / 3.0, 0.0};
   INITCHK(hipMemcpyAsync(c->d.pV, pv0, sizeof pv0, hipMemcpyHostToDevice, s));
   // V(0) from phiB == phiA at this point
@@ -584,7 +583,7 @@ struct fslbm_server {
   char* pool_mem = nullptr;
   Pool* pool = nullptr;
   Dev* d_devs = nullptr;          // max_slots Dev records
-  BatchEntry* d_tab = nullptr;    // kGroups x 4 x max_slots entries
+  BatchEntry* d_tab = nullptr;    // kGroups x kLaunches x max_slots entries
   BatchEntry* h_tab = nullptr;    // pinned staging of the same
   std::vector<int> free_slots;
   std::deque<PendingRun> queue;
@@ -607,8 +606,8 @@ int srv_fail(fslbm_server* s, hipError_t e) {
   return FSLBM_EDEVICE;
 }
 
-// Block ranges of one run in the four launches of a batched step.
-void run_blocks(const fslbm_ctx* c, int nb[4], int stream_split[2], int compact_args[2]) {
+// Block ranges of one run in the launches of a batched step.
+void run_blocks(const fslbm_ctx* c, int nb[kLaunches], int stream_split[2], int compact_args[2]) {
   const int gen = round8(std::min<int64_t>(if_blocks(c), 192));
   const int bord = round8(std::min<int64_t>(border_blocks(c), 64));
   const int liq = round8(std::min<int64_t>(liquid_blocks(c), 256));
@@ -618,11 +617,10 @@ void run_blocks(const fslbm_ctx* c, int nb[4], int stream_split[2], int compact_
   // (only the streaming launch needs XCD-aligned ranges; the compaction needs
   // exactly one block per tile beside its workers)
   nb[1] = (int)std::min<int64_t>(retype_blocks(c), 64);
-  const int workers = (int)(std::min<int64_t>(retype_blocks(c), 64) + 3) / 4;
+  const int workers = compact_workers(c);
   compact_args[0] = (int)c->L.conv_per;
   compact_args[1] = workers;
   nb[2] = (int)c->L.tiles + workers;
-  nb[3] = (int)std::min<int64_t>(finish_blocks(c), 128);
 }
 
 // Tables of every group from the resident runs.
@@ -633,13 +631,13 @@ int rebuild_plan(fslbm_server* s) {
     bl = BatchLaunch{};
     bl.devs = s->d_devs;
     bl.buf = (g & 1) != 0;
-    int cursor[4] = {0, 0, 0, 0};
+    int cursor[kLaunches] = {0, 0, 0};
     for (const ResidentRun& r : s->resident) {
       if (r.group != g) continue;
-      int nb[4], split[2], cargs[2];
+      int nb[kLaunches], split[2], cargs[2];
       run_blocks(r.ctx, nb, split, cargs);
-      for (int k = 0; k < 4; ++k) {
-        BatchEntry& e = s->h_tab[((size_t)g * 4 + k) * s->max_slots + bl.n];
+      for (int k = 0; k < kLaunches; ++k) {
+        BatchEntry& e = s->h_tab[((size_t)g * kLaunches + k) * s->max_slots + bl.n];
         e.slot = r.slot;
         e.blk0 = cursor[k];
         e.nblk = nb[k];
@@ -652,11 +650,11 @@ int rebuild_plan(fslbm_server* s) {
       }
       ++bl.n;
     }
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kLaunches; ++k) {
       bl.blocks[k] = cursor[k];
-      bl.tab[k] = s->d_tab + ((size_t)g * 4 + k) * s->max_slots;
+      bl.tab[k] = s->d_tab + ((size_t)g * kLaunches + k) * s->max_slots;
       if (bl.n > 0 &&
-          hipMemcpyAsync(const_cast<BatchEntry*>(bl.tab[k]), s->h_tab + ((size_t)g * 4 + k) * s->max_slots,
+          hipMemcpyAsync(const_cast<BatchEntry*>(bl.tab[k]), s->h_tab + ((size_t)g * kLaunches + k) * s->max_slots,
                          sizeof(BatchEntry) * bl.n, hipMemcpyHostToDevice, s->stream) != hipSuccess)
         return srv_fail(s, hipErrorUnknown);
     }
@@ -770,7 +768,7 @@ int fslbm_server_create(size_t hbm_budget_bytes, int max_slots, void* hip_stream
   s->budget = hbm_budget_bytes;
   s->max_slots = max_slots;
   s->stream = static_cast<hipStream_t>(hip_stream);
-  const size_t tab = sizeof(BatchEntry) * (size_t)kGroups * 4 * (size_t)max_slots;
+  const size_t tab = sizeof(BatchEntry) * (size_t)kGroups * kLaunches * (size_t)max_slots;
   if (hipMalloc(reinterpret_cast<void**>(&s->pool_mem), hbm_budget_bytes) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_devs), sizeof(Dev) * (size_t)max_slots) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_tab), tab) != hipSuccess ||

@@ -84,13 +84,5 @@ __global__ __launch_bounds__(kCompBlock) void kb_compact(const Dev* devs, const 
   compact_body<S, Q, TRT>(d, (int)blockIdx.x - e.blk0, e.nblk, 0, e.a, e.b);
 }
 
-template <int S, int Q, bool TRT>
-__global__ __launch_bounds__(kBlock) void kb_finish(const Dev* devs, const BatchEntry* tab, int n,
-                                                    int64_t tick) {
-  const BatchEntry e = batch_entry(tab, n);
-  Dev d;
-  if (!batch_dev(devs, e, tick, d)) return;
-  finish_body<S, Q, TRT>(d, (int)blockIdx.x - e.blk0, e.nblk, 0);
-}
 
 }  // namespace fslbm

@@ -78,7 +78,8 @@ enum {
   CNT_GEN = 8,     // liquid cells next to the domain boundary or an obstacle
   CNT_NG = 9,      // new interface cells from gas in this step
   CNT_HALT0 = 10,  // halt words, slot (step & 1): the run stopped after an instability
-  CNT_N = 12
+  CNT_NL = 12,     // new interface cells from liquid in this step
+  CNT_N = 16
 };
 enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8 };
 
@@ -189,8 +190,19 @@ __device__ __forceinline__ void coords(const Geom& g, int64_t c, int& x, int& y,
 
 // Index of (x,y,z)+(dx,dy,dz) after periodic wrap, or -1 beyond a wall face;
 // *wall receives the ghost's obstacle type (no-slip wins where faces meet).
+// (x,y,z) is a cell of the domain and the offsets are -1, 0 or 1, so a
+// periodic wrap is one period, and with compile-time offsets (directions of
+// an unrolled loop) only the faces the offset can cross are tested; this
+// keeps the function small, which matters where it is unrolled over q
+// directions.
 __device__ __forceinline__ int64_t nb_index(const Geom& g, int x, int y, int z, int dx, int dy,
                                             int dz, int* wall) {
+  __builtin_assume(x >= 0 && x < g.nx);
+  __builtin_assume(y >= 0 && y < g.ny);
+  __builtin_assume(z >= 0 && z < g.nz);
+  __builtin_assume(dx >= -1 && dx <= 1);
+  __builtin_assume(dy >= -1 && dy <= 1);
+  __builtin_assume(dz >= -1 && dz <= 1);
   int c[3] = {x + dx, y + dy, z + dz};
   const int n[3] = {g.nx, g.ny, g.nz};
   int w = 0;
@@ -204,10 +216,32 @@ __device__ __forceinline__ int64_t nb_index(const Geom& g, int x, int y, int z, 
     if (face < 0) continue;
     const int b = face_kind(g, face);
     if (b == BND_PERIODIC) {
-      int m = c[a] % n[a];
-      c[a] = m < 0 ? m + n[a] : m;
+      c[a] += (face & 1) ? -n[a] : n[a];
     } else {
       int t = (b == BND_NOSLIP) ? T_NOSLIP : T_FREESLIP;
+      if (w != T_NOSLIP) w = t;
+    }
+  }
+  *wall = w;
+  if (w) return -1;
+  return (int64_t)(c[0] + g.nx * (c[1] + g.ny * c[2]));
+}
+
+// Index of the point (x,y,z), any distance outside the domain, after periodic
+// wrap, or -1 beyond a wall face (*wall as for nb_index).
+__device__ __forceinline__ int64_t wrap_index(const Geom& g, int x, int y, int z, int* wall) {
+  int c[3] = {x, y, z};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int w = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (c[a] >= 0 && c[a] < n[a]) continue;
+    const int b = face_kind(g, c[a] < 0 ? 2 * a : 2 * a + 1);
+    if (b == BND_PERIODIC) {
+      const int m = c[a] % n[a];
+      c[a] = m < 0 ? m + n[a] : m;
+    } else {
+      const int t = (b == BND_NOSLIP) ? T_NOSLIP : T_FREESLIP;
       if (w != T_NOSLIP) w = t;
     }
   }

@@ -1,7 +1,7 @@
 // HIP kernels of the free-surface LBM step for gfx950.
 //
-// One time step is four launches (plus two for surface tension, two for the
-// bubble volume); the last three do their work only when some cell was marked:
+// One time step is three launches (plus two for surface tension, two for the
+// bubble volume); the last two do their work only when some cell was marked:
 //   k_stream    three roles       : every liquid cell away from walls (chunk
 //                                   list; pull streaming, collision - the
 //                                   bandwidth part), every liquid cell next to
@@ -11,16 +11,17 @@
 //                                   mass exchange, fill level, conversion mark,
 //                                   collision)
 //   k_retype    mark-list-driven  : new types around every marked cell (to-gas
-//                                   marks next to a to-liquid mark are dropped)
+//                                   marks next to a to-liquid mark are dropped);
+//                                   lists of the new interface cells
 //   k_compact   every cell        : the new interface, converted, liquid-chunk
 //                                   and wall-liquid lists, compacted in ascending
 //                                   order by a single-pass scan (block scan +
 //                                   published tile counts); beside it, worker
-//                                   blocks reinitialise the new interface cells
-//                                   from gas and split the excess mass of the
-//                                   converted cells
-//   k_finish    list-driven       : mass of new interface cells from liquid,
-//                                   excess-mass gather, fill levels, flux classes
+//                                   blocks complete the conversion: converted
+//                                   cells, reinitialisation of the new interface
+//                                   cells from gas, and the excess-mass gather,
+//                                   fill level and flux classes of every
+//                                   interface cell next to a changed cell
 // The state between steps is the post-collision population f* (grid A); the
 // step writes grid B and the host swaps A/B. Marks, counters and lists stay on the
 // device, so a step needs no host synchronisation.
@@ -54,13 +55,13 @@ struct Dev {
   double* rhoG;  // per-cell gas density (surface tension), or null
   double* phis;  // smoothed fill level (surface tension), or null
   double* lost;  // per-cell lost excess mass
-  double* xs;    // per converted cell: its excess-mass share per interface neighbour
   int32_t* if_list;
   int32_t* conv_list;
   int32_t* chunk_list;  // 64-cell chunks with liquid cells, ascending
   int32_t* gen_list;    // liquid cells with the BORDER flag, ascending
   int32_t* mark_list;   // cells marked in this step (unordered)
   int32_t* ng_list;     // new interface cells from gas of this step (unordered)
+  int32_t* nl_list;     // new interface cells from liquid of this step (unordered)
   int32_t* cnt;
   unsigned long long* scan_status;  // two words per compaction tile
   double* pV;  // device scalars: [0] p^V, [1] p^V(0), [2] V(0)
@@ -601,7 +602,7 @@ __device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk) {
 // that one launch can also serve many runs, each with its own block range.)
 // After a step that flagged an instability, the run stops: every step kernel
 // of the later steps returns at once (halt word of the step's slot, written
-// only by the previous step's k_finish, so all blocks of a launch see the same
+// only by the previous step's k_compact, so all blocks of a launch see the same
 // value), and the state stays that of the failing step.
 __device__ __forceinline__ bool halted(const Dev& d) { return d.cnt[CNT_HALT0 + (d.step & 1)] != 0; }
 
@@ -610,7 +611,8 @@ __device__ __forceinline__ void stream_body(const Dev& d, int b, int nb, int gen
   if (halted(d)) return;
   if (b == 0 && threadIdx.x == 0) {
     d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // mark slot of the next step
-    d.cnt[CNT_NG] = 0;                          // new-gas list of this step
+    d.cnt[CNT_NG] = 0;                          // new-cell lists of this step
+    d.cnt[CNT_NL] = 0;
   }
   if (b < gen)
     generic_role<S, Q, TRT>(d, b, gen);
@@ -636,18 +638,19 @@ __global__ __launch_bounds__(kBlock) void k_stream(Dev d, int gen, int bord) {
 // interface. A surviving to-gas cell has no to-liquid neighbour, so no cell is
 // asked to become two things; a cell reached from several marked cells gets
 // the same byte from each, whatever the order of the groups.
-// Turns the gas cell j into a new interface cell (static bits kept) by a
+// Turns cell j, if it still has type `from` (gas or liquid), into a new
+// interface cell with the transient bit `bit` (static bits kept) by a
 // compare-and-swap on the 32-bit word holding its flag byte; true for the one
 // caller that made the change. Plain byte stores to the other bytes of the
 // word only make the exchange retry.
-__device__ __forceinline__ bool set_new_gas(uint8_t* flags, int64_t j) {
+__device__ __forceinline__ bool set_new_type(uint8_t* flags, int64_t j, uint8_t from, uint8_t bit) {
   uint32_t* w = reinterpret_cast<uint32_t*>(flags + (j & ~(int64_t)3));
   const int sh = 8 * (int)(j & 3);
   uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
     const uint8_t f = (uint8_t)(old >> sh);
-    if ((f & T_MASK) != T_GAS) return false;
-    const uint8_t nf = (uint8_t)((f & F_STATIC) | T_IF | F_NEW_GAS);
+    if ((f & T_MASK) != from) return false;
+    const uint8_t nf = (uint8_t)((f & F_STATIC) | T_IF | bit);
     const uint32_t want = (old & ~(0xffu << sh)) | ((uint32_t)nf << sh);
     if (__hip_atomic_compare_exchange_strong(w, &old, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT))
@@ -685,11 +688,13 @@ __device__ __forceinline__ void retype_body(const Dev& d, int b, int nb, int reb
       if (j >= 0 && (fj & T_MASK) == T_GAS) {
         // the one group whose exchange turns the gas byte into an interface
         // byte lists the cell for its reinitialisation
-        if (set_new_gas(d.flags, j)) d.ng_list[atomicAdd(&d.cnt[CNT_NG], 1)] = (int32_t)j;
+        if (set_new_type(d.flags, j, T_GAS, F_NEW_GAS)) d.ng_list[atomicAdd(&d.cnt[CNT_NG], 1)] = (int32_t)j;
       }
     } else if (mk == MK_G && !nb_liq_mark) {
       if (l == 0) d.flags[c] = (uint8_t)((d.flags[c] & F_STATIC) | T_GAS | F_CONV);
-      if (j >= 0 && (fj & T_MASK) == T_LIQ) d.flags[j] = (uint8_t)((fj & F_STATIC) | T_IF | F_NEW_LIQ);
+      if (j >= 0 && (fj & T_MASK) == T_LIQ) {
+        if (set_new_type(d.flags, j, T_LIQ, F_NEW_LIQ)) d.nl_list[atomicAdd(&d.cnt[CNT_NL], 1)] = (int32_t)j;
+      }
     }
   }
 }
@@ -763,16 +768,17 @@ __device__ __forceinline__ uint4 load_flags16(const uint8_t* flags, int64_t b0, 
   return u.v;
 }
 
-// A converted cell z (Sec. 2.2): its excess mass (m - rho when filled, m when
-// emptied) is split in equal shares over its interface neighbours of the new
-// types (k_finish adds them); with no interface neighbour it is booked as lost.
-// Its mark is cleared and its fill level set to 1 or 0.
+// Flux class of an interface cell from the types around it.
+__device__ __forceinline__ uint8_t flux_class(bool has_liq, bool has_gas) {
+  return (!has_liq && has_gas) ? CLS_NOLIQ : ((!has_gas && has_liq) ? CLS_NOGAS : CLS_STD);
+}
+
+// Interface neighbours (new types) of cell z, its q-1 flag loads issued
+// together (a wall neighbour reads z itself and is ignored).
 template <int Q>
-__device__ __forceinline__ void finish_converted(const Dev& d, int64_t z) {
+__device__ __forceinline__ int count_if_nb(const Dev& d, int64_t z) {
   int x, y, zz;
   coords(d.g, z, x, y, zz);
-  // every load is issued unconditionally (a wall neighbour reads the cell
-  // itself and is then ignored), so the q-1 loads share one round trip
   uint8_t t[Q];
 #pragma unroll
   for (int k = 1; k < Q; ++k) {
@@ -781,16 +787,43 @@ __device__ __forceinline__ void finish_converted(const Dev& d, int64_t z) {
     const uint8_t f = d.flags[j >= 0 ? j : z];
     t[k] = j >= 0 ? (uint8_t)(f & T_MASK) : (uint8_t)T_NOSLIP;
   }
-  const bool liq = (d.flags[z] & T_MASK) == T_LIQ;
-  const double mz = d.m[z], rz = d.rho_if[z];
   int n = 0;
 #pragma unroll
   for (int k = 1; k < Q; ++k) n += (t[k] == T_IF) ? 1 : 0;
-  const double excess = liq ? mz - rz : mz;
-  if (n == 0)
-    d.lost[z] += excess;
-  else
-    d.xs[z] = excess / (double)n;
+  return n;
+}
+
+// Excess mass of a converted cell z (Sec. 2.2): m - rho when it filled, m
+// when it emptied; each of its interface neighbours (new types) receives an
+// equal share.
+template <int Q>
+__device__ __forceinline__ double excess_share(const Dev& d, int64_t z, bool filled) {
+  const double mz = d.m[z], rz = d.rho_if[z];
+  const int n = count_if_nb<Q>(d, z);
+  return (filled ? mz - rz : mz) / (double)n;
+}
+
+// A marked cell z, by a group of 32 lanes (lane l looks at z + c_l): if it
+// converted, with no interface neighbour (new types) its excess mass is
+// booked as lost, its mark is cleared and its fill level set to 1 or 0.
+template <int Q>
+__device__ __forceinline__ void finish_converted(const Dev& d, int64_t z, int l) {
+  const Geom& g = d.g;
+  int x, y, zz;
+  coords(g, z, x, y, zz);
+  const uint8_t fz = d.flags[z];
+  bool nb_if = false;
+  if (l > 0 && l < Q) {
+    int w;
+    const int64_t j = nb_index(g, x, y, zz, cxd(l), cyd(l), czd(l), &w);
+    const uint8_t f = d.flags[j >= 0 ? j : z];
+    nb_if = j >= 0 && (f & T_MASK) == T_IF;
+  }
+  const double mz = d.m[z], rz = d.rho_if[z];
+  const uint32_t nif = gballot(nb_if);
+  if (!(fz & F_CONV) || l != 0) return;
+  const bool liq = (fz & T_MASK) == T_LIQ;
+  if (nif == 0u) d.lost[z] += liq ? mz - rz : mz;
   d.mark[z] = MK_NONE;
   d.phiA[z] = liq ? 1.0 : 0.0;
   d.phiB[z] = liq ? 1.0 : 0.0;
@@ -799,8 +832,9 @@ __device__ __forceinline__ void finish_converted(const Dev& d, int64_t z) {
 // A new interface cell c from gas (Sec. 2.2), by a group of 32 lanes, lane k
 // looking at the neighbour x + c_k: the equilibrium of the mean density and
 // velocity of its liquid and old interface neighbours (post-collision moments
-// of this step), then the collision of this step; m = 0 (shares of converted
-// neighbours are added by k_finish).
+// of this step), then the collision of this step; rho = the mean density, m =
+// the shares of its converted neighbours (added in direction order), fill
+// level m / rho, flux classes from the neighbour types.
 template <int S, int Q, bool TRT>
 __device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) {
   using St = Store<S, Q>;
@@ -818,10 +852,12 @@ __device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) 
   uint8_t fj = 0;
   if (act && l > 0) {
     int w;
-    j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
-    if (j >= 0) fj = d.flags[j];
+    j = nb_index(g, x, y, z, cxd(k), cyd(k), czd(k), &w);
+    fj = d.flags[j >= 0 ? j : c];
   }
-  const bool use = j >= 0 && is_fluid(fj & T_MASK) && !(fj & F_NEW_GAS);
+  const int tj = j >= 0 ? (fj & T_MASK) : -1;
+  const bool use = j >= 0 && is_fluid(tj) && !(fj & F_NEW_GAS);
+  const bool cv = j >= 0 && (fj & F_CONV);
   R r = R(0), a = R(0), b = R(0), cc = R(0);
   if (use) {
     R fn[Q];
@@ -829,19 +865,91 @@ __device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) 
     for (int i = 0; i < Q; ++i) fn[i] = St::ld(B, i * stride + j, i);
     post_moments<R, Q, SH>(fn, R(d.gx), R(d.gy), R(d.gz), r, a, b, cc);
   }
+  const double share = cv ? excess_share<Q>(d, j, tj == T_LIQ) : 0.0;
+  const uint32_t liq = gballot(tj == T_LIQ), gas = gballot(tj == T_GAS), cvm = gballot(cv);
   const int cnt = __popc(gballot(use));
   const R rb = gsum(r, Q) / R(cnt);
   const R ub0 = gsum(a, Q) / R(cnt), ub1 = gsum(b, Q) / R(cnt), ub2 = gsum(cc, Q) / R(cnt);
   const R usq = ub0 * ub0 + ub1 * ub1 + ub2 * ub2;
-  const R fe = feq_k<R, Q, SH>(k, rb, rb - R(1), cdot<R>(kCX[k], kCY[k], kCZ[k], ub0, ub1, ub2), usq);
+  const R fe = feq_k<R, Q, SH>(k, rb, rb - R(1), cdot<R>(cxd(k), cyd(k), czd(k), ub0, ub1, ub2), usq);
   CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
   R rr, vx, vy, vz;
   const R fs = gcollide<R, Q, TRT, SH>(fe, l, cp, rr, vx, vy, vz);
   if (act) St::st(B, k * stride + c, k, fs);
-  if (l == 0) {
-    d.m[c] = 0.0;
-    d.rho_if[c] = (double)rb;
+  double mass = 0.0;
+  for (int i = 1; i < Q; ++i) {
+    const double si = __shfl(share, i, kG);
+    if ((cvm >> i) & 1u) mass += si;
   }
+  if (l == 0) {
+    const double rho_n = (double)rb;
+    d.m[c] = mass;
+    d.rho_if[c] = rho_n;
+    d.phiB[c] = mass / rho_n;
+    d.cls[c] = flux_class(liq != 0u, gas != 0u);
+  }
+}
+
+// Completion of the cell c = z + c_k (k = 0: z itself) for a source z of this
+// step (a cell that carries a transient bit: converted, or new interface),
+// by a group of 32 lanes (lane l looks at c + c_l), when c is an old interface
+// cell or a new one from liquid: flux classes from the new neighbour types; a
+// new cell from liquid takes rho = m = the density of its populations; the
+// shares of converted neighbours (each computed by its lane) are added in
+// direction order; fill level m / rho. Of all pairs that reach c, the one
+// whose source is the first source around c in direction order (c itself
+// first) completes it; the others stop after the flag loads. Pairs from the
+// mark list whose cell did not convert are no source and never complete.
+template <int S, int Q, bool TRT>
+__device__ __forceinline__ void complete_pair(const Dev& d, int64_t z, int k, int l) {
+  using St = Store<S, Q>;
+  using T = typename St::T;
+  const Geom& g = d.g;
+  int x, y, zz;
+  coords(g, z, x, y, zz);
+  int64_t c = z;
+  if (k > 0) {
+    int w;
+    c = nb_index(g, x, y, zz, cxd(k), cyd(k), czd(k), &w);
+    if (c < 0) return;
+    coords(g, c, x, y, zz);
+  }
+  const bool act = l > 0 && l < Q;
+  int64_t j = -1;
+  if (act) {
+    int w;
+    j = nb_index(g, x, y, zz, cxd(l), cyd(l), czd(l), &w);
+  }
+  const uint8_t fc = d.flags[c];
+  const uint8_t f = d.flags[j >= 0 ? j : c];
+  const double m_old = d.m[c], r_old = d.rho_if[c];
+  if ((fc & T_MASK) != T_IF || (fc & F_NEW_GAS)) return;
+  const int t = j >= 0 ? (f & T_MASK) : -1;
+  const bool cv = j >= 0 && (f & F_CONV);
+  const uint32_t liq = gballot(t == T_LIQ), gas = gballot(t == T_GAS), cvm = gballot(cv);
+  const uint32_t src = gballot(j >= 0 && (f & F_TRANSIENT)) | ((fc & F_NEW_LIQ) ? 1u : 0u);
+  if (__ffs(src) - 1 != opp(k)) return;  // another pair completes c (or z is no source)
+  const double share = cv ? excess_share<Q>(d, j, t == T_LIQ) : 0.0;
+  const bool new_liq = (fc & F_NEW_LIQ) != 0;
+  double pop = 0.0;
+  if (new_liq && l < Q) pop = (double)St::ld(static_cast<const T*>(d.fB), l * g.stride + c, l);
+  double mass = m_old, rho_n = r_old;
+  if (new_liq) {
+    double r = 0.0;
+    for (int i = 0; i < Q; ++i) r += __shfl(pop, i, kG);
+    rho_n = (St::kShift ? 1.0 : 0.0) + r;
+    mass = rho_n;
+  }
+  for (int i = 1; i < Q; ++i) {
+    const double si = __shfl(share, i, kG);
+    if ((cvm >> i) & 1u) mass += si;
+  }
+  if (l != 0) return;
+  d.cls[c] = flux_class(liq != 0u, gas != 0u);
+  if (!new_liq && cvm == 0u) return;  // mass and fill level unchanged
+  d.m[c] = mass;
+  d.rho_if[c] = rho_n;
+  d.phiB[c] = mass / rho_n;
 }
 
 // Tile status: two 64-bit words per tile, [epoch:16 | count:24 | count:24],
@@ -866,7 +974,10 @@ __device__ __forceinline__ unsigned long long pack2(uint32_t epoch, uint32_t a, 
 // predecessor is bounded: on expiry the scan error bit is set and the kernel
 // completes (with a wrong list, reported by the host). Skipped in a step
 // without marks (the lists are unchanged then).
-// The first `workers` blocks do the other work that k_finish waits for.
+// The first `workers` blocks complete the conversion beside the compaction:
+// converted cells, new interface cells, and the interface cells next to any
+// of them. Each of these reads only flags, and masses and populations of
+// cells other than the ones written in this launch.
 template <int S, int Q, bool TRT>
 __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int rebuild_only, int per,
                                              int workers) {
@@ -874,22 +985,52 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   __shared__ uint32_t s_epoch;
   __shared__ uint32_t s_scan[4][kCompBlock / 64];
   __shared__ uint32_t s_red[4][kCompBlock / 64];
+  // the next step's halt word: this step's, or set by an instability flagged
+  // in this step (its slot is not read by this launch)
+  if (!rebuild_only && b == 0 && threadIdx.x == 0)
+    d.cnt[CNT_HALT0 + ((d.step + 1) & 1)] =
+        (d.cnt[CNT_HALT0 + (d.step & 1)] != 0 || (d.cnt[CNT_ERR] & ERR_UNSTABLE) != 0) ? 1 : 0;
   if (!rebuild_only && halted(d)) return;
   if (b < workers) {
-    // worker blocks, beside the compaction: the converted cells (the marked
-    // cells that carry the converted bit) get their excess-mass share, the new
-    // interface cells from gas their reinitialisation
+    // worker blocks, beside the compaction, over one index space of 32-lane
+    // groups (at typical conversion rates about one item per group, so that
+    // all items proceed at once): the new interface cells from gas
+    // (reinitialisation), the marked cells (finished if they converted), and
+    // the (source, direction) pairs of the completion, sources being the
+    // converted and the new cells
     if (rebuild_only) return;
     const int nmk = d.cnt[CNT_MARK0 + (d.step & 1)];
     const int nng = d.cnt[CNT_NG];
-    for (int i = b * kCompBlock + threadIdx.x; i < nmk; i += workers * kCompBlock) {
-      const int64_t zc = d.mark_list[i];
-      if (d.flags[zc] & F_CONV) finish_converted<Q>(d, zc);
-    }
+    const int nnl = d.cnt[CNT_NL];
+    // (every item is a 32-lane group; the start and the stride are multiples
+    // of 32, so every condition below is uniform over a group)
+    const int64_t g_cv = (int64_t)nng + nmk;
+    const int64_t g_all = g_cv + ((int64_t)nmk + nng + nnl) * Q;
+    const int64_t stride = (int64_t)workers * kCompBlock;
     const int l = threadIdx.x & (kG - 1);
-    const int ngroups = workers * (kCompBlock / kG);
-    for (int item = b * (kCompBlock / kG) + threadIdx.x / kG; item < nng; item += ngroups)
-      reinit_from_gas<S, Q, TRT>(d, d.ng_list[item], l);
+    // (two loops over the thread's indices of the one space: the first ends
+    // where the second begins, so a thread with one item does only one of them)
+    int64_t it = (int64_t)b * kCompBlock + threadIdx.x;
+    for (; it < g_cv * kG; it += stride) {
+      const int64_t gi = it / kG;
+      if (gi < nng)
+        reinit_from_gas<S, Q, TRT>(d, d.ng_list[gi], l);
+      else
+        finish_converted<Q>(d, d.mark_list[gi - nng], l);
+    }
+    for (; it < g_all * kG; it += stride) {
+      const int64_t pr = it / kG - g_cv;
+      const int64_t si = pr / Q;
+      const int k = (int)(pr - si * Q);
+      int64_t z;
+      if (si < nmk)
+        z = d.mark_list[si];
+      else if (si < (int64_t)nmk + nng)
+        z = d.ng_list[si - nmk];
+      else
+        z = d.nl_list[si - nmk - nng];
+      complete_pair<S, Q, TRT>(d, z, k, l);
+    }
     return;
   }
   if (threadIdx.x == 0) {
@@ -1070,106 +1211,29 @@ __global__ __launch_bounds__(kCompBlock) void k_compact(Dev d, int rebuild_only,
 }
 
 // ---------------------------------------------------------------------------
-// k_finish: list-driven completion of the conversion, one thread per cell of
-// the new interface list.
+// k_classes: flux classes of every cell of the interface list from the types
+// around it (when a domain is set up; in a step, the compaction's worker
+// blocks update the cells whose neighbourhood changed).
 // ---------------------------------------------------------------------------
-template <int S, int Q, bool TRT>
-__device__ __forceinline__ void finish_interface(const Dev& d, int32_t e, bool classes_only) {
-  using St = Store<S, Q>;
-  using T = typename St::T;
-  using R = typename St::R;
-  constexpr bool SH = St::kShift;
-  T* B = static_cast<T*>(d.fB);
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_classes(Dev d) {
   const Geom& g = d.g;
-  const int64_t stride = g.stride;
-  const int64_t c = list_cell(e);
-  // neighbour indices and flags, all loads issued before the first use
-  // (unconditional loads: a wall neighbour reads the cell itself and is then
-  // ignored, so the loads share one round trip); a cell without the BORDER
-  // bit takes linear offsets
-  int64_t jn[Q];
-  uint8_t fn[Q];
-  if (list_border(e)) {
+  const int nif = d.cnt[CNT_IF];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nif; i += gridDim.x * kBlock) {
+    const int64_t c = list_cell(d.if_list[i]);
     int x, y, z;
     coords(g, c, x, y, z);
+    bool has_liq = false, has_gas = false;
 #pragma unroll
     for (int k = 1; k < Q; ++k) {
       int w;
-      jn[k] = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
+      const int64_t j = nb_index(g, x, y, z, kCX[k], kCY[k], kCZ[k], &w);
+      const int t = j >= 0 ? (d.flags[j] & T_MASK) : (int)T_NOSLIP;
+      has_liq |= t == T_LIQ;
+      has_gas |= t == T_GAS;
     }
-  } else {
-    const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
-#pragma unroll
-    for (int k = 1; k < Q; ++k) jn[k] = c + kCX[k] + kCY[k] * nx + kCZ[k] * nxy;
+    d.cls[c] = flux_class(has_liq, has_gas);
   }
-#pragma unroll
-  for (int k = 1; k < Q; ++k) {
-    const uint8_t f = d.flags[jn[k] >= 0 ? jn[k] : c];
-    fn[k] = jn[k] >= 0 ? f : (uint8_t)T_NOSLIP;
-  }
-  const uint8_t fl = classes_only ? (uint8_t)0 : d.flags[c];
-  const double m_old = classes_only ? 0.0 : d.m[c];
-  const double r_old = classes_only ? 0.0 : d.rho_if[c];
-  bool has_liq = false, has_gas = false, any_conv = false;
-#pragma unroll
-  for (int k = 1; k < Q; ++k) {
-    const int t = fn[k] & T_MASK;
-    has_liq |= t == T_LIQ;
-    has_gas |= t == T_GAS;
-    any_conv |= (fn[k] & F_CONV) != 0;
-  }
-  const uint8_t cls = (!has_liq && has_gas) ? CLS_NOLIQ : ((!has_gas && has_liq) ? CLS_NOGAS : CLS_STD);
-  d.cls[c] = cls;
-  if (classes_only) return;
-  if (!(fl & (F_NEW_GAS | F_NEW_LIQ)) && !any_conv) return;  // mass and fill level unchanged
-  // (a new interface cell from gas was reinitialised by the compaction kernel:
-  // m = 0 and rho_if = the reinitialisation density)
-  double mass, rho_n;
-  if (fl & F_NEW_LIQ) {
-    double r = 0.0;
-    R fc[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) fc[k] = St::ld(B, k * stride + c, k);
-#pragma unroll
-    for (int k = 0; k < Q; ++k) r += (double)fc[k];
-    rho_n = (SH ? 1.0 : 0.0) + r;
-    mass = rho_n;
-  } else {
-    mass = m_old;
-    rho_n = r_old;
-  }
-  // excess mass of converted neighbours: their equal shares (Sec. 2.2), added
-  // in direction order
-  // (directions without a converted neighbour read the cell's own entry, one
-  // cache line, so that all loads are issued together)
-  double sh[Q];
-#pragma unroll
-  for (int k = 1; k < Q; ++k) sh[k] = d.xs[(fn[k] & F_CONV) ? jn[k] : c];
-#pragma unroll
-  for (int k = 1; k < Q; ++k)
-    if (fn[k] & F_CONV) mass += sh[k];
-  d.m[c] = mass;
-  d.rho_if[c] = rho_n;
-  d.phiB[c] = mass / rho_n;
-}
-
-template <int S, int Q, bool TRT>
-__device__ __forceinline__ void finish_body(const Dev& d, int b, int nb, int classes_only) {
-  // the next step's halt word: this step's, or set by an instability flagged
-  // in this step (written before any early return, read from the next step on)
-  if (b == 0 && threadIdx.x == 0)
-    d.cnt[CNT_HALT0 + ((d.step + 1) & 1)] =
-        (d.cnt[CNT_HALT0 + (d.step & 1)] != 0 || (d.cnt[CNT_ERR] & ERR_UNSTABLE) != 0) ? 1 : 0;
-  if (!classes_only && halted(d)) return;
-  if (!classes_only && d.cnt[CNT_MARK0 + (d.step & 1)] == 0) return;
-  const int nif = d.cnt[CNT_IF];
-  for (int i = b * kBlock + threadIdx.x; i < nif; i += nb * kBlock)
-    finish_interface<S, Q, TRT>(d, d.if_list[i], classes_only != 0);
-}
-
-template <int S, int Q, bool TRT>
-__global__ __launch_bounds__(kBlock) void k_finish(Dev d, int classes_only) {
-  finish_body<S, Q, TRT>(d, (int)blockIdx.x, (int)gridDim.x, classes_only);
 }
 
 // ---------------------------------------------------------------------------
@@ -1194,7 +1258,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Dev d) {
     const int rr = e - lz * (TY + 2) * (TX + 2);
     const int ly = rr / (TX + 2), lx = rr - ly * (TX + 2);
     int w;
-    const int64_t j = nb_index(g, tx0 + lx - 1, ty0 + ly - 1, tz + lz - 1, 0, 0, 0, &w);
+    const int64_t j = wrap_index(g, tx0 + lx - 1, ty0 + ly - 1, tz + lz - 1, &w);
     const bool ob = (j < 0) || is_obst(d.flags[j] & T_MASK);
     s_obs[lz][ly][lx] = ob;
     s_phi[lz][ly][lx] = ob ? 0.0 : d.phiA[j];

@@ -27,7 +27,7 @@ struct Layout {
   int64_t N, stride, tiles, conv_per, red_blocks;
   size_t off_fA, off_fB, off_flags, off_mark, off_cls, off_phiA, off_phiB, off_m, off_rho_if,
       off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_gen_list,
-      off_mark_list, off_ng_list, off_xs, off_cnt, off_scan_status,
+      off_mark_list, off_ng_list, off_nl_list, off_cnt, off_scan_status,
       off_pv, off_partial, off_stage, total;
 };
 
@@ -67,7 +67,7 @@ inline Layout make_layout(const fslbm_params& p) {
   L.off_gen_list = take(4 * L.N);
   L.off_mark_list = take(4 * L.N);
   L.off_ng_list = take(4 * L.N);
-  L.off_xs = take(8 * L.N);
+  L.off_nl_list = take(4 * L.N);
   L.off_cnt = take(4 * CNT_N);
   L.off_scan_status = take(16 * L.tiles);
   L.off_pv = take(8 * 8);
@@ -160,19 +160,27 @@ inline unsigned retype_blocks(const fslbm_ctx* c) {
   return (unsigned)std::min<int64_t>(b, 512);
 }
 
-// k_finish: one thread per interface cell
-inline unsigned finish_blocks(const fslbm_ctx* c) {
+// k_classes and k_curvature: one thread per interface cell
+inline unsigned list_blocks(const fslbm_ctx* c) {
   int64_t b = grid_for(c->L.N) / 32 + 16;
   return (unsigned)std::min<int64_t>(b, 512);
 }
 
+// worker blocks of the compaction: about one thread per (changed cell,
+// direction) pair at typical conversion rates
+inline int compact_workers(const fslbm_ctx* c) {
+  return (int)std::max<int64_t>(8, std::min<int64_t>(grid_for(c->L.N) / 64, 256));
+}
+
 // One batched step over the resident runs of one (storage, lattice,
 // collision, addressing) group: device tables of the four launches.
+constexpr int kLaunches = 3;  // streaming, re-typing, compaction and completion
+
 struct BatchLaunch {
   const Dev* devs = nullptr;
-  const BatchEntry* tab[4] = {nullptr, nullptr, nullptr, nullptr};  // stream, retype, compact, finish
-  int n = 0;                       // entries of each table (one per run)
-  int blocks[4] = {0, 0, 0, 0};    // blocks of each launch
+  const BatchEntry* tab[kLaunches] = {nullptr, nullptr, nullptr};  // one table per launch
+  int n = 0;                                 // entries of each table (one per run)
+  int blocks[kLaunches] = {0, 0, 0};         // blocks of each launch
   bool buf = true;                 // buffer addressing (every grid below 2 GiB)
 };
 
@@ -180,7 +188,7 @@ struct BatchLaunch {
 struct Ops {
   void (*step)(fslbm_ctx*, hipStream_t);
   void (*convert)(fslbm_ctx*, hipStream_t, int rebuild_only);
-  void (*finish)(fslbm_ctx*, hipStream_t, int classes_only);
+  void (*classes)(fslbm_ctx*, hipStream_t);
   void (*reduce_mass)(fslbm_ctx*, hipStream_t);
   void (*batch_step)(const BatchLaunch&, hipStream_t, int64_t tick);
   void (*init_state)(fslbm_ctx*, hipStream_t, int resume);
@@ -219,13 +227,12 @@ struct Impl {
   }
   static void convert(fslbm_ctx* c, hipStream_t s, int rebuild) {
     hipLaunchKernelGGL((k_retype<Q>), dim3(retype_blocks(c)), dim3(kBlock), 0, s, c->d, rebuild);
-    const int workers = rebuild ? 0 : (int)(retype_blocks(c) + 3) / 4;
+    const int workers = rebuild ? 0 : compact_workers(c);
     hipLaunchKernelGGL((k_compact<S, Q, TRT>), dim3((unsigned)(c->L.tiles + workers)), dim3(kCompBlock),
                        0, s, c->d, rebuild, (int)c->L.conv_per, workers);
   }
-  static void finish(fslbm_ctx* c, hipStream_t s, int classes_only) {
-    hipLaunchKernelGGL((k_finish<S, Q, TRT>), dim3(finish_blocks(c)), dim3(kBlock), 0, s, c->d,
-                       classes_only);
+  static void classes(fslbm_ctx* c, hipStream_t s) {
+    hipLaunchKernelGGL((k_classes<Q>), dim3(list_blocks(c)), dim3(kBlock), 0, s, c->d);
   }
   static void batch_step(const BatchLaunch& bl, hipStream_t s, int64_t tick) {
     if (bl.n == 0) return;
@@ -239,8 +246,6 @@ struct Impl {
                        bl.n, tick);
     hipLaunchKernelGGL((kb_compact<S, Q, TRT>), dim3((unsigned)bl.blocks[2]), dim3(kCompBlock), 0, s,
                        bl.devs, bl.tab[2], bl.n, tick);
-    hipLaunchKernelGGL((kb_finish<S, Q, TRT>), dim3((unsigned)bl.blocks[3]), dim3(kBlock), 0, s, bl.devs,
-                       bl.tab[3], bl.n, tick);
   }
   static void reduce_mass(fslbm_ctx* c, hipStream_t s) {
     hipLaunchKernelGGL((k_reduce_mass<S, Q>), dim3((unsigned)c->L.red_blocks), dim3(kBlock), 0, s,
@@ -262,7 +267,7 @@ struct Impl {
                        what);
   }
   static constexpr Ops ops() {
-    return Ops{&step, &convert, &finish, &reduce_mass, &batch_step, &init_state, &init_flags, &import_plane,
+    return Ops{&step, &convert, &classes, &reduce_mass, &batch_step, &init_state, &init_flags, &import_plane,
                &export_field};
   }
 };

@@ -5,7 +5,8 @@
 * taylor512 (D3Q27, surface tension, bubble model) in FP64 mode against the
   oracle;
 * cyl256 (D3Q27 TRT, free-slip walls, 8.4 M cells) in FP32: mass conservation,
-  the interface list, and the mirror symmetries of the setup."""
+  the interface list, and the mirror symmetries of the setup (in bulk); the
+  same run in FP64: the symmetries to rounding."""
 import numpy as np
 import pytest
 
@@ -47,10 +48,24 @@ def test_taylor512_fp64_parity():
     g.close()
 
 
+def _mirror_diffs(f, p):
+    """(share of cells whose type differs, |phi| differences over the cells
+    that are interface on both sides) for the x mirror, the y mirror and the
+    x <-> y swap."""
+    t3 = f["type"].reshape(p.nz, p.ny, p.nx)
+    phi = f["phi"].reshape(p.nz, p.ny, p.nx)
+    out = []
+    for mt, mp in ((t3[:, :, ::-1], phi[:, :, ::-1]), (t3[:, ::-1, :], phi[:, ::-1, :]),
+                   (t3.transpose(0, 2, 1), phi.transpose(0, 2, 1))):
+        same = mt == t3
+        both_if = same & (t3 == I.INTERFACE)
+        out.append((1.0 - same.mean(), np.abs(mp[both_if] - phi[both_if])))
+    return out
+
+
 def test_cyl256_fp32_properties():
     from paper_2207_13962_amd.fslbm import Simulation
     s = I.workload("cyl256")
-    p = s.params
     g = Simulation(s)
     m0 = g.mass()["total_mass"]
     g.step(300)
@@ -60,21 +75,33 @@ def test_cyl256_fp32_properties():
     g.close()
     assert r["status"] == 0
     assert abs(r["total_mass"] - m0) / m0 < 1e-6
-    t = f["type"]
-    assert np.array_equal(lst, np.nonzero(t == I.INTERFACE)[0])
+    assert np.array_equal(lst, np.nonzero(f["type"] == I.INTERFACE)[0])
     assert r["n_interface"] == lst.size
-    # the column is centred between cells: mirror symmetric in x and y and
-    # symmetric under x <-> y. FP32 sums run in a different order on the
-    # mirrored side: almost every fill level agrees to rounding, while a
-    # conversion that happens one step apart on the two sides moves mass of
-    # order 1e-3 in a few cells.
-    t3 = t.reshape(p.nz, p.ny, p.nx)
-    phi = f["phi"].reshape(p.nz, p.ny, p.nx)
-    for mt, mp in ((t3[:, :, ::-1], phi[:, :, ::-1]), (t3[:, ::-1, :], phi[:, ::-1, :]),
-                   (t3.transpose(0, 2, 1), phi.transpose(0, 2, 1))):
-        same = mt == t3
-        assert same.mean() > 1 - 1e-4
-        both_if = same & (t3 == I.INTERFACE)
-        dphi = np.abs(mp[both_if] - phi[both_if])
-        assert np.quantile(dphi, 0.999) < 1e-5
-        assert dphi.max() < 1e-2
+    # the column is centred between cells, so the run is mirror symmetric in
+    # x and y and symmetric under x <-> y up to rounding. In FP32 the sums on
+    # the two sides run in different orders; a conversion that one rounding
+    # puts a step earlier on one side then perturbs its neighbourhood, so the
+    # bound is on the bulk (99 % of the interface cells) and on how many cells
+    # are off (the FP64 run below is symmetric to rounding everywhere).
+    for differ, dphi in _mirror_diffs(f, s.params):
+        assert differ < 1e-5
+        assert np.quantile(dphi, 0.99) < 2e-5
+        assert (dphi > 1e-3).mean() < 5e-3
+
+
+def test_cyl256_fp64_symmetry():
+    """The same run with FP64 populations: types identical and fill levels
+    equal to 1e-11 under both mirrors and the swap."""
+    from paper_2207_13962_amd.fslbm import Simulation
+    s = I.workload("cyl256", storage=I.F64)
+    g = Simulation(s)
+    m0 = g.mass()["total_mass"]
+    g.step(300)
+    r = g.mass()
+    f = g.fields(pdf=False)
+    g.close()
+    assert r["status"] == 0
+    assert abs(r["total_mass"] - m0) / m0 < 1e-12
+    for differ, dphi in _mirror_diffs(f, s.params):
+        assert differ == 0.0
+        assert dphi.max() < 1e-11
