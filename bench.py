@@ -34,7 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-KERNEL_SOURCES = ["paper_2207_13962_amd/csrc/fslbm_kernels.h", "paper_2207_13962_amd/csrc/fslbm_device.h"]
+KERNEL_SOURCES = ["paper_2207_13962_amd/csrc/fslbm_kernels.h", "paper_2207_13962_amd/csrc/fslbm_device.h",
+                  "paper_2207_13962_amd/csrc/fslbm_ops.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_dam256_traffic.txt")
 
 
