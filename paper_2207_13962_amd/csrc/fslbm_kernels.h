@@ -728,6 +728,37 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
   return before + inc - v;
 }
 
+// The same for four counts at once, packed in 16-bit fields (every prefix and
+// the total of each count below 2^16): one scan instead of four.
+template <int NT>
+__device__ __forceinline__ void block_excl_scan4(const uint32_t v[4], unsigned long long* sh, uint32_t pre[4],
+                                                 uint32_t tot[4]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long p = (unsigned long long)v[0] | ((unsigned long long)v[1] << 16) |
+                               ((unsigned long long)v[2] << 32) | ((unsigned long long)v[3] << 48);
+  unsigned long long inc = p;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  unsigned long long before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    if (w < wv) before += sh[w];
+    all += sh[w];
+  }
+  __syncthreads();
+  const unsigned long long ex = before + inc - p;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    pre[i] = (uint32_t)(ex >> (16 * i)) & 0xffffu;
+    tot[i] = (uint32_t)(all >> (16 * i)) & 0xffffu;
+  }
+}
+
 // Counts of the four lists over the cells [b, e) of one thread, vectors of
 // 16 flag bytes (b is a multiple of 64). Chunks are the 64-cell blocks of the
 // range that hold a liquid cell away from walls.
@@ -751,9 +782,11 @@ __device__ __forceinline__ uint32_t mask_of(const uint4& v, int64_t b0, int64_t 
     else if (which == 2) hit = (f & (T_MASK | F_COMPLEX)) == T_LIQ;
     else if (which == 3) hit = (f & (T_MASK | F_COMPLEX)) == (T_LIQ | F_COMPLEX);
     else hit = (f & (T_MASK | F_BORDER)) == (T_IF | F_BORDER);
-    if (hit && b0 + j < N) m |= 1u << j;
+    m |= hit ? 1u << j : 0u;
   }
-  return m;
+  // the cells of the vector inside the grid
+  const uint32_t lim = b0 + 16 <= N ? 0xffffu : (b0 < N ? (1u << (uint32_t)(N - b0)) - 1u : 0u);
+  return m & lim;
 }
 
 __device__ __forceinline__ uint4 load_flags16(const uint8_t* flags, int64_t b0, int64_t N) {
@@ -984,6 +1017,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   __shared__ int s_tile, s_run;
   __shared__ uint32_t s_epoch;
   __shared__ uint32_t s_scan[4][kCompBlock / 64];
+  __shared__ unsigned long long s_scan4[kCompBlock / 64];
   __shared__ uint32_t s_red[4][kCompBlock / 64];
   // the next step's halt word: this step's, or set by an instability flagged
   // in this step (its slot is not read by this launch)
@@ -1033,6 +1067,18 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
     }
     return;
   }
+  // the first 16 flag bytes of this thread, for the tile that the launch
+  // order gives the block, requested before the ticket round trip (the ticket
+  // almost always agrees; when it does not, they are loaded again)
+  constexpr int kBatch = 4;
+  const int64_t N = d.g.N;
+  const int nvec = per / 16;
+  const int spec = b - workers;
+  uint4 first;
+  {
+    const int64_t b0 = ((int64_t)spec * kCompBlock + threadIdx.x) * per;
+    first = b0 < N ? load_flags16(d.flags, b0, N) : make_uint4(0, 0, 0, 0);
+  }
   if (threadIdx.x == 0) {
     // the mark count, the epoch and the ticket in one round trip (a ticket
     // taken in a step without marks is harmless: the counter is reset before
@@ -1047,14 +1093,12 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   if (s_run == 0) return;
   const int tile = s_tile;
   const uint32_t epoch = s_epoch;
-  const int64_t N = d.g.N;
   const int64_t base = ((int64_t)tile * kCompBlock + threadIdx.x) * per;
-  const int nvec = per / 16;
+  if (tile != spec) first = base < N ? load_flags16(d.flags, base, N) : make_uint4(0, 0, 0, 0);
   // threads per 64-cell chunk (per < 64), else chunks per thread
   const int tpc = per < 64 ? 64 / per : 1;
   // pass 1: masks and counts, in batches of kBatch 16-byte vectors requested
   // together; the masks of the first batch are kept for pass 2
-  constexpr int kBatch = 4;
   uint32_t keep[5][kBatch];  // the four lists, and interface cells with the BORDER bit
   uint32_t c[4] = {0, 0, 0, 0};
   uint32_t own_any = 0;
@@ -1066,7 +1110,10 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         const int64_t b0 = base + 16 * (v0 + u);
-        vec[u] = (v0 + u < nvec && b0 < N) ? load_flags16(d.flags, b0, N) : make_uint4(0, 0, 0, 0);
+        if (v0 + u == 0)
+          vec[u] = first;
+        else
+          vec[u] = (v0 + u < nvec && b0 < N) ? load_flags16(d.flags, b0, N) : make_uint4(0, 0, 0, 0);
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
@@ -1100,8 +1147,13 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
     c[2] = ((threadIdx.x % tpc) == 0) ? lead_any : 0u;
   }
   uint32_t pre[4], tot[4];
+  if (per <= 32) {
+    // every count of the tile stays below 1024 * 32 < 2^16
+    block_excl_scan4<kCompBlock>(c, s_scan4, pre, tot);
+  } else {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) pre[i] = block_excl_scan<kCompBlock>(c[i], s_scan[i], &tot[i]);
+    for (int i = 0; i < 4; ++i) pre[i] = block_excl_scan<kCompBlock>(c[i], s_scan[i], &tot[i]);
+  }
   unsigned long long* st = d.scan_status;
   if (threadIdx.x == 0) {
     __hip_atomic_store(&st[2 * tile], pack2(epoch, tot[0], tot[1]), __ATOMIC_RELAXED,

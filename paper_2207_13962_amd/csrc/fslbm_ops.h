@@ -173,7 +173,7 @@ inline int compact_workers(const fslbm_ctx* c) {
 }
 
 // One batched step over the resident runs of one (storage, lattice,
-// collision, addressing) group: device tables of the four launches.
+// collision, addressing) group: device tables of its launches.
 constexpr int kLaunches = 3;  // streaming, re-typing, compaction and completion
 
 struct BatchLaunch {
