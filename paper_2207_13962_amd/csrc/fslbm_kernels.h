@@ -728,34 +728,67 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, ui
   return before + inc - v;
 }
 
-// The same for four counts at once, packed in 16-bit fields (every prefix and
-// the total of each count below 2^16): one scan instead of four.
+// Inclusive prefix sum within each 16-lane row (DPP row shifts by 1, 2, 4, 8;
+// lanes shifted in from outside the row read 0).
+__device__ __forceinline__ uint32_t row_scan(uint32_t x) {
+  int v = (int)x;
+  v += dpp32<0x111>(v);
+  v += dpp32<0x112>(v);
+  v += dpp32<0x114>(v);
+  v += dpp32<0x118>(v);
+  return (uint32_t)v;
+}
+
+// Sum over the 64 lanes of the wave (integer): the 32-lane group sum, then
+// both halves read as scalars.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+  int v = (int)x;
+  v += dpp32<kDppXor1>(v);
+  v += dpp32<kDppXor2>(v);
+  v += dpp32<kDppHalfMirror>(v);
+  v += dpp32<kDppMirror>(v);
+  v += __builtin_amdgcn_ds_swizzle(v, kSwzXor16);
+  return (uint32_t)(__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 32));
+}
+
+// The block scan for four counts at once, packed two to a 32-bit word in
+// 16-bit fields (every prefix and the total of each count below 2^16, so no
+// sum carries into the next field or word): row scans by DPP, the rows of a
+// wave joined by scalar reads of their totals, the waves through LDS.
 template <int NT>
-__device__ __forceinline__ void block_excl_scan4(const uint32_t v[4], unsigned long long* sh, uint32_t pre[4],
+__device__ __forceinline__ void block_excl_scan4(const uint32_t v[4], uint32_t (*sh)[NT / 64], uint32_t pre[4],
                                                  uint32_t tot[4]) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const unsigned long long p = (unsigned long long)v[0] | ((unsigned long long)v[1] << 16) |
-                               ((unsigned long long)v[2] << 32) | ((unsigned long long)v[3] << 48);
-  unsigned long long inc = p;
+  const uint32_t p[2] = {v[0] | (v[1] << 16), v[2] | (v[3] << 16)};
+  uint32_t inc[2];
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const unsigned long long t = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += t;
+  for (int h = 0; h < 2; ++h) {
+    uint32_t x = row_scan(p[h]);
+    const uint32_t r0 = __builtin_amdgcn_readlane(x, 15), r1 = __builtin_amdgcn_readlane(x, 31),
+                   r2 = __builtin_amdgcn_readlane(x, 47);
+    const int row = lane >> 4;
+    x += (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
+    inc[h] = x;
+    if (lane == 63) sh[h][wv] = x;
   }
-  if (lane == 63) sh[wv] = inc;
   __syncthreads();
-  unsigned long long before = 0, all = 0;
+  uint32_t before[2] = {0, 0}, all[2] = {0, 0};
 #pragma unroll
   for (int w = 0; w < NT / 64; ++w) {
-    if (w < wv) before += sh[w];
-    all += sh[w];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (w < wv) before[h] += sh[h][w];
+      all[h] += sh[h][w];
+    }
   }
   __syncthreads();
-  const unsigned long long ex = before + inc - p;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    pre[i] = (uint32_t)(ex >> (16 * i)) & 0xffffu;
-    tot[i] = (uint32_t)(all >> (16 * i)) & 0xffffu;
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t ex = before[h] + inc[h] - p[h];
+    pre[2 * h] = ex & 0xffffu;
+    pre[2 * h + 1] = ex >> 16;
+    tot[2 * h] = all[h] & 0xffffu;
+    tot[2 * h + 1] = all[h] >> 16;
   }
 }
 
@@ -766,23 +799,32 @@ struct ListCounts {
   uint32_t n[4];  // interface, converted, chunks, COMPLEX liquid
 };
 
+// Per-byte tests on four flag bytes at once (one 32-bit word): a 4-bit mask
+// of the bytes whose bits under `mask` equal `val` (an exact zero-byte test:
+// no carry crosses a byte), and of the bytes with bit `bit` set.
+__device__ __forceinline__ uint32_t bytes_eq4(uint32_t w, uint32_t mask, uint32_t val) {
+  const uint32_t x = (w & (mask * 0x01010101u)) ^ (val * 0x01010101u);
+  const uint32_t z = ~(((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x | 0x7f7f7f7fu);  // 0x80 in the zero bytes
+  // the byte-top bits 7, 15, 23, 31 gathered into bits 21..24 by one product
+  return (((z >> 7) * 0x00204081u) >> 21) & 0xfu;
+}
+static_assert(F_CONV == (1u << 6), "bytes_bit4 below tests bit 6");
+__device__ __forceinline__ uint32_t bytes_bit4(uint32_t w, int bit) {
+  return ((((w >> bit) & 0x01010101u) * 0x00204081u) >> 21) & 0xfu;
+}
+
 __device__ __forceinline__ uint32_t mask_of(const uint4& v, int64_t b0, int64_t N, int which) {
-  union {
-    uint4 v;
-    uint8_t b[16];
-  } u;
-  u.v = v;
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
   uint32_t m = 0;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const uint8_t f = u.b[j];
-    bool hit;
-    if (which == 0) hit = (f & T_MASK) == T_IF;
-    else if (which == 1) hit = (f & F_CONV) != 0;
-    else if (which == 2) hit = (f & (T_MASK | F_COMPLEX)) == T_LIQ;
-    else if (which == 3) hit = (f & (T_MASK | F_COMPLEX)) == (T_LIQ | F_COMPLEX);
-    else hit = (f & (T_MASK | F_BORDER)) == (T_IF | F_BORDER);
-    m |= hit ? 1u << j : 0u;
+  for (int q = 0; q < 4; ++q) {
+    uint32_t n;
+    if (which == 0) n = bytes_eq4(w[q], T_MASK, T_IF);
+    else if (which == 1) n = bytes_bit4(w[q], 6);  // F_CONV
+    else if (which == 2) n = bytes_eq4(w[q], T_MASK | F_COMPLEX, T_LIQ);
+    else if (which == 3) n = bytes_eq4(w[q], T_MASK | F_COMPLEX, T_LIQ | F_COMPLEX);
+    else n = bytes_eq4(w[q], T_MASK | F_BORDER, T_IF | F_BORDER);
+    m |= n << (4 * q);
   }
   // the cells of the vector inside the grid
   const uint32_t lim = b0 + 16 <= N ? 0xffffu : (b0 < N ? (1u << (uint32_t)(N - b0)) - 1u : 0u);
@@ -1017,7 +1059,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   __shared__ int s_tile, s_run;
   __shared__ uint32_t s_epoch;
   __shared__ uint32_t s_scan[4][kCompBlock / 64];
-  __shared__ unsigned long long s_scan4[kCompBlock / 64];
+  __shared__ uint32_t s_scan4[2][kCompBlock / 64];
   __shared__ uint32_t s_red[4][kCompBlock / 64];
   // the next step's halt word: this step's, or set by an instability flagged
   // in this step (its slot is not read by this launch)
@@ -1186,8 +1228,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      uint32_t x = acc[i];
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      const uint32_t x = wave_sum(acc[i]);
       if (lane == 0) s_red[i][wv] = x;
     }
   }
