@@ -158,6 +158,59 @@ def write_trace_summary(trace_dir, out_path, last, command):
     print(open(out_path).read())
 
 
+def scale_point(args, variant=3, warm=200, timed=200):
+    """The streaming kernel on the dam break scaled 2x per axis (512x256x128,
+    8.4x the fluid cells, a working set well beyond the Infinity Cache): its
+    algorithmic HBM rate where bandwidth and not latency bounds the step.
+    Context for the roofline above, not the headline workload."""
+    import torch
+    from paper_2207_13962_amd import inputs as I
+    from paper_2207_13962_amd.fslbm import Simulation
+
+    s = I.workload("dam512", **({"smagorinsky": args.les} if args.les else {}))
+    p = s.params
+    sb = {I.F64: 8, I.F32: 4, I.F16S: 2}[p.storage]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim = Simulation(s, variant=variant, device="cuda:0", stream=stream)
+        sim.step(warm)
+        stream.synchronize()
+        b = sim.mass(check=False)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        sim.step(timed)
+        ev1.record(stream)
+        stream.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        sim.set_timing(timed)
+        kb = sim.mass(check=False)
+        sim.step(timed)
+        stream.synchronize()
+        ka = sim.mass(check=False)
+        n, kms = sim.kernel_time()
+        sim.set_timing(0)
+        sim.close()
+    nfl = 0.5 * (kb["n_liquid"] + kb["n_interface"] + ka["n_liquid"] + ka["n_interface"])
+    per_launch = nfl * bytes_per_update(p.q, sb)
+    achieved = per_launch / (kms / n * 1e-3) / 1e9
+    step_updates = 0.5 * (b["n_liquid"] + b["n_interface"] + kb["n_liquid"] + kb["n_interface"]) * timed
+    return {
+        "workload": "dam512: rectangular dam break %dx%dx%d, D3Q%d TRT%s, variant %s, steps %d-%d"
+                    % (p.nx, p.ny, p.nz, p.q, " + LES" if args.les else "", I.VARIANT_NAMES[variant],
+                       warm, warm + 2 * timed),
+        "fluid_cells": int(ka["n_liquid"] + ka["n_interface"]),
+        "mlups": step_updates / (ms * 1e-3) / 1e6,
+        "kernel": "k_stream",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "avg_launch_ms": kms / n,
+        "bytes_per_launch": per_launch,
+        "status": "ok" if ka["status"] == 0 else "unstable (%d)" % ka["status"],
+    }
+
+
 def copy_calibration():
     """A plain device copy of COPY_BYTES, five times (run under rocprofv3
     counters to calibrate FETCH_SIZE and WRITE_SIZE)."""
@@ -340,6 +393,8 @@ def main():
     ap.add_argument("--dam-steps", type=int, default=1500, help="precision study: dam-break steps")
     ap.add_argument("--taylor-steps", type=int, default=10000, help="precision study: Taylor-bubble steps")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-scale-point", action="store_true",
+                    help="skip the streaming kernel on the dam break scaled 2x per axis")
     ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
     ap.add_argument("--requests", type=int, default=48, help="serving: runs in the mix")
     ap.add_argument("--l-min", type=int, default=32, help="serving: smallest domain edge")
@@ -510,6 +565,11 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if not args.no_scale_point:
+        try:
+            out["roofline_dam512"] = scale_point(args)
+        except Exception as e:  # context only: never hides the headline result
+            out["roofline_dam512"] = {"error": repr(e)}
     if not args.no_serving:
         try:
             out["serving"] = serving_section(args)
