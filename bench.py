@@ -223,6 +223,37 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 5}))
 
 
+def copy_rate():
+    """Device-to-device copy rate of a 1 GiB buffer (read + write bytes per
+    second, best of five), the bandwidth a plain streaming kernel reaches."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 0.0
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2.0 * COPY_BYTES / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(setup_fn, steps):
     """FP64 oracle on the host: fluid+interface updates per second over `steps`
     steps of the same workload (single thread)."""
@@ -512,6 +543,10 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic()
     whole_gbs = updates * bytes_per_update(p.q, sb) / (ms * 1e-3) / 1e9
+    try:
+        copy_gbs = copy_rate()
+    except Exception:  # context only
+        copy_gbs = None
 
     cpu = None
     if not args.no_cpu:
@@ -520,7 +555,7 @@ def main():
             cpu = {"value": v, "unit": "MLUPS", "cores": 1, "kind": "oracle",
                    "sample": "first %d steps of the %s workload (%dx%dx%d, FP64 oracle, variant OM),"
                              " %.1f s" % (args.cpu_steps, args.workload, p.nx, p.ny, p.nz, dt),
-                   "host_cpus": os.cpu_count()}
+                   "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model()}
         except Exception as e:  # the baseline must never hide the GPU result
             cpu = {"value": None, "error": repr(e)}
 
@@ -544,6 +579,8 @@ def main():
             "cells": p.n,
             "parallelism": "single GPU",
             "effective_GBps_whole_step": whole_gbs,
+            "effective_whole_step_frac_of_peak": whole_gbs / HBM_PEAK_GBS,
+            "copy_GBps_measured": copy_gbs,
             "smagorinsky": args.les,
             "step_launches": "kernel by kernel" if args.no_graphs else "replayed HIP graphs of 8 steps",
             "per_variant": per_variant,
@@ -562,6 +599,7 @@ def main():
             "avg_launch_ms": avg_ms,
             "launches": launches,
             "bytes_per_launch": bytes_per_launch,
+            "frac_of_measured_copy": achieved / copy_gbs if copy_gbs else None,
         },
         "cpu_baseline": cpu,
     }
