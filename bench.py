@@ -173,6 +173,7 @@ def scale_point(args, variant=3, warm=200, timed=200):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         sim = Simulation(s, variant=variant, device="cuda:0", stream=stream)
+        sim.set_graphs(not args.no_graphs)
         sim.step(warm)
         stream.synchronize()
         b = sim.mass(check=False)
@@ -426,6 +427,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-scale-point", action="store_true",
                     help="skip the streaming kernel on the dam break scaled 2x per axis")
+    ap.add_argument("--scale-only", action="store_true",
+                    help="only the streaming kernel on the dam break scaled 2x per axis (kernel by kernel)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
     ap.add_argument("--requests", type=int, default=48, help="serving: runs in the mix")
     ap.add_argument("--l-min", type=int, default=32, help="serving: smallest domain edge")
@@ -476,6 +479,9 @@ def main():
         return
     if args.precision_study:
         print(json.dumps(precision_study(args)))
+        return
+    if args.scale_only:
+        print(json.dumps(scale_point(args)))
         return
     variants = [int(v) for v in args.variants.split(",")]
     setup_fn = lambda: I.workload(args.workload, **({"smagorinsky": args.les} if args.les else {}))  # noqa: E731
