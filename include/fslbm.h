@@ -153,6 +153,15 @@ int fslbm_kernel_time(fslbm_ctx* ctx, int64_t* launches, double* total_ms);
  * identical either way. Errors: FSLBM_EINVAL (NULL). */
 int fslbm_set_graphs(fslbm_ctx* ctx, int enable);
 
+/* Compaction tile size: every thread of a 1024-thread compaction tile scans
+ * cells_per_thread consecutive cells (16 times a power of two). The library
+ * picks the smallest size that keeps the tile count within its status array;
+ * a larger one (fewer, longer tiles) is accepted, a smaller one is not. It
+ * changes the work split only: results are identical. For tuning and for
+ * exercising every tile shape on small domains. Errors: FSLBM_EINVAL (NULL,
+ * not 16 times a power of two, below the library's size, above 4096). */
+int fslbm_set_compaction_tile(fslbm_ctx* ctx, int cells_per_thread);
+
 /* Releases the context (NULL-safe; never fails). Does not free a caller arena. */
 void fslbm_destroy(fslbm_ctx* ctx);
 

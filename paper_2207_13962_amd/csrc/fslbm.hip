@@ -430,6 +430,18 @@ int fslbm_set_graphs(fslbm_ctx* c, int enable) {
   return FSLBM_OK;
 }
 
+int fslbm_set_compaction_tile(fslbm_ctx* c, int cells_per_thread) {
+  if (!c) return FSLBM_EINVAL;
+  const int64_t per = cells_per_thread;
+  const bool pow2 = per >= 16 && per % 16 == 0 && ((per / 16) & (per / 16 - 1)) == 0;
+  if (!pow2 || per < c->L.conv_per || per > 4096) return FSLBM_EINVAL;
+  // fewer tiles than the status array was sized for
+  c->L.conv_per = per;
+  c->L.tiles = (c->L.N + (int64_t)kCompBlock * per - 1) / ((int64_t)kCompBlock * per);
+  drop_graph(c);  // the tile count and size are launch arguments of the captured steps
+  return FSLBM_OK;
+}
+
 int fslbm_set_timing(fslbm_ctx* c, int64_t capacity) {
   if (!c || capacity < 0) return FSLBM_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -51,8 +51,8 @@ _lib = None
 
 EXPORTED = ["fslbm_workspace_bytes", "fslbm_create", "fslbm_set_variant", "fslbm_step",
             "fslbm_mass", "fslbm_fields", "fslbm_interface_list", "fslbm_set_timing",
-            "fslbm_kernel_time", "fslbm_set_graphs", "fslbm_destroy", "fslbm_strerror",
-            "fslbm_last_error", "fslbm_server_create", "fslbm_server_submit",
+            "fslbm_kernel_time", "fslbm_set_graphs", "fslbm_set_compaction_tile", "fslbm_destroy",
+            "fslbm_strerror", "fslbm_last_error", "fslbm_server_create", "fslbm_server_submit",
             "fslbm_server_advance", "fslbm_server_poll", "fslbm_server_result",
             "fslbm_server_stats_get", "fslbm_server_destroy"]
 
@@ -93,6 +93,8 @@ def load_library(path: str = LIB_PATH):
     lib.fslbm_kernel_time.restype = C.c_int
     lib.fslbm_set_graphs.argtypes = [vp, C.c_int]
     lib.fslbm_set_graphs.restype = C.c_int
+    lib.fslbm_set_compaction_tile.argtypes = [vp, C.c_int]
+    lib.fslbm_set_compaction_tile.restype = C.c_int
     lib.fslbm_destroy.argtypes = [vp]
     lib.fslbm_destroy.restype = None
     lib.fslbm_strerror.argtypes = [C.c_int]
@@ -246,6 +248,11 @@ class Simulation:
     def set_graphs(self, enable):
         """Replay captured step graphs (default) or launch kernel by kernel."""
         self._check(self._lib.fslbm_set_graphs(self._h, int(bool(enable))))
+
+    def set_compaction_tile(self, cells_per_thread):
+        """Cells scanned per thread of a compaction tile (16 times a power of
+        two, at least the library's choice); results are identical."""
+        self._check(self._lib.fslbm_set_compaction_tile(self._h, int(cells_per_thread)))
 
     def set_timing(self, capacity):
         """Bracket the next `capacity` streaming-kernel launches (one per step) with HIP events."""

@@ -93,8 +93,7 @@ def test_interface_list_sorted_and_complete():
 
 
 def test_lists_large_ragged_domain():
-    """A domain of 8.6 M cells (more than 512 compaction tiles of 64 cells per
-    thread, so the tiles grow to 128 cells per thread; N is not a multiple of
+    """A domain of 8.6 M cells (525 compaction tiles; N is not a multiple of
     the tile or of the 64-cell chunk): after conversion-heavy steps the
     interface list equals the interface cells in ascending order and mass is
     conserved (a chunk missing from the liquid list would leave its cells
@@ -112,6 +111,37 @@ def test_lists_large_ragged_domain():
         assert r["n_interface"] == lst.size
         assert abs(r["total_mass"] - m0) / m0 < 1e-6
     g.close()
+
+
+def test_compaction_tile_sizes_identical():
+    """Compaction tiles of 16, 32, 64 and 128 cells per thread - the packed
+    and the separate scans of the list counts, one and two flag batches per
+    thread, chunks shared by threads or held by one - give bitwise the same
+    run on a ragged domain: types, fill levels, populations, interface list.
+    Sizes below the library's choice or not 16 times a power of two are
+    refused."""
+    from paper_2207_13962_amd.fslbm import FslbmError
+    s = I.rect_dam_break(nx=133, ny=70, nz=37, wx=40, hy=50, g=2e-4, nu=2e-3, storage=I.F32,
+                         variant=I.OM)
+    ref = None
+    for per in (16, 32, 64, 128):
+        g = _sim(s)
+        if per == 16:
+            for bad in (8, 48, 8192):
+                with pytest.raises(FslbmError):
+                    g.set_compaction_tile(bad)
+        else:
+            g.set_compaction_tile(per)
+        g.step(60)
+        f = g.fields(pdf=True)
+        lst = g.interface_list()
+        g.close()
+        assert np.array_equal(lst, np.nonzero(f["type"] == I.INTERFACE)[0]), per
+        if ref is None:
+            ref = f
+            continue
+        for k in ("type", "phi", "mass", "pdf"):
+            assert np.array_equal(f[k], ref[k]), (per, k)
 
 
 def test_flat_rest_all_variants():
