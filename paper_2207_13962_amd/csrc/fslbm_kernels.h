@@ -792,13 +792,6 @@ __device__ __forceinline__ void block_excl_scan4(const uint32_t v[4], uint32_t (
   }
 }
 
-// Counts of the four lists over the cells [b, e) of one thread, vectors of
-// 16 flag bytes (b is a multiple of 64). Chunks are the 64-cell blocks of the
-// range that hold a liquid cell away from walls.
-struct ListCounts {
-  uint32_t n[4];  // interface, converted, chunks, COMPLEX liquid
-};
-
 // Per-byte tests on four flag bytes at once (one 32-bit word): a 4-bit mask
 // of the bytes whose bits under `mask` equal `val` (an exact zero-byte test:
 // no carry crosses a byte), and of the bytes with bit `bit` set.
