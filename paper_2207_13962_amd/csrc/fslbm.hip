@@ -663,11 +663,11 @@ int rebuild_plan(fslbm_server* s) {
       ++bl.n;
     }
     for (int k = 0; k < kLaunches; ++k) {
+      const size_t at = ((size_t)g * kLaunches + k) * s->max_slots;
       bl.blocks[k] = cursor[k];
-      bl.tab[k] = s->d_tab + ((size_t)g * kLaunches + k) * s->max_slots;
-      if (bl.n > 0 &&
-          hipMemcpyAsync(const_cast<BatchEntry*>(bl.tab[k]), s->h_tab + ((size_t)g * kLaunches + k) * s->max_slots,
-                         sizeof(BatchEntry) * bl.n, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+      bl.tab[k] = s->d_tab + at;
+      if (bl.n > 0 && hipMemcpyAsync(const_cast<BatchEntry*>(bl.tab[k]), s->h_tab + at, sizeof(BatchEntry) * bl.n,
+                                     hipMemcpyHostToDevice, s->stream) != hipSuccess)
         return srv_fail(s, hipErrorUnknown);
     }
   }

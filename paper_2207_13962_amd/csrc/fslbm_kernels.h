@@ -641,12 +641,15 @@ __global__ __launch_bounds__(kBlock) void k_stream(Dev d, int gen, int bord) {
 // Turns cell j, if it still has type `from` (gas or liquid), into a new
 // interface cell with the transient bit `bit` (static bits kept) by a
 // compare-and-swap on the 32-bit word holding its flag byte; true for the one
-// caller that made the change. Plain byte stores to the other bytes of the
-// word only make the exchange retry.
-__device__ __forceinline__ bool set_new_type(uint8_t* flags, int64_t j, uint8_t from, uint8_t bit) {
+// caller that made the change. `seen` is the caller's earlier read of that
+// word, the first expected value (a stale one only makes the exchange fail
+// once and retry with the current word); plain byte stores to the other bytes
+// of the word only make the exchange retry.
+__device__ __forceinline__ bool set_new_type(uint8_t* flags, int64_t j, uint8_t from, uint8_t bit,
+                                             uint32_t seen) {
   uint32_t* w = reinterpret_cast<uint32_t*>(flags + (j & ~(int64_t)3));
   const int sh = 8 * (int)(j & 3);
-  uint32_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t old = seen;
   for (;;) {
     const uint8_t f = (uint8_t)(old >> sh);
     if ((f & T_MASK) != from) return false;
@@ -681,19 +684,25 @@ __device__ __forceinline__ void retype_body(const Dev& d, int b, int nb, int reb
       j = nb_index(d.g, x, y, z, cxd(l), cyd(l), czd(l), &w);
     }
     const uint8_t mj = j >= 0 ? d.mark[j] : (uint8_t)MK_NONE;
-    const uint8_t fj = j >= 0 ? d.flags[j] : (uint8_t)0;
+    // the aligned word holding the neighbour's flag byte (the flag array is
+    // padded past its last cell), so that a compare-and-swap below needs no
+    // read of its own
+    const uint32_t wj = j >= 0 ? *reinterpret_cast<const uint32_t*>(d.flags + (j & ~(int64_t)3)) : 0u;
+    const uint8_t fj = (uint8_t)(wj >> (8 * (int)(j & 3)));
     const bool nb_liq_mark = gballot(mj == MK_L) != 0u;
     if (mk == MK_L) {
       if (l == 0) d.flags[c] = (uint8_t)((d.flags[c] & F_STATIC) | T_LIQ | F_CONV);
       if (j >= 0 && (fj & T_MASK) == T_GAS) {
         // the one group whose exchange turns the gas byte into an interface
         // byte lists the cell for its reinitialisation
-        if (set_new_type(d.flags, j, T_GAS, F_NEW_GAS)) d.ng_list[atomicAdd(&d.cnt[CNT_NG], 1)] = (int32_t)j;
+        if (set_new_type(d.flags, j, T_GAS, F_NEW_GAS, wj))
+          d.ng_list[atomicAdd(&d.cnt[CNT_NG], 1)] = (int32_t)j;
       }
     } else if (mk == MK_G && !nb_liq_mark) {
       if (l == 0) d.flags[c] = (uint8_t)((d.flags[c] & F_STATIC) | T_GAS | F_CONV);
       if (j >= 0 && (fj & T_MASK) == T_LIQ) {
-        if (set_new_type(d.flags, j, T_LIQ, F_NEW_LIQ)) d.nl_list[atomicAdd(&d.cnt[CNT_NL], 1)] = (int32_t)j;
+        if (set_new_type(d.flags, j, T_LIQ, F_NEW_LIQ, wj))
+          d.nl_list[atomicAdd(&d.cnt[CNT_NL], 1)] = (int32_t)j;
       }
     }
   }
@@ -1663,7 +1672,8 @@ __global__ __launch_bounds__(kBlock) void k_export(Dev d, double* out, int what)
       for (int k = 0; k < Q; ++k) f[k] = St::ld(A, k * g.stride + c, k);
       R rho, ux, uy, uz;
       post_moments<R, Q, St::kShift>(f, R(d.gx), R(d.gy), R(d.gz), rho, ux, uy, uz);
-      v = what == 0 || what == 4 ? density64<R, Q, St::kShift>(f) : (what == 1 ? (double)ux : (what == 2 ? (double)uy : (double)uz));
+      v = what == 0 || what == 4 ? density64<R, Q, St::kShift>(f)
+                                 : (what == 1 ? (double)ux : (what == 2 ? (double)uy : (double)uz));
     }
   }
   out[c] = v;
