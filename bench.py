@@ -212,6 +212,26 @@ def scale_point(args, variant=3, warm=200, timed=200):
     }
 
 
+def validate_taylor(D=32):
+    """The paper's Taylor-bubble setup at tube diameter D, all four variants:
+    the Reynolds number of the rising bubble beside the paper's values."""
+    from paper_2207_13962_amd import inputs as I
+    from paper_2207_13962_amd.validation import PAPER_TAYLOR_RE, taylor_reynolds
+
+    out = {"setup": "paper Taylor bubble, D = %d (%dx%dx%d, D3Q19 SRT, omega 1.8, Mo 0.015, Bo 100)"
+                    % (D, D, D, 10 * D), "variants": {}}
+    for v in (1, 2, 3, 4):
+        r = taylor_reynolds(D, variant=v)
+        paper = PAPER_TAYLOR_RE.get(D, {}).get(v)
+        r["Re_paper"] = paper
+        r["rel_diff"] = (r["Re"] - paper) / paper if paper else None
+        r["status"] = "ok" if r["status"] == 0 else "unstable (%d)" % r["status"]
+        out["variants"][I.VARIANT_NAMES[v]] = r
+        print("taylor D=%d %s: Re %.2f (paper %s)" % (D, I.VARIANT_NAMES[v], r["Re"], paper), file=sys.stderr,
+              flush=True)
+    return out
+
+
 def copy_calibration():
     """A plain device copy of COPY_BYTES, five times (run under rocprofv3
     counters to calibrate FETCH_SIZE and WRITE_SIZE)."""
@@ -427,6 +447,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-scale-point", action="store_true",
                     help="skip the streaming kernel on the dam break scaled 2x per axis")
+    ap.add_argument("--validate-taylor", type=int, default=0, metavar="D",
+                    help="the paper's Taylor-bubble runs at tube diameter D (32, 64 or 128), four variants")
     ap.add_argument("--scale-only", action="store_true",
                     help="only the streaming kernel on the dam break scaled 2x per axis (kernel by kernel)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
@@ -482,6 +504,9 @@ def main():
         return
     if args.scale_only:
         print(json.dumps(scale_point(args)))
+        return
+    if args.validate_taylor:
+        print(json.dumps(validate_taylor(args.validate_taylor)))
         return
     variants = [int(v) for v in args.variants.split(",")]
     setup_fn = lambda: I.workload(args.workload, **({"smagorinsky": args.les} if args.les else {}))  # noqa: E731

@@ -293,13 +293,13 @@ def cyl_dam_break(nx=256, ny=256, nz=128, radius=32.0, height=96.0, g=2e-5, nu=5
 
 def taylor_bubble(nx=64, ny=64, nz=512, tube_radius=30.0, bubble_radius=24.0, z0=64.0,
                   length=96.0, g=1e-6, nu=1e-3, sigma=1e-4, q=27, collision=TRT, storage=F64,
-                  variant=OM, steps=2000) -> Setup:
+                  variant=OM, steps=2000, cap=True, z_ref=None) -> Setup:
     """Rising Taylor bubble (Sec. 4.4 shape): a tube along z inside no-slip
     walls (cells whose centre lies farther than tube_radius from the axis are
-    obstacles), a gas cylinder of bubble_radius from z0 to z0 + length capped by
-    a hemisphere, liquid elsewhere, gravity -z, surface tension on, one
-    enclosed bubble with volume pressure. Hydrostatic density is referenced to
-    the bubble's centre height."""
+    obstacles), a gas cylinder of bubble_radius from z0 to z0 + length, capped
+    by a hemisphere when `cap`, liquid elsewhere, gravity -z, surface tension
+    on, one enclosed bubble with volume pressure. Hydrostatic density is
+    referenced to z_ref (default: the bubble's centre height)."""
     b = (WALL_NOSLIP,) * 6
     p = Params(nx, ny, nz, q=q, collision=collision, storage=storage, boundary=b, variant=variant,
                tau=tau_from_nu(nu), gravity=(0.0, 0.0, -g), sigma=sigma, bubble_model=1)
@@ -309,16 +309,34 @@ def taylor_bubble(nx=64, ny=64, nz=512, tube_radius=30.0, bubble_radius=24.0, z0
     def in_bubble(x, y, z):
         r2 = (x - cx) ** 2 + (y - cy) ** 2
         cyl = (r2 < bubble_radius ** 2) & (z >= z0) & (z < ztop)
-        cap = (r2 + (z - ztop) ** 2 < bubble_radius ** 2) & (z >= ztop)
-        return cyl | cap
+        if not cap:
+            return cyl
+        top = (r2 + (z - ztop) ** 2 < bubble_radius ** 2) & (z >= ztop)
+        return cyl | top
 
     phi = 1.0 - supersampled_fill(nx, ny, nz, in_bubble)
     i, j, k = _grid(nx, ny, nz)
     obstacle = (i + 0.5 - cx) ** 2 + (j + 0.5 - cy) ** 2 > tube_radius ** 2
-    zc = z0 + 0.5 * (length + bubble_radius)
+    zc = z_ref if z_ref is not None else z0 + 0.5 * (length + bubble_radius)
     rho = hydrostatic_rho(p, zc, 2, g)
     return _finish(p, phi, rho, "taylor_bubble", steps, obstacle=obstacle,
                    meta=dict(g=g, z0=z0, length=length, bubble_radius=bubble_radius))
+
+
+def taylor_bubble_paper(D=32, variant=OM, storage=F64) -> Setup:
+    """The paper's Taylor-bubble setup (Sec. 4.4): tube of diameter D in a
+    D x D x 10D domain, no-slip walls, gas cylinder of diameter 0.75 D and
+    length 3 D starting D above the bottom, hydrostatic pressure equal to the
+    volume pressure at height 5 D; D3Q19 SRT with relaxation rate 1.8;
+    Mo = g mu^4 / (rho sigma^3) = 0.015 and Bo = g D^2 / sigma = 100 (liquid
+    density 1) fix g and sigma."""
+    tau = 1.0 / 1.8
+    nu = (tau - 0.5) / 3.0
+    g = nu * nu * 1000.0 / (math.sqrt(0.015) * D ** 3)
+    sigma = g * D * D / 100.0
+    return taylor_bubble(nx=D, ny=D, nz=10 * D, tube_radius=D / 2.0, bubble_radius=0.375 * D, z0=float(D),
+                         length=3.0 * D, g=g, nu=nu, sigma=sigma, q=19, collision=SRT, storage=storage,
+                         variant=variant, cap=False, z_ref=5.0 * D)
 
 
 def droplet_impact(L=48, diameter=None, pool=None, velocity=0.03, g=1e-5, tau=None, q=19,
