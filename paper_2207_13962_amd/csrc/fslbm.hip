@@ -603,6 +603,12 @@ struct fslbm_server {
   std::map<uint64_t, DoneRun> done;
   std::vector<std::pair<uint64_t, int>> unpolled;
   BatchLaunch launch[kGroups];
+  // groups touch disjoint runs: each runs its ticks on a stream of its own
+  // (default priority), forked from and joined back to `stream` per chunk
+  static constexpr int kGroupStreams = 4;
+  hipStream_t gstream[kGroupStreams] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kGroupStreams] = {nullptr, nullptr, nullptr, nullptr};
   bool dirty = true;
   uint64_t next_id = 1;
   int64_t tick = 0, completed = 0;
@@ -759,6 +765,12 @@ int admit_queued(fslbm_server* s) {
 
 void free_server(fslbm_server* s) {
   for (ResidentRun& r : s->resident) fslbm_destroy(r.ctx);
+  for (int k = 0; k < fslbm_server::kGroupStreams; ++k) {
+    if (s->gstream[k]) (void)hipStreamSynchronize(s->gstream[k]);
+    if (s->gstream[k]) (void)hipStreamDestroy(s->gstream[k]);
+    if (s->join_ev[k]) (void)hipEventDestroy(s->join_ev[k]);
+  }
+  if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
   if (s->d_devs) (void)hipFree(s->d_devs);
   if (s->d_tab) (void)hipFree(s->d_tab);
   if (s->h_tab) (void)hipHostFree(s->h_tab);
@@ -793,6 +805,15 @@ int fslbm_server_create(size_t hbm_budget_bytes, int max_slots, void* hip_stream
   if (!s->pool) {
     free_server(s);
     return FSLBM_ENOMEM;
+  }
+  bool ok = hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; ok && k < fslbm_server::kGroupStreams; ++k)
+    ok = hipStreamCreateWithFlags(&s->gstream[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&s->join_ev[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_server(s);
+    return FSLBM_EDEVICE;
   }
   for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
   *out = s;
@@ -842,20 +863,42 @@ int fslbm_server_advance(fslbm_server* s, int64_t ticks) {
     // ticks until the next run finishes
     int64_t chunk = left;
     for (const ResidentRun& r : s->resident) chunk = std::min(chunk, r.tick0 + r.nsteps - s->tick);
-    for (int64_t i = 0; i < chunk; ++i) {
-      for (int g = 0; g < kGroups; ++g) {
-        const BatchLaunch& bl = s->launch[g];
-        if (bl.n == 0) continue;
-        const fslbm_params* p = nullptr;
-        for (const ResidentRun& r : s->resident)
-          if (r.group == g) {
-            p = &r.ctx->p;
-            break;
-          }
-        pick(*p).batch_step(bl, s->stream, s->tick);
-      }
-      ++s->tick;
+    // the active groups and their kernel tables
+    Ops ops[kGroups];
+    int active[kGroups], na = 0;
+    for (int g = 0; g < kGroups; ++g) {
+      if (s->launch[g].n == 0) continue;
+      for (const ResidentRun& r : s->resident)
+        if (r.group == g) {
+          ops[na] = pick(r.ctx->p);
+          break;
+        }
+      active[na++] = g;
     }
+    // one group runs on the server stream; several run side by side on
+    // streams of their own (disjoint runs), forked here and joined below
+    const bool fork = na > 1;
+    int used = 0;
+    if (fork) {
+      if (hipEventRecord(s->fork_ev, s->stream) != hipSuccess) return srv_fail(s, hipErrorUnknown);
+      for (int a = 0; a < na; ++a) used |= 1 << (active[a] % fslbm_server::kGroupStreams);
+      for (int k = 0; k < fslbm_server::kGroupStreams; ++k)
+        if ((used >> k) & 1)
+          if (hipStreamWaitEvent(s->gstream[k], s->fork_ev, 0) != hipSuccess) return srv_fail(s, hipErrorUnknown);
+    }
+    for (int64_t i = 0; i < chunk; ++i)
+      for (int a = 0; a < na; ++a) {
+        hipStream_t st = fork ? s->gstream[active[a] % fslbm_server::kGroupStreams] : s->stream;
+        ops[a].batch_step(s->launch[active[a]], st, s->tick + i);
+      }
+    if (fork) {
+      for (int k = 0; k < fslbm_server::kGroupStreams; ++k)
+        if ((used >> k) & 1)
+          if (hipEventRecord(s->join_ev[k], s->gstream[k]) != hipSuccess ||
+              hipStreamWaitEvent(s->stream, s->join_ev[k], 0) != hipSuccess)
+            return srv_fail(s, hipErrorUnknown);
+    }
+    s->tick += chunk;
     if (hipGetLastError() != hipSuccess) return srv_fail(s, hipErrorUnknown);
     left -= chunk;
   }
