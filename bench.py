@@ -232,6 +232,33 @@ def validate_taylor(D=32):
     return out
 
 
+def validate_wave(L=200, variants=(1, 2, 3, 4)):
+    """The paper's gravity wave at wavelength L, all four variants: the
+    surface elevation at x = 0 against the analytic model (errors over the
+    first t* = 6, 12 and 24), sampled every t* = 0.05 up to t* = 40."""
+    from paper_2207_13962_amd import inputs as I
+    from paper_2207_13962_amd.validation import gravity_wave_elevation, wave_errors
+
+    out = {"setup": "paper gravity wave, L = %d (%dx%dx1, D3Q19 SRT, omega 1.8, Re 10, a0 0.01 L, d L/2)"
+                    % (L, L, L), "variants": {}}
+    for v in variants:
+        name = I.VARIANT_NAMES[v]
+        t0 = time.perf_counter()
+        r = gravity_wave_elevation(L, variant=v, progress=lambda ts: print(
+            "wave L=%d %s: t* = %.1f" % (L, name, ts), file=sys.stderr, flush=True))
+        e = wave_errors(r)
+        e["steps"] = r["steps"]
+        e["seconds"] = round(time.perf_counter() - t0, 1)
+        e["status"] = "ok" if r["status"] == 0 else "unstable (%d)" % r["status"]
+        # the elevation at every t* = 1 for plotting against the model
+        e["a_sim_every_t1"] = [round(float(x), 4) for x in r["a_sim"][::20]]
+        out["variants"][name] = e
+        print("wave L=%d %s: max err to t*=12 %.3f, to t*=24 %.3f" % (
+            L, name, e["max_abs_err_t12"], e["max_abs_err_t24"]), file=sys.stderr, flush=True)
+    out["a_model_every_t1"] = [round(float(x), 4) for x in r["a_model"][::20]]
+    return out
+
+
 def copy_calibration():
     """A plain device copy of COPY_BYTES, five times (run under rocprofv3
     counters to calibrate FETCH_SIZE and WRITE_SIZE)."""
@@ -449,6 +476,8 @@ def main():
                     help="skip the streaming kernel on the dam break scaled 2x per axis")
     ap.add_argument("--validate-taylor", type=int, default=0, metavar="D",
                     help="the paper's Taylor-bubble runs at tube diameter D (32, 64 or 128), four variants")
+    ap.add_argument("--validate-wave", type=int, default=0, metavar="L",
+                    help="the paper's gravity wave at wavelength L (200, 400 or 800), four variants")
     ap.add_argument("--scale-only", action="store_true",
                     help="only the streaming kernel on the dam break scaled 2x per axis (kernel by kernel)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
@@ -507,6 +536,9 @@ def main():
         return
     if args.validate_taylor:
         print(json.dumps(validate_taylor(args.validate_taylor)))
+        return
+    if args.validate_wave:
+        print(json.dumps(validate_wave(args.validate_wave, [int(v) for v in args.variants.split(",")])))
         return
     variants = [int(v) for v in args.variants.split(",")]
     setup_fn = lambda: I.workload(args.workload, **({"smagorinsky": args.les} if args.les else {}))  # noqa: E731

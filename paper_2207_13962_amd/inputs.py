@@ -261,6 +261,24 @@ def gravity_wave(nx=64, ny=64, nz=1, depth=32.0, amp=0.64, g=1e-5, tau=0.55, q=1
                    meta=dict(depth=depth, amp=amp, g=g, wavelength=wavelength or nx))
 
 
+def gravity_wave_paper(L=200, variant=OM, storage=F64, steps=0) -> Setup:
+    """The paper's gravity wave (Sec. 4.1): L x L x 1, liquid depth L/2,
+    amplitude 0.01 L, one wavelength across x, D3Q19 SRT with relaxation rate
+    1.8; Re = a0 omega0 L / nu = 10 fixes the wave's angular frequency
+    omega0 = 1000 nu / L^2, and the dispersion relation omega0^2 =
+    g k tanh(k d) with k = 2 pi / L fixes g."""
+    tau = 1.0 / 1.8
+    nu = (tau - 0.5) / 3.0
+    k = 2.0 * math.pi / L
+    d = 0.5 * L
+    omega0 = 10.0 * nu / (0.01 * L * L)
+    g = omega0 * omega0 / (k * math.tanh(k * d))
+    s = gravity_wave(nx=L, ny=L, nz=1, depth=d, amp=0.01 * L, g=g, tau=tau, q=19, collision=SRT,
+                     storage=storage, variant=variant, steps=steps, wavelength=L)
+    s.meta.update(omega0=omega0, nu=nu, k=k)
+    return s
+
+
 def rect_dam_break(nx=256, ny=128, nz=64, wx=64, hy=96, g=2e-5, nu=1e-3, q=19, collision=TRT,
                    storage=F32, variant=OM, steps=5000, boundary=None) -> Setup:
     """Rectangular dam break (Sec. 4.2 shape): a liquid column wx x hy x nz in

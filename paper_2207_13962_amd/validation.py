@@ -1,8 +1,9 @@
 """Validation against the paper's own results: the Taylor-bubble runs of
 Sec. 4.4 (tube diameter D, all four boundary-condition variants), whose
-Reynolds numbers the paper tabulates. Every step runs in libfslbm; this module
-builds the setup, samples the fill levels and reduces them to the rise
-velocity."""
+Reynolds numbers the paper tabulates, and the gravity wave of Sec. 4.1 at the
+paper's resolutions against the analytic model the paper compares with. Every
+step runs in libfslbm; this module builds the setups, samples the fill levels
+and reduces them to the rise velocity or the surface elevation."""
 from __future__ import annotations
 
 import math
@@ -52,3 +53,71 @@ def taylor_reynolds(D=32, variant=I.OM, storage=I.F64, device="cuda:0"):
             sim.close()
     u = (z15 - z10) / (t15 - t10)
     return dict(Re=D * u / nu, z_centroid_t10=z10, z_centroid_t15=z15, steps=t15, status=status)
+
+
+def wave_model(t_star, nu, k, omega0):
+    """The paper's analytic surface elevation at x = 0 (Sec. 4.1): a*(0, t*) =
+    exp(-2 nu k^2 t) cos(t*), t = t* / omega0."""
+    t = np.asarray(t_star, dtype=np.float64) / omega0
+    return np.exp(-2.0 * nu * k * k * t) * np.cos(np.asarray(t_star, dtype=np.float64))
+
+
+def gravity_wave_elevation(L=200, variant=I.OM, storage=I.F64, t_end=40.0, dt_star=0.05,
+                           device="cuda:0", progress=None):
+    """The paper's gravity wave of wavelength L (Sec. 4.1) run to t* = t_end
+    (t* = t omega0); every dt_star the surface elevation at the left border
+    x = 0: the liquid height of a column (sum of fill levels over y) averaged
+    over the two columns next to x = 0 (cells 0 and L - 1 of the periodic
+    domain), minus the depth, over a0. Returns t*, the simulated and the
+    model's a*, and the run's status."""
+    import torch
+
+    from .fslbm import Simulation
+
+    s = I.gravity_wave_paper(L, variant=variant, storage=storage)
+    p, m = s.params, s.meta
+    omega0, nu, k = m["omega0"], m["nu"], m["k"]
+    d, a0 = m["depth"], m["amp"]
+    n_samples = int(round(t_end / dt_star))
+    steps = [int(round(i * dt_star / omega0)) for i in range(n_samples + 1)]
+    stream = torch.cuda.Stream(device=device)
+    a_sim = np.zeros(n_samples + 1)
+    status = 0
+    with torch.cuda.stream(stream):
+        sim = Simulation(s, device=device, stream=stream)
+
+        def elevation():
+            f = sim.fields(pdf=False, check=False)
+            phi = np.where(f["type"] == I.LIQUID, 1.0,
+                           np.where(f["type"] == I.INTERFACE, f["phi"], 0.0)).reshape(p.ny, p.nx)
+            h = 0.5 * (phi[:, 0].sum() + phi[:, p.nx - 1].sum())
+            return (h - d) / a0, int(f["status"])
+
+        try:
+            done = 0
+            for i, st in enumerate(steps):
+                if st > done:
+                    sim.step(st - done)
+                    done = st
+                a_sim[i], status = elevation()
+                if status:
+                    a_sim[i + 1:] = np.nan
+                    break
+                if progress and i % max(1, n_samples // 8) == 0:
+                    progress(i * dt_star)
+        finally:
+            sim.close()
+    t_star = np.arange(n_samples + 1) * dt_star
+    return dict(t_star=t_star, a_sim=a_sim, a_model=wave_model(t_star, nu, k, omega0),
+                steps=steps[-1], status=status)
+
+
+def wave_errors(r, windows=(6.0, 12.0, 24.0)):
+    """Max and RMS of a*_sim - a*_model over t* in [0, w] for each window w."""
+    out = {}
+    for w in windows:
+        sel = r["t_star"] <= w + 1e-9
+        e = r["a_sim"][sel] - r["a_model"][sel]
+        out["max_abs_err_t%g" % w] = float(np.max(np.abs(e)))
+        out["rms_err_t%g" % w] = float(np.sqrt(np.mean(e * e)))
+    return out

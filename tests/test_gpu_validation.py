@@ -1,6 +1,9 @@
 """The paper's Taylor-bubble runs (Sec. 4.4) at tube diameter 32, all four
 variants: the Reynolds number of the rising bubble against the paper's table,
-and the variants in the paper's order (OM > OM3 > NBRC > NBKC)."""
+and the variants in the paper's order (OM > OM3 > NBRC > NBKC). The paper's
+gravity wave (Sec. 4.1) at wavelength 200: the surface elevation at x = 0
+against the analytic model the paper compares with."""
+import numpy as np
 import pytest
 
 from paper_2207_13962_amd import inputs as I
@@ -20,3 +23,20 @@ def test_taylor_bubble_reynolds_as_in_the_paper():
         # variants; the same setup here lands within 5 % of each
         assert abs(re[v] - paper) <= 0.05 * paper, (I.VARIANT_NAMES[v], re[v], paper)
     assert re[I.OM] > re[I.OM3] > re[I.NBRC] > re[I.NBKC]
+
+
+def test_gravity_wave_follows_the_analytic_model():
+    from paper_2207_13962_amd.validation import gravity_wave_elevation, wave_errors
+    for v in (I.NBRC, I.NBKC, I.OM, I.OM3):
+        r = gravity_wave_elevation(200, variant=v, t_end=12.0)
+        assert r["status"] == 0
+        assert abs(r["a_sim"][0] - 1.0) < 1e-3
+        e = wave_errors(r, windows=(12.0,))
+        # at L = 200 the four variants stay within 0.16-0.30 of the model up
+        # to t* = 12 (RMS 0.08-0.12); the error shrinks with L (0.10-0.15 at
+        # L = 400, 0.08-0.13 at L = 800)
+        assert e["max_abs_err_t12"] < 0.35 and e["rms_err_t12"] < 0.15, (I.VARIANT_NAMES[v], e)
+        # the wave reverses: its first trough lies near t* = pi
+        t, a = r["t_star"], r["a_sim"]
+        trough = t[np.argmin(np.where(t < 2 * np.pi, a, np.inf))]
+        assert abs(trough - np.pi) < 0.5, (I.VARIANT_NAMES[v], trough)
