@@ -212,7 +212,7 @@ def scale_point(args, variant=3, warm=200, timed=200):
     }
 
 
-def validate_taylor(D=32):
+def validate_taylor(D=32, variants=(1, 2, 3, 4)):
     """The paper's Taylor-bubble setup at tube diameter D, all four variants:
     the Reynolds number of the rising bubble beside the paper's values."""
     from paper_2207_13962_amd import inputs as I
@@ -220,8 +220,9 @@ def validate_taylor(D=32):
 
     out = {"setup": "paper Taylor bubble, D = %d (%dx%dx%d, D3Q19 SRT, omega 1.8, Mo 0.015, Bo 100)"
                     % (D, D, D, 10 * D), "variants": {}}
-    for v in (1, 2, 3, 4):
-        r = taylor_reynolds(D, variant=v)
+    for v in variants:
+        r = taylor_reynolds(D, variant=v, progress=lambda k: print(
+            "taylor D=%d %s: step %d" % (D, I.VARIANT_NAMES[v], k), file=sys.stderr, flush=True))
         paper = PAPER_TAYLOR_RE.get(D, {}).get(v)
         r["Re_paper"] = paper
         r["rel_diff"] = (r["Re"] - paper) / paper if paper else None
@@ -535,7 +536,7 @@ def main():
         print(json.dumps(scale_point(args)))
         return
     if args.validate_taylor:
-        print(json.dumps(validate_taylor(args.validate_taylor)))
+        print(json.dumps(validate_taylor(args.validate_taylor, [int(v) for v in args.variants.split(",")])))
         return
     if args.validate_wave:
         print(json.dumps(validate_wave(args.validate_wave, [int(v) for v in args.variants.split(",")])))

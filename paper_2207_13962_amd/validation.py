@@ -19,7 +19,7 @@ PAPER_TAYLOR_RE = {32: {1: 21.92, 2: 20.98, 3: 24.12, 4: 22.68},
                    128: {1: 25.12, 2: 24.27, 3: 25.89, 4: 24.74}}
 
 
-def taylor_reynolds(D=32, variant=I.OM, storage=I.F64, device="cuda:0"):
+def taylor_reynolds(D=32, variant=I.OM, storage=I.F64, device="cuda:0", progress=None):
     """Re = D u / nu of the paper's Taylor bubble, u the rise velocity of the
     bubble's centre of mass (gas weight 1 - phi over gas and interface cells)
     between t* = 10 and t* = 15 (t* = t sqrt(g / D)). Returns a dict with Re,
@@ -44,10 +44,21 @@ def taylor_reynolds(D=32, variant=I.OM, storage=I.F64, device="cuda:0"):
             w = np.where(gas, 1.0 - f["phi"], 0.0)
             return float((w * z).sum() / w.sum()), int(f["status"])
 
+        def advance(n, done):
+            chunk = 10000
+            while n > 0:
+                k = min(chunk, n)
+                sim.step(k)
+                n -= k
+                done += k
+                if progress:
+                    progress(done)
+            return done
+
         try:
-            sim.step(t10)
+            done = advance(t10, 0)
             z10, _ = centroid()
-            sim.step(t15 - t10)
+            advance(t15 - t10, done)
             z15, status = centroid()
         finally:
             sim.close()
