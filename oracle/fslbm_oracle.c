@@ -90,6 +90,13 @@ struct orc_sim {
   uint8_t* ntype; /* type after conversion */
   double m_lost;
   double pV, pV0, V0;
+  /* tracked bubbles (bubble_model 2): label per cell (-1: no bubble), and at
+   * each bubble's label index its gas amount and pressure; per cell the
+   * volume pressure of its bubble; work arrays of the update */
+  int32_t *blab, *bnew;
+  double *bamt, *bpr, *bpc, *bV, *bW, *bnn;
+  uint8_t* bhas;
+  long* bqueue;
   int64_t step;
   int status;
 };
@@ -451,7 +458,117 @@ void orc_destroy(orc_sim* s) {
   free(s->conv);
   free(s->cls);
   free(s->ntype);
+  free(s->blab);
+  free(s->bnew);
+  free(s->bamt);
+  free(s->bpr);
+  free(s->bpc);
+  free(s->bV);
+  free(s->bW);
+  free(s->bnn);
+  free(s->bhas);
+  free(s->bqueue);
   free(s);
+}
+
+/* ---------------------------------------------------------------------------
+ * Tracked bubbles (bubble_model 2). The paper follows the volume pressure of
+ * each enclosed gas volume through coalescence and segmentation (Sec. 2.2,
+ * volume-pressure equation and the bubble model it cites) without stating
+ * the rules. Reading used here: a bubble is a connected set of gas and
+ * interface cells, neighbours being the lattice directions (across periodic
+ * faces; walls and obstacles separate); its volume V is the sum of 1 - phi
+ * over its cells; its gas amount n = p^V V is what the volume-pressure
+ * equation keeps constant (Boyle's law). After each step the bubbles are
+ * found again; every old bubble hands its amount to the new bubbles holding
+ * its former cells, in proportion to the gas volume of those cells
+ * (coalescence adds amounts; a bubble that splits leaves each part at its
+ * pressure), cells that were in no bubble add volume only, and a new bubble
+ * holding none of an old bubble's volume starts at p^V(0). p^V = n / V
+ * (p^V(0) where V <= 0). A bubble is labelled by its smallest cell index.
+ * ------------------------------------------------------------------------- */
+static int is_bubble_cell(int t) { return t == ORC_GAS || t == ORC_INTERFACE; }
+
+/* Connected components of gas and interface cells, breadth first from the
+ * lowest unlabelled cell (which is then the component's smallest index). */
+static void label_bubbles(const orc_sim* s, int32_t* lab, long* queue) {
+  long N = s->N;
+  for (long c = 0; c < N; ++c) lab[c] = -1;
+  for (long c = 0; c < N; ++c) {
+    if (!is_bubble_cell(s->type[c]) || lab[c] >= 0) continue;
+    long head = 0, tail = 0;
+    lab[c] = (int32_t)c;
+    queue[tail++] = c;
+    while (head < tail) {
+      long a = queue[head++];
+      int x, y, z;
+      coords(s, a, &x, &y, &z);
+      for (int i = 1; i < s->q; ++i) {
+        long j;
+        int t = lookup(s, x, y, z, CV[i][0], CV[i][1], CV[i][2], &j);
+        if (j < 0 || !is_bubble_cell(t) || lab[j] >= 0) continue;
+        lab[j] = (int32_t)c;
+        queue[tail++] = j;
+      }
+    }
+  }
+}
+
+/* Gas volume a bubble cell contributes (gas cells hold phi = 0). */
+static double gas_volume(const orc_sim* s, long c) { return 1.0 - s->phi[c]; }
+
+/* New bubbles, their amounts and pressures from the types and fill levels
+ * of the end of a step; `first`: no old bubbles (creation). */
+static void update_bubbles(orc_sim* s, int first) {
+  long N = s->N;
+  int32_t* nl = s->bnew;
+  label_bubbles(s, nl, s->bqueue);
+  for (long c = 0; c < N; ++c) {
+    s->bV[c] = 0.0;
+    s->bW[c] = 0.0;
+    s->bnn[c] = 0.0;
+    s->bhas[c] = 0;
+  }
+  /* V of each new bubble; W of each old bubble: the gas volume of its
+   * former cells that are still bubble cells */
+  for (long c = 0; c < N; ++c) {
+    if (nl[c] < 0) continue;
+    s->bV[nl[c]] += gas_volume(s, c);
+    if (!first && s->blab[c] >= 0) s->bW[s->blab[c]] += gas_volume(s, c);
+  }
+  /* amounts: old bubble b gives n_b w / W_b through each former cell */
+  for (long c = 0; c < N; ++c) {
+    if (nl[c] < 0 || first || s->blab[c] < 0) continue;
+    long b = s->blab[c];
+    if (!(s->bW[b] > 0.0)) continue;
+    s->bnn[nl[c]] += s->bamt[b] * (gas_volume(s, c) / s->bW[b]);
+    s->bhas[nl[c]] = 1;
+  }
+  for (long c = 0; c < N; ++c) {
+    if (nl[c] != c) continue;
+    double n = s->bhas[c] ? s->bnn[c] : s->pV0 * s->bV[c];
+    s->bamt[c] = n;
+    s->bpr[c] = s->bV[c] > 0.0 ? n / s->bV[c] : s->pV0;
+  }
+  for (long c = 0; c < N; ++c) {
+    s->blab[c] = nl[c];
+    s->bpc[c] = nl[c] >= 0 ? s->bpr[nl[c]] : s->pV0;
+  }
+}
+
+int64_t orc_bubbles(const orc_sim* s, int64_t* label, double* volume, double* pressure, int64_t cap) {
+  if (s->p.bubble_model != 2) return 0;
+  int64_t n = 0;
+  for (long c = 0; c < s->N; ++c) {
+    if (s->blab[c] != c) continue;
+    if (n < cap) {
+      label[n] = c;
+      volume[n] = s->bV[c];
+      pressure[n] = s->bpr[c];
+    }
+    n += 1;
+  }
+  return n;
 }
 
 static double bubble_volume(const orc_sim* s) {
@@ -472,6 +589,7 @@ int orc_create(const orc_params* p, const uint8_t* type, const double* phi, cons
   if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1 || (p->q != 19 && p->q != 27)) return ORC_EINVAL;
   if (!(p->tau > 0.5) || (p->collision != ORC_SRT && p->collision != ORC_TRT)) return ORC_EINVAL;
   if (p->variant < ORC_NBRC || p->variant > ORC_OM3) return ORC_EINVAL;
+  if (p->bubble_model < 0 || p->bubble_model > 2) return ORC_EINVAL;
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   if (!s) return ORC_ENOMEM;
   s->p = *p;
@@ -531,6 +649,24 @@ int orc_create(const orc_params* p, const uint8_t* type, const double* phi, cons
   }
   s->pV0 = s->pV = p->rho_gas / 3.0;
   s->V0 = bubble_volume(s);
+  if (p->bubble_model == 2) {
+    s->blab = (int32_t*)xcalloc(N, 4);
+    s->bnew = (int32_t*)xcalloc(N, 4);
+    s->bamt = (double*)xcalloc(N, 8);
+    s->bpr = (double*)xcalloc(N, 8);
+    s->bpc = (double*)xcalloc(N, 8);
+    s->bV = (double*)xcalloc(N, 8);
+    s->bW = (double*)xcalloc(N, 8);
+    s->bnn = (double*)xcalloc(N, 8);
+    s->bhas = (uint8_t*)xcalloc(N, 1);
+    s->bqueue = (long*)xcalloc(N, sizeof(long));
+    if (!s->blab || !s->bnew || !s->bamt || !s->bpr || !s->bpc || !s->bV || !s->bW || !s->bnn ||
+        !s->bhas || !s->bqueue) {
+      orc_destroy(s);
+      return ORC_ENOMEM;
+    }
+    update_bubbles(s, 1);
+  }
   *out = s;
   return ORC_OK;
 }
@@ -558,7 +694,7 @@ int orc_set_variant(orc_sim* s, int variant) {
  *  S11 excess mass of converted cells, spread evenly over the interface
  *      neighbours after conversion (lost-mass counter if there are none);
  *  S12 fill levels of interface cells;
- *  S13 bubble volume and volume pressure (one enclosed bubble);
+ *  S13 bubble volume and volume pressure (one enclosed bubble, or tracked bubbles);
  *  S14 stability checks.
  * ------------------------------------------------------------------------- */
 static void collide_all(orc_sim* s, const double* f, double* fs, double* ut) {
@@ -651,7 +787,8 @@ static int step_once(orc_sim* s) {
     int x, y, z;
     coords(s, c, &x, &y, &z);
     double kappa = s->p.sigma != 0.0 ? curvature_at(s, x, y, z) : 0.0;
-    s->rhoG[c] = 3.0 * (s->pV + s->p.sigma * kappa);
+    const double pv = s->p.bubble_model == 2 ? s->bpc[c] : s->pV;
+    s->rhoG[c] = 3.0 * (pv + s->p.sigma * kappa);
     s->cls[c] = (uint8_t)flux_class(s, x, y, z);
   }
 
@@ -878,8 +1015,10 @@ static int step_once(orc_sim* s) {
     }
   }
 
-  /* S13: one enclosed bubble, Sec. 2.2 volume pressure p^V = p^V(0) V(0)/V(t) */
-  if (s->p.bubble_model) s->pV = s->pV0 * s->V0 / bubble_volume(s);
+  /* S13: Sec. 2.2 volume pressure p^V = p^V(0) V(0)/V(t): one enclosed
+   * bubble, or every bubble tracked through coalescence and segmentation */
+  if (s->p.bubble_model == 1) s->pV = s->pV0 * s->V0 / bubble_volume(s);
+  if (s->p.bubble_model == 2) update_bubbles(s, 0);
 
   /* S14: instability (the paper observed blow-ups once the flow exceeded the
    * lattice speed of sound) */

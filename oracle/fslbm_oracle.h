@@ -43,7 +43,8 @@ typedef struct {
   int32_t boundary[6];   /* faces -x,+x,-y,+y,-z,+z */
   int32_t variant;       /* ORC_NBRC..ORC_OM3 */
   int32_t thurey_flux;   /* 1: forced fill/empty flux modification */
-  int32_t bubble_model;  /* 0: constant volume pressure, 1: one enclosed bubble */
+  int32_t bubble_model;  /* 0: constant volume pressure, 1: one enclosed bubble,
+                            2: every bubble tracked (coalescence, segmentation) */
   double tau, trt_lambda;
   double gravity[3];
   double rho_gas;        /* gas density at zero surface tension (= 3 p^V) */
@@ -80,6 +81,10 @@ typedef struct {
   int64_t n_liquid, n_interface, n_gas, step;
 } orc_report;
 void orc_mass(const orc_sim* s, orc_report* r);
+/* Tracked bubbles (bubble_model 2), ascending by label (the smallest cell
+ * index of the bubble): label, gas volume and volume pressure of the first
+ * `cap` of them. Returns the number of bubbles (0 for other models). */
+int64_t orc_bubbles(const orc_sim* s, int64_t* label, double* volume, double* pressure, int64_t cap);
 
 /* Isolated routines exposed for the pins. */
 /* Equilibrium of the given lattice (q = 19/27); feq has q entries. */

@@ -74,6 +74,8 @@ def _L():
         lib.orc_fields.argtypes = [C.c_void_p, u8, dp, dp, dp, dp, dp, dp, dp]
         lib.orc_post_collision.argtypes = [C.c_void_p, dp]
         lib.orc_mass.argtypes = [C.c_void_p, C.POINTER(_Report)]
+        lib.orc_bubbles.argtypes = [C.c_void_p, C.POINTER(C.c_int64), dp, dp, C.c_int64]
+        lib.orc_bubbles.restype = C.c_int64
         lib.orc_equilibrium.argtypes = [C.c_int, C.c_double, dp, dp]
         lib.orc_lattice.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), dp]
         lib.orc_opposite.argtypes = [C.c_int, C.c_int]
@@ -208,6 +210,15 @@ class Oracle:
         r = _Report()
         _L().orc_mass(self._h, C.byref(r))
         return OracleReport(**{k: getattr(r, k) for k, _ in _Report._fields_})
+
+    def bubbles(self):
+        """Tracked bubbles (bubble model 2): labels (smallest cell index),
+        gas volumes and volume pressures, ascending by label."""
+        cnt = _L().orc_bubbles(self._h, None, None, None, 0)
+        lab = np.zeros(max(cnt, 1), dtype=np.int64)
+        vol, pr = np.zeros(max(cnt, 1)), np.zeros(max(cnt, 1))
+        _L().orc_bubbles(self._h, lab.ctypes.data_as(C.POINTER(C.c_int64)), _dp(vol), _dp(pr), cnt)
+        return lab[:cnt], vol[:cnt], pr[:cnt]
 
     def normal(self, x, y, z):
         n = np.zeros(3)

@@ -279,6 +279,52 @@ def gravity_wave_paper(L=200, variant=OM, storage=F64, steps=0) -> Setup:
     return s
 
 
+def bubble_pair(kind="apart", q=19, storage=F64, variant=OM, periodic_x=False, g=0.0, steps=0) -> Setup:
+    """Gas bubbles (5 x 4 x 4 gas cells, each inside a one-cell interface shell
+    with phi = 0.5) in liquid at rest, 28 x 10 x 10 cells, no-slip walls (x
+    periodic if periodic_x), tracked-bubble model. kind "apart": two bubbles,
+    shells five liquid cells apart; "merge": one liquid cell between the
+    shells, and the first bubble's shell face next to it holds phi = -0.05, so
+    it empties in the first step and the film cell turns interface, joining
+    the bubbles; "split": the shells five cells apart, joined by a one-cell
+    line of interface cells with phi = 1.05, which fill in the first step and
+    separate the bubbles; "straddle": one bubble across the x faces (two
+    halves when x has walls)."""
+    nx, ny, nz = 28, 10, 10
+    wall = WALL_NOSLIP
+    b = ((PERIODIC, PERIODIC) if periodic_x else (wall, wall)) + (wall, wall, wall, wall)
+    p = Params(nx, ny, nz, q=q, collision=SRT, storage=storage, boundary=b, variant=variant, tau=0.6,
+               bubble_model=2, gravity=(0.0, 0.0, -g))
+    t = np.full((nz, ny, nx), LIQUID, dtype=np.uint8)
+    phi = np.ones((nz, ny, nx))
+
+    def bubble(xs):
+        for x in xs:
+            t[2:8, 2:8, x] = INTERFACE
+            phi[2:8, 2:8, x] = 0.5
+        for x in xs[1:-1]:
+            t[3:7, 3:7, x] = GAS
+            phi[3:7, 3:7, x] = 0.0
+
+    if kind == "straddle":
+        bubble([(nx - 3 + i) % nx for i in range(7)])
+    else:
+        bubble(list(range(2, 9)))
+        x0 = 10 if kind == "merge" else 14
+        bubble(list(range(x0, x0 + 7)))
+    if kind == "merge":
+        face = t[2:8, 2:8, 8] == INTERFACE
+        phi[2:8, 2:8, 8] = np.where(face, -0.05, phi[2:8, 2:8, 8])
+    elif kind == "split":
+        t[5, 5, 9:14] = INTERFACE
+        phi[5, 5, 9:14] = 1.05
+    rho = np.ones(p.n)
+    z = np.zeros(p.n)
+    tt = t.ravel().copy()
+    ph = np.where(tt == LIQUID, 1.0, np.where(tt == GAS, 0.0, phi.ravel()))
+    return Setup(p, tt, ph, rho, z.copy(), z.copy(), z.copy(), "bubble_pair_" + kind, steps)
+
+
 def rect_dam_break(nx=256, ny=128, nz=64, wx=64, hy=96, g=2e-5, nu=1e-3, q=19, collision=TRT,
                    storage=F32, variant=OM, steps=5000, boundary=None) -> Setup:
     """Rectangular dam break (Sec. 4.2 shape): a liquid column wx x hy x nz in

@@ -1,0 +1,123 @@
+"""Pins of the oracle's tracked-bubble model (bubble model 2, Sec. 2.2
+volume-pressure equation followed through coalescence and segmentation):
+the bubbles against scipy's connected-component labelling, Boyle's law for
+each bubble while none merges or splits, amounts added on coalescence,
+pressure kept on segmentation, periodic faces, and the single-bubble model as
+the special case of one bubble."""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from oracle.oracle import Oracle
+from paper_2207_13962_amd import inputs as I
+
+
+def _structure(q):
+    # lattice neighbours: faces and edges (D3Q19), also corners (D3Q27)
+    o = np.indices((3, 3, 3)) - 1
+    n1 = np.abs(o).sum(axis=0)
+    return n1 <= (3 if q == 27 else 2)
+
+
+def _random_state(q, seed, shape=(12, 11, 10)):
+    # gas cores of random boxes inside interface shells (all lattice
+    # neighbours of gas), stray interface cells, and obstacle cells strewn
+    # over everything; liquid elsewhere
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    gas = np.zeros(shape, dtype=bool)
+    for _ in range(7):
+        c = [rng.integers(1, n - 1) for n in shape]
+        h = rng.integers(0, 2, size=3)
+        gas[c[0] - h[0]:c[0] + h[0] + 1, c[1] - h[1]:c[1] + h[1] + 1, c[2] - h[2]:c[2] + h[2] + 1] = True
+    shell = ndimage.binary_dilation(np.pad(gas, 1), structure=_structure(q))[1:-1, 1:-1, 1:-1] & ~gas
+    t = np.full(shape, I.LIQUID, dtype=np.uint8)
+    t[shell | (rng.random(shape) < 0.03)] = I.INTERFACE
+    t[gas] = I.GAS
+    t[rng.random(shape) < 0.08] = I.NOSLIP
+    phi = np.where(t == I.INTERFACE, rng.uniform(0.05, 0.95, shape), np.where(t == I.LIQUID, 1.0, 0.0))
+    b = (I.WALL_NOSLIP,) * 6
+    p = I.Params(nx, ny, nz, q=q, boundary=b, bubble_model=2, tau=0.7)
+    n = p.n
+    z = np.zeros(n)
+    return I.Setup(p, t.ravel().copy(), phi.ravel().copy(), np.ones(n), z.copy(), z.copy(), z.copy())
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_bubbles_are_the_connected_components(q, seed):
+    s = _random_state(q, seed)
+    p = s.params
+    lab, vol, pr = Oracle(s).bubbles()
+    t = s.type.reshape(p.nz, p.ny, p.nx)
+    comp, n = ndimage.label((t == I.GAS) | (t == I.INTERFACE), structure=_structure(q))
+    comp = comp.ravel()
+    assert len(lab) == n and n > 3
+    w = 1.0 - s.phi
+    want = sorted((int(np.flatnonzero(comp == k)[0]), float(w[comp == k].sum())) for k in range(1, n + 1))
+    assert [int(x) for x in lab] == [a for a, _ in want]
+    np.testing.assert_allclose(vol, [v for _, v in want], rtol=1e-14)
+    np.testing.assert_allclose(pr, 1.0 / 3.0, rtol=1e-15)  # every bubble starts at p^V(0) = rho_gas / 3
+
+
+def test_periodic_faces_join_a_bubble():
+    lab1, vol1, _ = Oracle(I.bubble_pair("straddle", periodic_x=True)).bubbles()
+    lab2, vol2, _ = Oracle(I.bubble_pair("straddle", periodic_x=False)).bubbles()
+    assert len(lab1) == 1 and len(lab2) == 2
+    assert vol1[0] == pytest.approx(vol2.sum(), rel=1e-15)
+
+
+def test_boyle_for_each_bubble_apart():
+    o = Oracle(I.bubble_pair("apart", g=2e-4))
+    lab0, v0, p0 = o.bubbles()
+    assert len(lab0) == 2
+    moved = False
+    for _ in range(40):
+        assert o.step(1) == 0
+        lab, v, p = o.bubbles()
+        # cells convert (a bubble's smallest index may move), the amounts stay
+        assert len(lab) == 2
+        np.testing.assert_allclose(p * v, p0 * v0, rtol=1e-12)
+        moved |= not np.allclose(v, v0, rtol=1e-6)
+    assert moved  # the volumes do change under gravity; the amounts do not
+
+
+def test_coalescence_adds_the_amounts():
+    o = Oracle(I.bubble_pair("merge"))
+    lab0, v0, p0 = o.bubbles()
+    assert len(lab0) == 2
+    assert o.step(1) == 0
+    lab, v, p = o.bubbles()
+    assert len(lab) == 1
+    assert p[0] * v[0] == pytest.approx((p0 * v0).sum(), rel=1e-13)
+    # the new interface cells of the film came from liquid: no volume added
+    assert v[0] == pytest.approx(v0.sum(), rel=1e-13)
+
+
+def test_segmentation_keeps_the_pressure():
+    o = Oracle(I.bubble_pair("split"))
+    lab0, v0, p0 = o.bubbles()
+    assert len(lab0) == 1
+    assert o.step(1) == 0
+    lab, v, p = o.bubbles()
+    assert len(lab) == 2
+    assert p[0] == pytest.approx(p[1], rel=1e-14)
+    assert (p * v).sum() == pytest.approx(p0[0] * v0[0], rel=1e-13)
+    # the bridge filled, so the parts hold less volume than the parent did
+    # and both sit at the parent's amount over their joint volume
+    assert p[0] == pytest.approx(p0[0] * v0[0] / v.sum(), rel=1e-13)
+
+
+def test_one_bubble_is_the_single_bubble_model():
+    s2 = I.bubble_pair("straddle", periodic_x=True, g=2e-4)
+    s1 = I.Setup(s2.params.with_(bubble_model=1), s2.type, s2.phi, s2.rho, s2.ux, s2.uy, s2.uz)
+    o1, o2 = Oracle(s1), Oracle(s2)
+    for _ in range(30):
+        assert o1.step(1) == 0 and o2.step(1) == 0
+        lab, v, p = o2.bubbles()
+        assert len(lab) == 1
+        m1 = o1.mass()
+        assert p[0] == pytest.approx(m1.p_volume, rel=1e-13)
+    f1, f2 = o1.fields(), o2.fields()
+    assert np.array_equal(f1["type"], f2["type"])
+    np.testing.assert_allclose(f2["pdf"], f1["pdf"], rtol=0, atol=1e-13)
