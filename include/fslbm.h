@@ -69,7 +69,10 @@ typedef struct {
   int32_t thurey_flux;   /* 1: interface cells without liquid (gas) neighbours are forced to
                             empty (fill) through the mass flux, Sec. 2.2; 0: plain flux */
   int32_t bubble_model;  /* 0: constant volume pressure; 1: one enclosed bubble,
-                            p^V(t) = p^V(0) V(0)/V(t), Sec. 2.2 */
+                            p^V(t) = p^V(0) V(0)/V(t), Sec. 2.2; 2: every connected
+                            region of gas and interface cells is a bubble with its own
+                            p^V, its amount p^V V kept (Boyle), added on coalescence
+                            and shared by gas volume on segmentation (fslbm_bubbles) */
   double tau;            /* relaxation time, > 0.5 (nu = (tau - 1/2)/3) */
   double trt_lambda;     /* TRT magic parameter, used only for FSLBM_TRT */
   double gravity[3];     /* acceleration; force density F = rho g, not weighted by phi */
@@ -136,6 +139,19 @@ int fslbm_fields(fslbm_ctx* ctx, uint8_t* type, double* phi, double* rho, double
 /* Number of interface cells in the compacted interface list and, if list is not
  * NULL, the list itself (ascending cell indices, at most max entries). Syncs. */
 int fslbm_interface_list(fslbm_ctx* ctx, int32_t* list, int64_t max, int64_t* count);
+
+/* Tracked bubbles (bubble_model 2: Sec. 2.2 volume-pressure equation, each
+ * connected region of gas and interface cells its own bubble, followed
+ * through coalescence and segmentation). Waits for the stream; *count = the
+ * number of bubbles (0 for the other models) and, for the first max of them
+ * in ascending label order, label[i] = the bubble's smallest cell index,
+ * volume[i] = sum of 1 - phi over its cells, pressure[i] = its volume
+ * pressure p^V. Arrays are host memory owned by the caller (may be NULL when
+ * max is 0). Errors: FSLBM_EINVAL (NULL count, or NULL arrays with max > 0);
+ * FSLBM_EDEVICE if the labelling did not complete; FSLBM_EUNSTABLE as for
+ * fslbm_mass (the arrays are still filled). */
+int fslbm_bubbles(fslbm_ctx* ctx, int64_t* label, double* volume, double* pressure, int64_t max,
+                  int64_t* count);
 
 /* Kernel timing for measurement. fslbm_set_timing(ctx, capacity) with
  * capacity > 0 brackets the next `capacity` launches of the streaming kernel

@@ -93,8 +93,8 @@ struct orc_sim {
   /* tracked bubbles (bubble_model 2): label per cell (-1: no bubble), and at
    * each bubble's label index its gas amount and pressure; per cell the
    * volume pressure of its bubble; work arrays of the update */
-  int32_t *blab, *bnew;
-  double *bamt, *bpr, *bpc, *bV, *bW, *bnn;
+  int32_t *blab, *bnew, *btgt;
+  double *bamt, *bpr, *bpc, *bV, *bW, *bR, *bnn;
   uint8_t* bhas;
   long* bqueue;
   int64_t step;
@@ -460,6 +460,8 @@ void orc_destroy(orc_sim* s) {
   free(s->ntype);
   free(s->blab);
   free(s->bnew);
+  free(s->btgt);
+  free(s->bR);
   free(s->bamt);
   free(s->bpr);
   free(s->bpc);
@@ -486,6 +488,12 @@ void orc_destroy(orc_sim* s) {
  * pressure), cells that were in no bubble add volume only, and a new bubble
  * holding none of an old bubble's volume starts at p^V(0). p^V = n / V
  * (p^V(0) where V <= 0). A bubble is labelled by its smallest cell index.
+ * The hand-over n_C = sum_b n_b w_bC / W_b (w_bC: volume of b's former cells
+ * now in C, W_b = sum_C w_bC) is summed so that a bubble that neither merges
+ * nor splits keeps its amount exactly: of each old bubble, the new bubble
+ * with the smallest label among its former cells receives the rest,
+ * n_b (1 - R_b / W_b), R_b being the volume of b's former cells elsewhere,
+ * and every other new bubble the shares of its cells.
  * ------------------------------------------------------------------------- */
 static int is_bubble_cell(int t) { return t == ORC_GAS || t == ORC_INTERFACE; }
 
@@ -526,23 +534,37 @@ static void update_bubbles(orc_sim* s, int first) {
   for (long c = 0; c < N; ++c) {
     s->bV[c] = 0.0;
     s->bW[c] = 0.0;
+    s->bR[c] = 0.0;
     s->bnn[c] = 0.0;
     s->bhas[c] = 0;
+    s->btgt[c] = -1;
   }
   /* V of each new bubble; W of each old bubble: the gas volume of its
-   * former cells that are still bubble cells */
+   * former cells that are still bubble cells; its target: the smallest new
+   * label among them */
   for (long c = 0; c < N; ++c) {
     if (nl[c] < 0) continue;
     s->bV[nl[c]] += gas_volume(s, c);
-    if (!first && s->blab[c] >= 0) s->bW[s->blab[c]] += gas_volume(s, c);
+    if (first || s->blab[c] < 0) continue;
+    long b = s->blab[c];
+    s->bW[b] += gas_volume(s, c);
+    if (s->btgt[b] < 0 || nl[c] < s->btgt[b]) s->btgt[b] = nl[c];
   }
-  /* amounts: old bubble b gives n_b w / W_b through each former cell */
+  /* amounts: through each former cell outside the target, n_b w / W_b;
+   * R_b collects those cells' volume */
   for (long c = 0; c < N; ++c) {
     if (nl[c] < 0 || first || s->blab[c] < 0) continue;
     long b = s->blab[c];
     if (!(s->bW[b] > 0.0)) continue;
-    s->bnn[nl[c]] += s->bamt[b] * (gas_volume(s, c) / s->bW[b]);
     s->bhas[nl[c]] = 1;
+    if (nl[c] == s->btgt[b]) continue;
+    s->bnn[nl[c]] += s->bamt[b] * (gas_volume(s, c) / s->bW[b]);
+    s->bR[b] += gas_volume(s, c);
+  }
+  /* the target receives the rest of the old bubble's amount */
+  for (long b = 0; b < N; ++b) {
+    if (s->btgt[b] < 0 || !(s->bW[b] > 0.0)) continue;
+    s->bnn[s->btgt[b]] += s->bamt[b] * (1.0 - s->bR[b] / s->bW[b]);
   }
   for (long c = 0; c < N; ++c) {
     if (nl[c] != c) continue;
@@ -652,6 +674,8 @@ int orc_create(const orc_params* p, const uint8_t* type, const double* phi, cons
   if (p->bubble_model == 2) {
     s->blab = (int32_t*)xcalloc(N, 4);
     s->bnew = (int32_t*)xcalloc(N, 4);
+    s->btgt = (int32_t*)xcalloc(N, 4);
+    s->bR = (double*)xcalloc(N, 8);
     s->bamt = (double*)xcalloc(N, 8);
     s->bpr = (double*)xcalloc(N, 8);
     s->bpc = (double*)xcalloc(N, 8);
@@ -660,7 +684,7 @@ int orc_create(const orc_params* p, const uint8_t* type, const double* phi, cons
     s->bnn = (double*)xcalloc(N, 8);
     s->bhas = (uint8_t*)xcalloc(N, 1);
     s->bqueue = (long*)xcalloc(N, sizeof(long));
-    if (!s->blab || !s->bnew || !s->bamt || !s->bpr || !s->bpc || !s->bV || !s->bW || !s->bnn ||
+    if (!s->blab || !s->bnew || !s->btgt || !s->bR || !s->bamt || !s->bpr || !s->bpc || !s->bV || !s->bW || !s->bnn ||
         !s->bhas || !s->bqueue) {
       orc_destroy(s);
       return ORC_ENOMEM;

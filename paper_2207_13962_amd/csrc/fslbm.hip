@@ -95,7 +95,8 @@ void bind(fslbm_ctx* c) {
   d.phiB = reinterpret_cast<double*>(a + L.off_phiB);
   d.m = reinterpret_cast<double*>(a + L.off_m);
   d.rho_if = reinterpret_cast<double*>(a + L.off_rho_if);
-  d.rhoG = c->p.sigma != 0.0 ? reinterpret_cast<double*>(a + L.off_rhoG) : nullptr;
+  const bool tracked = c->p.bubble_model == 2;
+  d.rhoG = c->p.sigma != 0.0 || tracked ? reinterpret_cast<double*>(a + L.off_rhoG) : nullptr;
   d.phis = c->p.sigma != 0.0 ? reinterpret_cast<double*>(a + L.off_phis) : nullptr;
   d.lost = reinterpret_cast<double*>(a + L.off_lost);
   d.if_list = reinterpret_cast<int32_t*>(a + L.off_if_list);
@@ -109,6 +110,16 @@ void bind(fslbm_ctx* c) {
   d.scan_status = reinterpret_cast<unsigned long long*>(a + L.off_scan_status);
   d.pV = reinterpret_cast<double*>(a + L.off_pv);
   d.partial = reinterpret_cast<double*>(a + L.off_partial);
+  d.blab = tracked ? reinterpret_cast<int32_t*>(a + L.off_blab) : nullptr;
+  d.bpar = tracked ? reinterpret_cast<int32_t*>(a + L.off_bpar) : nullptr;
+  d.btgt = tracked ? reinterpret_cast<int32_t*>(a + L.off_btgt) : nullptr;
+  d.bV = tracked ? reinterpret_cast<double*>(a + L.off_bV) : nullptr;
+  d.bW = tracked ? reinterpret_cast<double*>(a + L.off_bW) : nullptr;
+  d.bR = tracked ? reinterpret_cast<double*>(a + L.off_bR) : nullptr;
+  d.bnn = tracked ? reinterpret_cast<double*>(a + L.off_bnn) : nullptr;
+  d.bamt = tracked ? reinterpret_cast<double*>(a + L.off_bamt) : nullptr;
+  d.bpr = tracked ? reinterpret_cast<double*>(a + L.off_bpr) : nullptr;
+  d.bhas = tracked ? reinterpret_cast<uint8_t*>(a + L.off_bhas) : nullptr;
 }
 
 double* stage(fslbm_ctx* c) { return reinterpret_cast<double*>(c->arena + c->L.off_stage); }
@@ -128,6 +139,22 @@ void launch_volume(fslbm_ctx* c, hipStream_t s, bool set_reference) {
   }
 }
 
+// Tracked bubbles from the types and fill levels at t+1 (flags, phiB): new
+// labels, volumes, amounts handed over, pressures, gas densities.
+void launch_bubbles(fslbm_ctx* c, hipStream_t s) {
+  const dim3 grid(grid_for(c->L.N)), block(kBlock);
+  hipLaunchKernelGGL(k_bub_init, grid, block, 0, s, c->d);
+  if (c->p.q == 19)
+    hipLaunchKernelGGL(k_bub_union<19>, grid, block, 0, s, c->d);
+  else
+    hipLaunchKernelGGL(k_bub_union<27>, grid, block, 0, s, c->d);
+  hipLaunchKernelGGL(k_bub_volume, grid, block, 0, s, c->d);
+  hipLaunchKernelGGL(k_bub_amount, grid, block, 0, s, c->d);
+  hipLaunchKernelGGL(k_bub_target, grid, block, 0, s, c->d);
+  hipLaunchKernelGGL(k_bub_pressure, grid, block, 0, s, c->d);
+  hipLaunchKernelGGL(k_bub_cells, grid, block, 0, s, c->d);
+}
+
 void enqueue_plain(fslbm_ctx* c, int64_t n) {
   const Ops ops = pick(c->p);
   hipStream_t s = c->stream;
@@ -142,7 +169,8 @@ void enqueue_plain(fslbm_ctx* c, int64_t n) {
     }
     ops.step(c, s);
     ops.convert(c, s, 0);
-    if (c->p.bubble_model) launch_volume(c, s, false);
+    if (c->p.bubble_model == 1) launch_volume(c, s, false);
+    if (c->p.bubble_model == 2) launch_bubbles(c, s);
     std::swap(c->d.fA, c->d.fB);
     std::swap(c->d.phiA, c->d.phiB);
     c->step += 1;
@@ -192,6 +220,10 @@ int read_status(fslbm_ctx* c) {
   if (err & ERR_SCAN) {
     c->status = FSLBM_EDEVICE;
     return set_err(c, FSLBM_EDEVICE, "interface-list scan did not complete");
+  }
+  if (err & ERR_BUBBLE) {
+    c->status = FSLBM_EDEVICE;
+    return set_err(c, FSLBM_EDEVICE, "bubble labelling did not complete");
   }
   if (err & (ERR_UNSTABLE | ERR_LAYER)) {
     char buf[160];
@@ -322,6 +354,11 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   INITCHK(hipMemcpyAsync(c->d.pV, pv0, sizeof pv0, hipMemcpyHostToDevice, s));
   // V(0) from phiB == phiA at this point
   launch_volume(c, s, true);
+  if (c->p.bubble_model == 2) {
+    // no old bubbles: every bubble starts at p^V(0)
+    INITCHK(hipMemsetAsync(c->d.blab, 0xff, 4 * N, s));
+    launch_bubbles(c, s);
+  }
   INITCHK(hipGetLastError());
   INITCHK(hipStreamSynchronize(s));
 #undef INITCHK
@@ -415,6 +452,33 @@ int fslbm_interface_list(fslbm_ctx* c, int32_t* list, int64_t max, int64_t* coun
     for (int64_t i = 0; i < n; ++i) list[i] &= 0x7fffffff;  // drop the BORDER bit
   }
   return FSLBM_OK;
+}
+
+int fslbm_bubbles(fslbm_ctx* c, int64_t* label, double* volume, double* pressure, int64_t max,
+                  int64_t* count) {
+  if (!c || !count) return FSLBM_EINVAL;
+  *count = 0;
+  if (max > 0 && (!label || !volume || !pressure)) return set_err(c, FSLBM_EINVAL, "NULL output array");
+  if (c->p.bubble_model != 2) return FSLBM_OK;
+  const int64_t N = c->L.N;
+  std::vector<int32_t> lab(N);
+  std::vector<double> V(N), P(N);
+  HIPCHK(c, hipMemcpyAsync(lab.data(), c->d.blab, 4 * N, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(V.data(), c->d.bV, 8 * N, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(P.data(), c->d.bpr, 8 * N, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int64_t n = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    if (lab[i] != (int32_t)i) continue;
+    if (n < max) {
+      label[n] = i;
+      volume[n] = V[i];
+      pressure[n] = P[i];
+    }
+    ++n;
+  }
+  *count = n;
+  return read_status(c);
 }
 
 static void release_events(fslbm_ctx* c) {

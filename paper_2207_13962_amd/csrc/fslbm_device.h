@@ -81,7 +81,7 @@ enum {
   CNT_NL = 12,     // new interface cells from liquid in this step
   CNT_N = 16
 };
-enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8 };
+enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8, ERR_BUBBLE = 16 };
 
 // ---------------------------------------------------------------------------
 // Population storage. R is the arithmetic type; kShift tells whether the

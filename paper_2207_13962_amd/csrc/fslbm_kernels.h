@@ -65,6 +65,15 @@ struct Dev {
   int32_t* cnt;
   unsigned long long* scan_status;  // two words per compaction tile
   double* pV;  // device scalars: [0] p^V, [1] p^V(0), [2] V(0)
+  // tracked bubbles (bubble model 2), N each, or null: label per cell (-1:
+  // no bubble) and the new labels while they are found; at a bubble's label
+  // index its volume, its former cells' volume, the amount handed to it, its
+  // amount and pressure, and whether any old bubble handed it an amount
+  int32_t* blab;
+  int32_t* bpar;
+  int32_t* btgt;  // at an old bubble's label: the smallest new label among its cells
+  double *bV, *bW, *bR, *bnn, *bamt, *bpr;
+  uint8_t* bhas;
   double* partial;  // reduction partials
   int64_t step;  // parity selects the mark-counter slot
 };
@@ -1432,7 +1441,8 @@ __global__ __launch_bounds__(kBlock) void k_curvature(Dev d) {
       div += 0.5 * (np_ - nm_);
     }
     const double kappa = -div;
-    d.rhoG[c] = 3.0 * (d.pV[0] + d.sigma * kappa);
+    const double pv = d.bubble == 2 ? d.bpr[d.blab[c]] : d.pV[0];
+    d.rhoG[c] = 3.0 * (pv + d.sigma * kappa);
   }
 }
 
@@ -1525,6 +1535,210 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partial, 
 
 __global__ void k_update_pv(double* pV, const double* V) {
   if (threadIdx.x == 0) pV[0] = pV[1] * pV[2] / V[0];
+}
+
+// ---------------------------------------------------------------------------
+// Tracked bubbles (bubble model 2; Sec. 2.2 volume pressure followed through
+// coalescence and segmentation). A bubble is a connected set of gas and
+// interface cells (lattice neighbours, periodic faces wrap); V = sum of
+// 1 - phi; its amount n = p^V V is kept by Boyle's law. After each step the
+// bubbles are found again (union-find, each bubble's root its smallest cell
+// index); an old bubble hands its amount to the new bubbles holding its
+// former cells in proportion to their gas volume, cells new to any bubble
+// add volume only, and a bubble without any handed amount starts at p^V(0).
+// Of each old bubble, the new bubble with the smallest label among its former
+// cells receives the rest of its amount, n_b (1 - R_b / W_b) (R_b: volume of
+// its former cells elsewhere), so a bubble that neither merges nor splits
+// keeps its amount exactly; the others the shares n_b w / W_b of their cells.
+// Seven passes over the grid; sums by atomic adds, combined per wave first.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool bubble_cell(uint8_t f) {
+  const int t = f & T_MASK;
+  return t == T_GAS || t == T_IF;
+}
+
+// A parent always has a smaller index than its child (a root is linked under
+// a smaller root by compare-and-swap, and halving replaces a parent by an
+// ancestor), so every chain of reads strictly decreases and ends within N
+// hops; `bound` (N + 1) only guards the kernel's exit. While links are being
+// made, finds halve the paths they walk (non-root entries only, so the
+// compare-and-swap on roots is unaffected); afterwards they only read.
+template <bool HALVE>
+__device__ __forceinline__ int32_t find_root(int32_t* par, int32_t x, int64_t bound) {
+  for (int64_t i = 0; i < bound; ++i) {
+    const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p < 0) return -1;
+    if (p == x) return x;
+    if (HALVE) {
+      const int32_t gp = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (gp < 0) return -1;
+      if (gp != p) __hip_atomic_store(&par[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      x = gp;
+    } else {
+      x = p;
+    }
+  }
+  return -1;
+}
+
+__device__ __forceinline__ bool unite(int32_t* par, int32_t a, int32_t b, int64_t bound) {
+  for (int64_t i = 0; i < bound; ++i) {
+    a = find_root<true>(par, a, bound);
+    b = find_root<true>(par, b, bound);
+    if (a < 0 || b < 0) return false;
+    if (a == b) return true;
+    if (a < b) {
+      const int32_t t = a;
+      a = b;
+      b = t;
+    }
+    int32_t expected = a;  // link the larger root under the smaller one
+    if (__hip_atomic_compare_exchange_strong(&par[a], &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return true;
+    a = expected;  // a was linked meanwhile: continue from its parent
+  }
+  return false;
+}
+
+// Adds v at base[key] once per distinct key of the wave's active lanes.
+__device__ __forceinline__ void wave_add(double* base, int32_t key, double v, bool act) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(act);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int32_t k = __shfl(key, leader);
+    const bool mine = ((pending >> lane) & 1ull) && key == k;
+    const unsigned long long m = __ballot(mine);
+    double x = mine ? v : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == leader) atomicAdd(&base[k], x);
+    pending &= ~m;
+  }
+}
+
+// Lowers base[key] to the smallest v of the wave's active lanes with that key.
+__device__ __forceinline__ void wave_min(int32_t* base, int32_t key, int32_t v, bool act) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(act);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int32_t k = __shfl(key, leader);
+    const bool mine = ((pending >> lane) & 1ull) && key == k;
+    const unsigned long long m = __ballot(mine);
+    int32_t x = mine ? v : INT32_MAX;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
+    if (lane == leader) atomicMin(&base[k], x);
+    pending &= ~m;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bub_init(Dev d) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= d.g.N) return;
+  d.bpar[c] = bubble_cell(d.flags[c]) ? (int32_t)c : -1;
+  d.bV[c] = 0.0;
+  d.bW[c] = 0.0;
+  d.bR[c] = 0.0;
+  d.bnn[c] = 0.0;
+  d.bhas[c] = 0;
+  d.btgt[c] = INT32_MAX;
+}
+
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_bub_union(Dev d) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= d.g.N || !bubble_cell(d.flags[c])) return;
+  int x, y, z;
+  coords(d.g, c, x, y, z);
+  bool ok = true;
+  // one direction of each opposite pair: every link is seen from one end
+  for (int k = 1; k < Q; k += 2) {
+    int w;
+    const int64_t j = nb_index(d.g, x, y, z, cxd(k), cyd(k), czd(k), &w);
+    if (j >= 0 && j != c && bubble_cell(d.flags[j]))
+      ok &= unite(d.bpar, (int32_t)c, (int32_t)j, d.g.N + 1);
+  }
+  if (!ok) atomicOr(&d.cnt[CNT_ERR], ERR_BUBBLE);
+}
+
+// Flattens the new labels; sums the new bubbles' volumes and the old
+// bubbles' still-gaseous volumes.
+__global__ __launch_bounds__(kBlock) void k_bub_volume(Dev d) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool in = c < d.g.N;
+  const uint8_t f = in ? d.flags[c] : 0;
+  const bool bub = in && bubble_cell(f);
+  int32_t r = -1;
+  if (bub) {
+    r = find_root<false>(d.bpar, (int32_t)c, d.g.N + 1);
+    if (r < 0) atomicOr(&d.cnt[CNT_ERR], ERR_BUBBLE);
+  }
+  const bool ok = bub && r >= 0;
+  const double w = ok ? ((f & T_MASK) == T_GAS ? 1.0 : 1.0 - d.phiB[c]) : 0.0;
+  const int32_t old = ok ? d.blab[c] : -1;
+  wave_add(d.bV, r, w, ok);
+  wave_add(d.bW, old, w, old >= 0);
+  wave_min(d.btgt, old, r, old >= 0);
+  // a root stays its own parent and r is an ancestor of c, so other
+  // threads' finds through c still end at the same root
+  if (ok) __hip_atomic_store(&d.bpar[c], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Amounts handed from old to new bubbles through the cells they share.
+__global__ __launch_bounds__(kBlock) void k_bub_amount(Dev d) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool in = c < d.g.N;
+  const uint8_t f = in ? d.flags[c] : 0;
+  const int32_t r = in && bubble_cell(f) ? d.bpar[c] : -1;
+  const int32_t old = r >= 0 ? d.blab[c] : -1;
+  double share = 0.0, w = 0.0;
+  bool act = false;
+  if (old >= 0) {
+    const double W = d.bW[old];
+    if (W > 0.0) {
+      d.bhas[r] = 1;
+      if (r != d.btgt[old]) {
+        w = (f & T_MASK) == T_GAS ? 1.0 : 1.0 - d.phiB[c];
+        share = d.bamt[old] * (w / W);
+        act = true;
+      }
+    }
+  }
+  wave_add(d.bnn, r, share, act);
+  wave_add(d.bR, old, w, act);
+}
+
+// Each old bubble's target receives the rest of its amount.
+__global__ __launch_bounds__(kBlock) void k_bub_target(Dev d) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= d.g.N) return;
+  const int32_t t = d.btgt[c];
+  if (t == INT32_MAX || !(d.bW[c] > 0.0)) return;
+  atomicAdd(&d.bnn[t], d.bamt[c] * (1.0 - d.bR[c] / d.bW[c]));
+}
+
+// Amount and pressure of each new bubble, at its root.
+__global__ __launch_bounds__(kBlock) void k_bub_pressure(Dev d) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= d.g.N || d.bpar[c] != (int32_t)c) return;
+  const double p0 = d.pV[1], V = d.bV[c];
+  const double n = d.bhas[c] ? d.bnn[c] : p0 * V;
+  d.bamt[c] = n;
+  d.bpr[c] = V > 0.0 ? n / V : p0;
+}
+
+// New labels become the current ones; gas density of every bubble cell from
+// its bubble's pressure (interface cells read it in the next step; with
+// surface tension the curvature pass adds the Laplace term).
+__global__ __launch_bounds__(kBlock) void k_bub_cells(Dev d) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= d.g.N) return;
+  const int32_t r = bubble_cell(d.flags[c]) ? d.bpar[c] : -1;
+  d.blab[c] = r;
+  if (r >= 0) d.rhoG[c] = 3.0 * d.bpr[r];
 }
 
 #endif  // FSLBM_HOST_KERNELS

@@ -28,7 +28,8 @@ struct Layout {
   size_t off_fA, off_fB, off_flags, off_mark, off_cls, off_phiA, off_phiB, off_m, off_rho_if,
       off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_gen_list,
       off_mark_list, off_ng_list, off_nl_list, off_cnt, off_scan_status,
-      off_pv, off_partial, off_stage, total;
+      off_pv, off_partial, off_stage, off_blab, off_bpar, off_btgt, off_bV, off_bW, off_bR, off_bnn,
+      off_bamt, off_bpr, off_bhas, total;
 };
 
 constexpr int kRedCells = 8192;  // cells per reduction block
@@ -58,7 +59,8 @@ inline Layout make_layout(const fslbm_params& p) {
   L.off_phiB = take(8 * L.N);
   L.off_m = take(8 * L.N);
   L.off_rho_if = take(8 * L.N);
-  L.off_rhoG = take(p.sigma != 0.0 ? 8 * L.N : 0);
+  const bool tracked = p.bubble_model == 2;
+  L.off_rhoG = take(p.sigma != 0.0 || tracked ? 8 * L.N : 0);
   L.off_phis = take(p.sigma != 0.0 ? 8 * L.N : 0);
   L.off_lost = take(8 * L.N);
   L.off_if_list = take(4 * L.N);
@@ -73,6 +75,16 @@ inline Layout make_layout(const fslbm_params& p) {
   L.off_pv = take(8 * 8);
   L.off_partial = take(8 * kRedN * L.red_blocks + 8 * 16);
   L.off_stage = take(8 * L.N);
+  L.off_blab = take(tracked ? 4 * L.N : 0);
+  L.off_bpar = take(tracked ? 4 * L.N : 0);
+  L.off_btgt = take(tracked ? 4 * L.N : 0);
+  L.off_bV = take(tracked ? 8 * L.N : 0);
+  L.off_bW = take(tracked ? 8 * L.N : 0);
+  L.off_bR = take(tracked ? 8 * L.N : 0);
+  L.off_bnn = take(tracked ? 8 * L.N : 0);
+  L.off_bamt = take(tracked ? 8 * L.N : 0);
+  L.off_bpr = take(tracked ? 8 * L.N : 0);
+  L.off_bhas = take(tracked ? L.N : 0);
   L.total = o;
   return L;
 }
@@ -98,6 +110,7 @@ inline const char* validate(const fslbm_params* p) {
   if (!(p->eps_phi >= 0.0)) return "eps_phi must be >= 0";
   if (p->sigma < 0.0) return "sigma must be >= 0";
   if (!(p->smagorinsky >= 0.0)) return "smagorinsky must be >= 0";
+  if (p->bubble_model < 0 || p->bubble_model > 2) return "bubble_model must be 0, 1 or 2";
   return nullptr;
 }
 

@@ -50,7 +50,7 @@ class MassReport(C.Structure):
 _lib = None
 
 EXPORTED = ["fslbm_workspace_bytes", "fslbm_create", "fslbm_set_variant", "fslbm_step",
-            "fslbm_mass", "fslbm_fields", "fslbm_interface_list", "fslbm_set_timing",
+            "fslbm_mass", "fslbm_fields", "fslbm_interface_list", "fslbm_bubbles", "fslbm_set_timing",
             "fslbm_kernel_time", "fslbm_set_graphs", "fslbm_set_compaction_tile", "fslbm_destroy",
             "fslbm_strerror", "fslbm_last_error", "fslbm_server_create", "fslbm_server_submit",
             "fslbm_server_advance", "fslbm_server_poll", "fslbm_server_result",
@@ -86,6 +86,8 @@ def load_library(path: str = LIB_PATH):
     lib.fslbm_fields.argtypes = [vp, u8p, dp, dp, dp, dp, dp, dp, dp]
     lib.fslbm_fields.restype = C.c_int
     lib.fslbm_interface_list.argtypes = [vp, C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int64)]
+    lib.fslbm_bubbles.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int64)]
     lib.fslbm_interface_list.restype = C.c_int
     lib.fslbm_set_timing.argtypes = [vp, C.c_int64]
     lib.fslbm_set_timing.restype = C.c_int
@@ -244,6 +246,22 @@ class Simulation:
         self._check(self._lib.fslbm_interface_list(
             self._h, out.ctypes.data_as(C.POINTER(C.c_int32)), cnt.value, C.byref(cnt)))
         return out[:cnt.value]
+
+    def bubbles(self, check=True):
+        """Tracked bubbles (bubble model 2): labels (smallest cell index), gas
+        volumes and volume pressures, ascending by label."""
+        cnt = C.c_int64()
+        st = self._lib.fslbm_bubbles(self._h, None, None, None, 0, C.byref(cnt))
+        if check:
+            self._check(st)
+        k = max(cnt.value, 1)
+        lab = np.zeros(k, dtype=np.int64)
+        vol, pr = np.zeros(k), np.zeros(k)
+        st = self._lib.fslbm_bubbles(self._h, lab.ctypes.data_as(C.POINTER(C.c_int64)), _dp(vol), _dp(pr),
+                                     cnt.value, C.byref(cnt))
+        if check:
+            self._check(st)
+        return lab[:cnt.value], vol[:cnt.value], pr[:cnt.value]
 
     def set_graphs(self, enable):
         """Replay captured step graphs (default) or launch kernel by kernel."""

@@ -325,6 +325,34 @@ def bubble_pair(kind="apart", q=19, storage=F64, variant=OM, periodic_x=False, g
     return Setup(p, tt, ph, rho, z.copy(), z.copy(), z.copy(), "bubble_pair_" + kind, steps)
 
 
+def bubbly_column(nx=48, ny=40, nz=56, n_bubbles=14, radius=(2.5, 6.0), fill=0.75, g=1e-4, seed=7, q=19,
+                  storage=F64, variant=OM, bubble_model=2, steps=0) -> Setup:
+    """Closed box (no-slip walls) filled with liquid up to fill * nz, gas
+    above, and n_bubbles spherical gas bubbles of random radius (seeded) in
+    the liquid, some overlapping; gravity -z, D3Q19 SRT, tracked-bubble model
+    (the gas above the surface is a bubble too: the box is closed)."""
+    rng = np.random.default_rng(seed)
+    b = (WALL_NOSLIP,) * 6
+    p = Params(nx, ny, nz, q=q, collision=SRT, storage=storage, boundary=b, variant=variant, tau=0.6,
+               bubble_model=bubble_model, gravity=(0.0, 0.0, -g))
+    h = fill * nz
+    centres = []
+    for _ in range(n_bubbles):
+        r = rng.uniform(*radius)
+        c = (rng.uniform(r + 1, nx - r - 1), rng.uniform(r + 1, ny - r - 1), rng.uniform(r + 2, h - r - 2))
+        centres.append((c, r))
+
+    def inside(x, y, z):  # liquid
+        liq = z < h
+        for (cx, cy, cz), r in centres:
+            liq &= (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 > r * r
+        return liq
+
+    phi = supersampled_fill(nx, ny, nz, inside, sub=4)
+    rho = hydrostatic_rho(p, h, 2, g)
+    return _finish(p, phi, rho, "bubbly_column", steps, meta=dict(g=g, fill=fill, bubbles=centres))
+
+
 def rect_dam_break(nx=256, ny=128, nz=64, wx=64, hy=96, g=2e-5, nu=1e-3, q=19, collision=TRT,
                    storage=F32, variant=OM, steps=5000, boundary=None) -> Setup:
     """Rectangular dam break (Sec. 4.2 shape): a liquid column wx x hy x nz in
