@@ -132,7 +132,8 @@ def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, last, command):
     print(open(TRAFFIC_FILE).read())
 
 
-def write_trace_summary(trace_dir, out_path, last, command):
+def write_trace_summary(trace_dir, out_path, last, command,
+                        title="rocprofv3 kernel trace of the benchmark, dam256 workload (4 variant runs)."):
     """Short text summary of a rocprofv3 --kernel-trace --stats run of the
     benchmark: per-kernel calls and mean duration, plus the streaming kernel's
     mean over the last `last` launches (the kernel-timing region)."""
@@ -143,7 +144,7 @@ def write_trace_summary(trace_dir, out_path, last, command):
     ks = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace
           if r["Kernel_Name"].startswith("void fslbm::k_stream<")]
     with open(out_path, "w") as fh:
-        fh.write("# rocprofv3 kernel trace of the benchmark, dam256 workload (4 variant runs).\n")
+        fh.write("# %s\n" % title)
         fh.write("# command (from the repository root):\n")
         for c in command:
             fh.write("#   %s\n" % c)
@@ -209,6 +210,63 @@ def scale_point(args, variant=3, warm=200, timed=200):
         "avg_launch_ms": kms / n,
         "bytes_per_launch": per_launch,
         "status": "ok" if ka["status"] == 0 else "unstable (%d)" % ka["status"],
+    }
+
+
+# Algorithmic bytes per grid cell of one tracked-bubble update (seven passes):
+# init 42 (flags; parent, volumes, target, flag written), union 5 (flags,
+# parent), volume 21 (flags, parent, phi, old label; root written), amount 17
+# (flags, parent, old label, phi), target 4, pressure 4, cells 17 (flags,
+# parent; label and gas density written). Per-bubble entries are cached.
+BUBBLE_BYTES_PER_CELL = 110
+
+
+def bubbles_bench(args, warm=100, timed=200):
+    """Cost of the tracked-bubble model (bubble model 2): the same closed box
+    of rising bubbles stepped with a constant volume pressure and with every
+    bubble tracked; the difference per step is the bubble update."""
+    import torch
+    from paper_2207_13962_amd import inputs as I
+    from paper_2207_13962_amd.fslbm import Simulation
+
+    out = {}
+    s2 = I.bubbly_column(nx=192, ny=128, nz=128, n_bubbles=80, radius=(3.0, 9.0), fill=0.8, g=2e-5,
+                         seed=11, storage=I.F32, bubble_model=2, sub=2)
+    print("bubbles bench: setup built", file=sys.stderr, flush=True)
+    for model in (0, 2):
+        s = I.Setup(s2.params.with_(bubble_model=model), s2.type, s2.phi, s2.rho, s2.ux, s2.uy, s2.uz)
+        p = s.params
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            sim = Simulation(s, device="cuda:0", stream=stream)
+            sim.set_graphs(not args.no_graphs)
+            sim.step(warm)
+            stream.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            sim.step(timed)
+            ev1.record(stream)
+            stream.synchronize()
+            ms = ev0.elapsed_time(ev1) / timed
+            m = sim.mass(check=False)
+            nb = len(sim.bubbles(check=False)[0]) if model == 2 else None
+            sim.close()
+        out[model] = dict(ms=ms, fluid=int(m["n_liquid"] + m["n_interface"]), status=m["status"], bubbles=nb)
+        print("bubbles bench: model %d %.4f ms per step" % (model, ms), file=sys.stderr, flush=True)
+    n = p.n
+    over_us = (out[2]["ms"] - out[0]["ms"]) * 1e3
+    return {
+        "workload": "closed box %dx%dx%d of liquid (80%% full) with 80 rising bubbles (radius 3-9), D3Q19 SRT "
+                    "FP32, variant OM, steps %d-%d" % (p.nx, p.ny, p.nz, warm, warm + timed),
+        "cells": n,
+        "fluid_cells": out[2]["fluid"],
+        "bubbles_tracked": out[2]["bubbles"],
+        "ms_per_step_constant_pressure": out[0]["ms"],
+        "ms_per_step_tracked_bubbles": out[2]["ms"],
+        "bubble_update_us": over_us,
+        "bubble_bytes_per_cell": BUBBLE_BYTES_PER_CELL,
+        "bubble_update_GBps": BUBBLE_BYTES_PER_CELL * n / (over_us * 1e-6) / 1e9 if over_us > 0 else None,
+        "status": ["ok" if out[k]["status"] == 0 else "unstable (%d)" % out[k]["status"] for k in (0, 2)],
     }
 
 
@@ -466,6 +524,8 @@ def main():
                     help="summarise rocprofv3 counter runs into the traffic file and exit")
     ap.add_argument("--write-trace-summary", metavar="TRACE_DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--trace-title", default=None, help="first line of a trace summary")
+    ap.add_argument("--trace-out", default=None, help="file a trace summary is written to")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in a profile summary (repeat per run)")
     ap.add_argument("--precision-study", action="store_true",
@@ -477,6 +537,8 @@ def main():
                     help="skip the streaming kernel on the dam break scaled 2x per axis")
     ap.add_argument("--validate-taylor", type=int, default=0, metavar="D",
                     help="the paper's Taylor-bubble runs at tube diameter D (32, 64 or 128), four variants")
+    ap.add_argument("--bubbles", action="store_true",
+                    help="only the cost of the tracked-bubble model on a closed box of rising bubbles")
     ap.add_argument("--validate-wave", type=int, default=0, metavar="L",
                     help="the paper's gravity wave at wavelength L (200, 400 or 800), four variants")
     ap.add_argument("--scale-only", action="store_true",
@@ -499,9 +561,10 @@ def main():
         write_traffic(*args.write_traffic, last, args.profile_command)
         return
     if args.write_trace_summary:
+        kw = {"title": args.trace_title} if args.trace_title else {}
         write_trace_summary(args.write_trace_summary,
-                            os.path.join(ROOT, "profiles", "k_stream_dam256_trace.txt"), last,
-                            args.profile_command)
+                            args.trace_out or os.path.join(ROOT, "profiles", "k_stream_dam256_trace.txt"), last,
+                            args.profile_command, **kw)
         return
     if args.copy_calibration:
         copy_calibration()
@@ -537,6 +600,9 @@ def main():
         return
     if args.validate_taylor:
         print(json.dumps(validate_taylor(args.validate_taylor, [int(v) for v in args.variants.split(",")])))
+        return
+    if args.bubbles:
+        print(json.dumps(bubbles_bench(args)))
         return
     if args.validate_wave:
         print(json.dumps(validate_wave(args.validate_wave, [int(v) for v in args.variants.split(",")])))

@@ -148,8 +148,9 @@ void launch_bubbles(fslbm_ctx* c, hipStream_t s) {
     hipLaunchKernelGGL(k_bub_union<19>, grid, block, 0, s, c->d);
   else
     hipLaunchKernelGGL(k_bub_union<27>, grid, block, 0, s, c->d);
-  hipLaunchKernelGGL(k_bub_volume, grid, block, 0, s, c->d);
-  hipLaunchKernelGGL(k_bub_amount, grid, block, 0, s, c->d);
+  const dim3 walk((unsigned)((c->L.N + kBlock * kBubIters - 1) / (kBlock * kBubIters)));
+  hipLaunchKernelGGL(k_bub_volume, walk, block, 0, s, c->d);
+  hipLaunchKernelGGL(k_bub_amount, walk, block, 0, s, c->d);
   hipLaunchKernelGGL(k_bub_target, grid, block, 0, s, c->d);
   hipLaunchKernelGGL(k_bub_pressure, grid, block, 0, s, c->d);
   hipLaunchKernelGGL(k_bub_cells, grid, block, 0, s, c->d);

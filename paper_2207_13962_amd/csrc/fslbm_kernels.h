@@ -1561,15 +1561,17 @@ __device__ __forceinline__ bool bubble_cell(uint8_t f) {
 // a smaller root by compare-and-swap, and halving replaces a parent by an
 // ancestor), so every chain of reads strictly decreases and ends within N
 // hops; `bound` (N + 1) only guards the kernel's exit. While links are being
-// made, finds halve the paths they walk (non-root entries only, so the
-// compare-and-swap on roots is unaffected); afterwards they only read.
-template <bool HALVE>
+// made, finds read device-coherently and halve the paths they walk (non-root
+// entries only, so the compare-and-swap on roots is unaffected); afterwards
+// the links are final and cached reads suffice.
+template <bool LINKING>
 __device__ __forceinline__ int32_t find_root(int32_t* par, int32_t x, int64_t bound) {
+  constexpr int kScope = LINKING ? __HIP_MEMORY_SCOPE_AGENT : __HIP_MEMORY_SCOPE_WORKGROUP;
   for (int64_t i = 0; i < bound; ++i) {
-    const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED, kScope);
     if (p < 0) return -1;
     if (p == x) return x;
-    if (HALVE) {
+    if (LINKING) {
       const int32_t gp = __hip_atomic_load(&par[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (gp < 0) return -1;
       if (gp != p) __hip_atomic_store(&par[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1596,13 +1598,49 @@ __device__ __forceinline__ bool unite(int32_t* par, int32_t a, int32_t b, int64_
     if (__hip_atomic_compare_exchange_strong(&par[a], &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT))
       return true;
+    if (expected < 0 || expected >= a) return false;
     a = expected;  // a was linked meanwhile: continue from its parent
   }
   return false;
 }
 
-// Adds v at base[key] once per distinct key of the wave's active lanes.
-__device__ __forceinline__ void wave_add(double* base, int32_t key, double v, bool act) {
+// Per-wave running sums for one key at a time (all lanes hold the same
+// state): consecutive cells mostly belong to one bubble, so a wave walking a
+// stretch of cells issues one atomic per change of key, not one per cell.
+struct WaveSum {
+  int32_t key = -1;
+  double sum = 0.0;
+  __device__ __forceinline__ void flush(double* base) {
+    if (key >= 0 && (threadIdx.x & 63) == 0) atomicAdd(&base[key], sum);
+    key = -1;
+    sum = 0.0;
+  }
+  __device__ __forceinline__ void add(double* base, int32_t k, double x) {
+    if (k != key) {
+      flush(base);
+      key = k;
+    }
+    sum += x;
+  }
+};
+struct WaveMin {
+  int32_t key = -1, val = INT32_MAX;
+  __device__ __forceinline__ void flush(int32_t* base) {
+    if (key >= 0 && (threadIdx.x & 63) == 0) atomicMin(&base[key], val);
+    key = -1;
+    val = INT32_MAX;
+  }
+  __device__ __forceinline__ void add(int32_t* base, int32_t k, int32_t v) {
+    if (k != key) {
+      flush(base);
+      key = k;
+    }
+    val = min(val, v);
+  }
+};
+
+// Sum of v over the wave's active lanes of each distinct key, handed to acc.
+__device__ __forceinline__ void wave_add(WaveSum& acc, double* base, int32_t key, double v, bool act) {
   const int lane = threadIdx.x & 63;
   unsigned long long pending = __ballot(act);
   while (pending) {
@@ -1613,13 +1651,13 @@ __device__ __forceinline__ void wave_add(double* base, int32_t key, double v, bo
     double x = mine ? v : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    if (lane == leader) atomicAdd(&base[k], x);
+    acc.add(base, k, x);
     pending &= ~m;
   }
 }
 
-// Lowers base[key] to the smallest v of the wave's active lanes with that key.
-__device__ __forceinline__ void wave_min(int32_t* base, int32_t key, int32_t v, bool act) {
+// Smallest v over the wave's active lanes of each distinct key, handed to acc.
+__device__ __forceinline__ void wave_min(WaveMin& acc, int32_t* base, int32_t key, int32_t v, bool act) {
   const int lane = threadIdx.x & 63;
   unsigned long long pending = __ballot(act);
   while (pending) {
@@ -1630,15 +1668,27 @@ __device__ __forceinline__ void wave_min(int32_t* base, int32_t key, int32_t v, 
     int32_t x = mine ? v : INT32_MAX;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
-    if (lane == leader) atomicMin(&base[k], x);
+    acc.add(base, k, x);
     pending &= ~m;
   }
 }
 
+// Initial parents: within each wave's 64 consecutive cells, a bubble cell
+// points at the first cell of its run of bubble cells along x (same row), so
+// those links need no union; the runs are joined by the union pass.
 __global__ __launch_bounds__(kBlock) void k_bub_init(Dev d) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= d.g.N) return;
-  d.bpar[c] = bubble_cell(d.flags[c]) ? (int32_t)c : -1;
+  const bool in = c < d.g.N;
+  const bool bub = in && bubble_cell(d.flags[c]);
+  const int lane = threadIdx.x & 63;
+  const int x = in ? (int)(c % d.g.nx) : 0;
+  const unsigned long long bm = __ballot(bub);
+  const bool cont = bub && lane > 0 && x > 0 && ((bm >> (lane - 1)) & 1ull);
+  const unsigned long long starts = bm & ~__ballot(cont);
+  const unsigned long long upto = starts & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+  const int first = upto ? 63 - __clzll((long long)upto) : lane;  // a bubble lane always has one
+  if (!in) return;
+  d.bpar[c] = bub ? (int32_t)(c - (lane - first)) : -1;
   d.bV[c] = 0.0;
   d.bW[c] = 0.0;
   d.bR[c] = 0.0;
@@ -1653,62 +1703,97 @@ __global__ __launch_bounds__(kBlock) void k_bub_union(Dev d) {
   if (c >= d.g.N || !bubble_cell(d.flags[c])) return;
   int x, y, z;
   coords(d.g, c, x, y, z);
+  const int nx = d.g.nx;
+  const int64_t bound = d.g.N + 1;
   bool ok = true;
-  // one direction of each opposite pair: every link is seen from one end
-  for (int k = 1; k < Q; k += 2) {
+  // +x: runs inside a wave's cells are joined by the initial parents; the
+  // link across a wave boundary and across a periodic x face are made here
+  {
     int w;
-    const int64_t j = nb_index(d.g, x, y, z, cxd(k), cyd(k), czd(k), &w);
-    if (j >= 0 && j != c && bubble_cell(d.flags[j]))
-      ok &= unite(d.bpar, (int32_t)c, (int32_t)j, d.g.N + 1);
+    const int64_t j = nb_index(d.g, x, y, z, 1, 0, 0, &w);
+    if (j >= 0 && j != c && bubble_cell(d.flags[j]) && (x == nx - 1 || ((c + 1) & 63) == 0))
+      ok &= unite(d.bpar, (int32_t)c, (int32_t)j, bound);
+  }
+  // the other directions, one of each opposite pair (every link seen from
+  // one end); the link (c, j) is implied by (c - 1, j - 1) when c - 1 and
+  // j - 1 are bubble cells beside c and j in their rows (x-linked to them)
+  const bool left = x > 0 && bubble_cell(d.flags[c - 1]);
+  for (int k = 3; k < Q; k += 2) {
+    const int cx = cxd(k);
+    int w;
+    const int64_t j = nb_index(d.g, x, y, z, cx, cyd(k), czd(k), &w);
+    if (j < 0 || j == c || !bubble_cell(d.flags[j])) continue;
+    const int xj = x + cx;
+    if (left && xj >= 1 && xj <= nx - 1 && bubble_cell(d.flags[j - 1])) continue;
+    ok &= unite(d.bpar, (int32_t)c, (int32_t)j, bound);
   }
   if (!ok) atomicOr(&d.cnt[CNT_ERR], ERR_BUBBLE);
 }
 
 // Flattens the new labels; sums the new bubbles' volumes and the old
-// bubbles' still-gaseous volumes.
+// bubbles' still-gaseous volumes. Each wave walks kBubIters stretches of 64
+// cells (fewer atomics on the few addresses of large bubbles; few enough
+// stretches that the walk's dependent reads stay short).
+constexpr int kBubIters = 4;
 __global__ __launch_bounds__(kBlock) void k_bub_volume(Dev d) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool in = c < d.g.N;
-  const uint8_t f = in ? d.flags[c] : 0;
-  const bool bub = in && bubble_cell(f);
-  int32_t r = -1;
-  if (bub) {
-    r = find_root<false>(d.bpar, (int32_t)c, d.g.N + 1);
-    if (r < 0) atomicOr(&d.cnt[CNT_ERR], ERR_BUBBLE);
+  const int lane = threadIdx.x & 63;
+  const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 64 * kBubIters;
+  WaveSum aV, aW;
+  WaveMin aT;
+  for (int it = 0; it < kBubIters; ++it) {
+    const int64_t c = base + it * 64 + lane;
+    const bool in = c < d.g.N;
+    const uint8_t f = in ? d.flags[c] : 0;
+    const bool bub = in && bubble_cell(f);
+    int32_t r = -1;
+    if (bub) {
+      r = find_root<false>(d.bpar, (int32_t)c, d.g.N + 1);
+      if (r < 0) atomicOr(&d.cnt[CNT_ERR], ERR_BUBBLE);
+    }
+    const bool ok = bub && r >= 0;
+    const double w = ok ? ((f & T_MASK) == T_GAS ? 1.0 : 1.0 - d.phiB[c]) : 0.0;
+    const int32_t old = ok ? d.blab[c] : -1;
+    wave_add(aV, d.bV, r, w, ok);
+    wave_add(aW, d.bW, old, w, old >= 0);
+    wave_min(aT, d.btgt, old, r, old >= 0);
+    // a root stays its own parent and r is an ancestor of c, so other
+    // threads' finds through c still end at the same root
+    if (ok) __hip_atomic_store(&d.bpar[c], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  const bool ok = bub && r >= 0;
-  const double w = ok ? ((f & T_MASK) == T_GAS ? 1.0 : 1.0 - d.phiB[c]) : 0.0;
-  const int32_t old = ok ? d.blab[c] : -1;
-  wave_add(d.bV, r, w, ok);
-  wave_add(d.bW, old, w, old >= 0);
-  wave_min(d.btgt, old, r, old >= 0);
-  // a root stays its own parent and r is an ancestor of c, so other
-  // threads' finds through c still end at the same root
-  if (ok) __hip_atomic_store(&d.bpar[c], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  aV.flush(d.bV);
+  aW.flush(d.bW);
+  aT.flush(d.btgt);
 }
 
 // Amounts handed from old to new bubbles through the cells they share.
 __global__ __launch_bounds__(kBlock) void k_bub_amount(Dev d) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool in = c < d.g.N;
-  const uint8_t f = in ? d.flags[c] : 0;
-  const int32_t r = in && bubble_cell(f) ? d.bpar[c] : -1;
-  const int32_t old = r >= 0 ? d.blab[c] : -1;
-  double share = 0.0, w = 0.0;
-  bool act = false;
-  if (old >= 0) {
-    const double W = d.bW[old];
-    if (W > 0.0) {
-      d.bhas[r] = 1;
-      if (r != d.btgt[old]) {
-        w = (f & T_MASK) == T_GAS ? 1.0 : 1.0 - d.phiB[c];
-        share = d.bamt[old] * (w / W);
-        act = true;
+  const int lane = threadIdx.x & 63;
+  const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 64 * kBubIters;
+  WaveSum aN, aR;
+  for (int it = 0; it < kBubIters; ++it) {
+    const int64_t c = base + it * 64 + lane;
+    const bool in = c < d.g.N;
+    const uint8_t f = in ? d.flags[c] : 0;
+    const int32_t r = in && bubble_cell(f) ? d.bpar[c] : -1;
+    const int32_t old = r >= 0 ? d.blab[c] : -1;
+    double share = 0.0, w = 0.0;
+    bool act = false;
+    if (old >= 0) {
+      const double W = d.bW[old];
+      if (W > 0.0) {
+        d.bhas[r] = 1;
+        if (r != d.btgt[old]) {
+          w = (f & T_MASK) == T_GAS ? 1.0 : 1.0 - d.phiB[c];
+          share = d.bamt[old] * (w / W);
+          act = true;
+        }
       }
     }
+    wave_add(aN, d.bnn, r, share, act);
+    wave_add(aR, d.bR, old, w, act);
   }
-  wave_add(d.bnn, r, share, act);
-  wave_add(d.bR, old, w, act);
+  aN.flush(d.bnn);
+  aR.flush(d.bR);
 }
 
 // Each old bubble's target receives the rest of its amount.

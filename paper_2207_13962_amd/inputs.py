@@ -326,7 +326,7 @@ def bubble_pair(kind="apart", q=19, storage=F64, variant=OM, periodic_x=False, g
 
 
 def bubbly_column(nx=48, ny=40, nz=56, n_bubbles=14, radius=(2.5, 6.0), fill=0.75, g=1e-4, seed=7, q=19,
-                  storage=F64, variant=OM, bubble_model=2, steps=0) -> Setup:
+                  storage=F64, variant=OM, bubble_model=2, steps=0, sub=4) -> Setup:
     """Closed box (no-slip walls) filled with liquid up to fill * nz, gas
     above, and n_bubbles spherical gas bubbles of random radius (seeded) in
     the liquid, some overlapping; gravity -z, D3Q19 SRT, tracked-bubble model
@@ -348,7 +348,7 @@ def bubbly_column(nx=48, ny=40, nz=56, n_bubbles=14, radius=(2.5, 6.0), fill=0.7
             liq &= (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 > r * r
         return liq
 
-    phi = supersampled_fill(nx, ny, nz, inside, sub=4)
+    phi = supersampled_fill(nx, ny, nz, inside, sub=sub)
     rho = hydrostatic_rho(p, h, 2, g)
     return _finish(p, phi, rho, "bubbly_column", steps, meta=dict(g=g, fill=fill, bubbles=centres))
 
