@@ -12,7 +12,9 @@
  * marked "parity unpinned" (the forced fill/empty flux table, the near-obstacle
  * normal substitution, the reinitialisation averages, the lost-mass fallback,
  * the K8/curvature details and the free-slip edge rules), whose exact form the
- * paper delegates to cited works.
+ * paper delegates to cited works. The tracked-bubble rules (also delegated)
+ * are pinned by invariants: connected components, Boyle's law per bubble,
+ * amounts added on coalescence, pressure kept on segmentation.
  */
 #include "fslbm_oracle.h"
 
