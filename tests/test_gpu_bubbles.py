@@ -80,3 +80,24 @@ def test_one_bubble_is_the_single_bubble_model_on_gpu():
     f1, f2 = g1.fields(), g2.fields()
     assert np.array_equal(f1["type"], f2["type"])
     np.testing.assert_allclose(f2["pdf"], f1["pdf"], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", ["taylor", "column"])
+def test_tracked_bubbles_with_surface_tension(case):
+    # the curvature pass adds the Laplace term to each interface cell's own
+    # bubble pressure: D3Q27 TRT rising bubble in a tube of obstacle cells,
+    # and the box of rising bubbles, both with sigma = 1e-3
+    if case == "taylor":
+        s = I.taylor_bubble(nx=24, ny=24, nz=64, tube_radius=10.5, bubble_radius=6.0, z0=16.0, length=16.0,
+                            g=1e-5, nu=0.01, sigma=1e-3, storage=I.F64, variant=I.OM)
+        s.params = s.params.with_(bubble_model=2)
+    else:
+        s = I.bubbly_column(variant=I.NBKC)
+        s.params = s.params.with_(sigma=1e-3)
+    g, o = _pair(s)
+    _same_bubbles(g, o, "init")
+    for k in range(2):
+        g.step(25)
+        assert o.step(25) == 0
+        _same_bubbles(g, o, "step %d" % (25 * (k + 1)))
+        compare_state(g, o, what="%s sigma step %d" % (case, 25 * (k + 1)))
