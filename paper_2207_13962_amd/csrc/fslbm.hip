@@ -140,14 +140,15 @@ void launch_volume(fslbm_ctx* c, hipStream_t s, bool set_reference) {
 }
 
 // Tracked bubbles from the types and fill levels at t+1 (flags, phiB): new
-// labels, volumes, amounts handed over, pressures, gas densities.
-void launch_bubbles(fslbm_ctx* c, hipStream_t s) {
+// labels, volumes, amounts handed over, pressures, gas densities. The
+// labelling passes skip a step without marks unless `force` (creation).
+void launch_bubbles(fslbm_ctx* c, hipStream_t s, bool force) {
   const dim3 grid(grid_for(c->L.N)), block(kBlock);
-  hipLaunchKernelGGL(k_bub_init, grid, block, 0, s, c->d);
+  hipLaunchKernelGGL(k_bub_init, grid, block, 0, s, c->d, force ? 1 : 0);
   if (c->p.q == 19)
-    hipLaunchKernelGGL(k_bub_union<19>, grid, block, 0, s, c->d);
+    hipLaunchKernelGGL(k_bub_union<19>, grid, block, 0, s, c->d, force ? 1 : 0);
   else
-    hipLaunchKernelGGL(k_bub_union<27>, grid, block, 0, s, c->d);
+    hipLaunchKernelGGL(k_bub_union<27>, grid, block, 0, s, c->d, force ? 1 : 0);
   const dim3 walk((unsigned)((c->L.N + kBlock * kBubIters - 1) / (kBlock * kBubIters)));
   hipLaunchKernelGGL(k_bub_volume, walk, block, 0, s, c->d);
   hipLaunchKernelGGL(k_bub_amount, walk, block, 0, s, c->d);
@@ -171,7 +172,7 @@ void enqueue_plain(fslbm_ctx* c, int64_t n) {
     ops.step(c, s);
     ops.convert(c, s, 0);
     if (c->p.bubble_model == 1) launch_volume(c, s, false);
-    if (c->p.bubble_model == 2) launch_bubbles(c, s);
+    if (c->p.bubble_model == 2) launch_bubbles(c, s, false);
     std::swap(c->d.fA, c->d.fB);
     std::swap(c->d.phiA, c->d.phiB);
     c->step += 1;
@@ -358,7 +359,7 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   if (c->p.bubble_model == 2) {
     // no old bubbles: every bubble starts at p^V(0)
     INITCHK(hipMemsetAsync(c->d.blab, 0xff, 4 * N, s));
-    launch_bubbles(c, s);
+    launch_bubbles(c, s, true);
   }
   INITCHK(hipGetLastError());
   INITCHK(hipStreamSynchronize(s));

@@ -1673,11 +1673,29 @@ __device__ __forceinline__ void wave_min(WaveMin& acc, int32_t* base, int32_t ke
   }
 }
 
+// Whether the bubbles must be found again: a step without marks changed no
+// cell type, so its bubbles are the previous ones (labels already roots).
+__device__ __forceinline__ bool bub_relabel(const Dev& d, int force) {
+  return force || d.cnt[CNT_MARK0 + (d.step & 1)] != 0;
+}
+
 // Initial parents: within each wave's 64 consecutive cells, a bubble cell
 // points at the first cell of its run of bubble cells along x (same row), so
-// those links need no union; the runs are joined by the union pass.
-__global__ __launch_bounds__(kBlock) void k_bub_init(Dev d) {
+// those links need no union; the runs are joined by the union pass. Without
+// a relabelling the parents are the current labels.
+__global__ __launch_bounds__(kBlock) void k_bub_init(Dev d, int force) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (!bub_relabel(d, force)) {
+    if (c >= d.g.N) return;
+    d.bpar[c] = d.blab[c];
+    d.bV[c] = 0.0;
+    d.bW[c] = 0.0;
+    d.bR[c] = 0.0;
+    d.bnn[c] = 0.0;
+    d.bhas[c] = 0;
+    d.btgt[c] = INT32_MAX;
+    return;
+  }
   const bool in = c < d.g.N;
   const bool bub = in && bubble_cell(d.flags[c]);
   const int lane = threadIdx.x & 63;
@@ -1698,7 +1716,8 @@ __global__ __launch_bounds__(kBlock) void k_bub_init(Dev d) {
 }
 
 template <int Q>
-__global__ __launch_bounds__(kBlock) void k_bub_union(Dev d) {
+__global__ __launch_bounds__(kBlock) void k_bub_union(Dev d, int force) {
+  if (!bub_relabel(d, force)) return;
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (c >= d.g.N || !bubble_cell(d.flags[c])) return;
   int x, y, z;

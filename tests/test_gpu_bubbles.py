@@ -51,6 +51,22 @@ def test_bubble_events_match_oracle(q, kind, periodic, count):
     compare_state(g, o, what="%s q%d step 30" % (kind, q))
 
 
+def test_bubbles_at_rest_keep_their_labels():
+    # a flat interface at rest marks no cell in any step: the labelling
+    # passes are skipped and the bubble (the gas above) carried over
+    s = I.flat_interface_rest(nx=16, ny=12, nz=8)
+    s.params = s.params.with_(bubble_model=2)
+    g, o = _pair(s)
+    lab0, v0, p0 = g.bubbles()
+    g.step(30)
+    assert o.step(30) == 0
+    lab, v, p = g.bubbles()
+    assert list(lab) == list(lab0)
+    np.testing.assert_allclose(p * v, p0 * v0, rtol=1e-14)
+    _same_bubbles(g, o, "step 30")
+    compare_state(g, o, what="flat rest step 30")
+
+
 @pytest.mark.parametrize("variant", [I.NBRC, I.OM])
 def test_bubbly_column_matches_oracle(variant):
     # 48 x 40 x 56 cells (420 blocks per pass), six bubbles including the gas
