@@ -407,17 +407,22 @@ __device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk) {
     // the batch
     const R fo = act ? St::ld(A, k * stride + c, k) : R(0);
     const R fpull = act ? St::ld(A, k * stride + js, k) : R(0);
-    const uint8_t fld = d.flags[js];
     const uint8_t flb = d.flags[jbs];
-    const double phid = d.phiA[js];
     const double phib = d.phiA[jbs];
-    const uint8_t clsd = d.cls[js];
-    const uint8_t cls_c = d.cls[c];
-    const double phi_c = d.phiA[c];
+    const uint8_t clsb = d.cls[jbs];
+    // the cell itself is the box centre (lane 13)
+    const uint8_t cls_c = (uint8_t)__shfl((int)clsb, 13, kG);
+    const double phi_c = __shfl(phib, 13, kG);
     const double m_c = d.m[c];
     const double rhoG_c = d.rhoG ? d.rhoG[c] : d.pV[0] * 3.0;
     // own post-collision population of the opposite direction
     const R fo_b = __shfl(fo, kb, kG);
+    // the pull source x - c_k is the box point of offset -c_k (same index,
+    // wrap and ghost), so its flag, fill level and class come from that lane
+    const int lb = (1 - cx) + 3 * (1 - cy) + 9 * (1 - cz);
+    const uint8_t fld = (uint8_t)__shfl((int)flb, lb, kG);
+    const double phid = __shfl(phib, lb, kG);
+    const uint8_t clsd = (uint8_t)__shfl((int)clsb, lb, kG);
     // kind of the pull source (Sec. 2.1 walls, Sec. 2.2 gas)
     const int st = jd >= 0 ? (fld & T_MASK) : wd;
     const bool wall = is_obst(st);
