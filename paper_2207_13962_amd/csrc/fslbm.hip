@@ -513,9 +513,12 @@ int fslbm_set_timing(fslbm_ctx* c, int64_t capacity) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   release_events(c);
   c->ev.reserve((size_t)(2 * capacity));
+  // timing only: no system-scope fence when an event completes (its cache
+  // write-back and invalidation would slow the launches being timed; the
+  // stream synchronisation before the times are read orders them)
   for (int64_t i = 0; i < 2 * capacity; ++i) {
     hipEvent_t e;
-    HIPCHK(c, hipEventCreate(&e));
+    HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     c->ev.push_back(e);
   }
   return FSLBM_OK;
