@@ -1749,6 +1749,9 @@ __global__ __launch_bounds__(kBlock) void k_bub_union(Dev d, int force) {
     if (j < 0 || j == c || !bubble_cell(d.flags[j])) continue;
     const int xj = x + cx;
     if (left && xj >= 1 && xj <= nx - 1 && bubble_cell(d.flags[j - 1])) continue;
+    // already joined as far as cached reads show (they see ancestors only)
+    if (find_root<false>(d.bpar, (int32_t)c, bound) == find_root<false>(d.bpar, (int32_t)j, bound))
+      continue;
     ok &= unite(d.bpar, (int32_t)c, (int32_t)j, bound);
   }
   if (!ok) atomicOr(&d.cnt[CNT_ERR], ERR_BUBBLE);
