@@ -42,8 +42,13 @@ def test_workspace_bytes_and_validation():
     assert n > 2 * 19 * p.n * 4
     assert fs.workspace_bytes(p.with_(storage=I.F64)) > n
     assert fs.workspace_bytes(p.with_(storage=I.F16S)) < n
+    # tracked bubbles: label, parent and target (int32), seven FP64 fields
+    # and a flag byte per cell more (the gas-density field included)
+    assert fs.workspace_bytes(p.with_(bubble_model=2)) - n >= 69 * p.n
+    assert fs.workspace_bytes(p.with_(bubble_model=1)) == n
     bad = [p.with_(q=15), p.with_(tau=0.5), p.with_(variant=7), p.with_(nx=0),
-           p.with_(storage=9), p.with_(boundary=(0, 1, 1, 1, 1, 1))]
+           p.with_(storage=9), p.with_(boundary=(0, 1, 1, 1, 1, 1)), p.with_(bubble_model=3),
+           p.with_(bubble_model=-1)]
     for b in bad:
         with pytest.raises(fs.FslbmError) as e:
             fs.workspace_bytes(b)
