@@ -1,0 +1,57 @@
+"""The paper-scale validation setups and reducers (CPU): the Taylor bubble's
+g and sigma reproduce the paper's Morton and Bond numbers (Sec. 4.4), the
+gravity wave's frequency and Reynolds number follow from its g (Sec. 4.1,
+dispersion relation), and the analytic elevation the runs are compared with
+starts at 1 and decays as the paper states."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2207_13962_amd import inputs as I
+from paper_2207_13962_amd.validation import wave_errors, wave_model
+
+
+@pytest.mark.parametrize("D", [32, 64, 128])
+def test_taylor_setup_morton_and_bond(D):
+    p = I.taylor_bubble_paper(D).params if D < 128 else None
+    if p is None:  # the 21 M-cell setup is not built here; same formulas
+        tau = 1.0 / 1.8
+        nu = (tau - 0.5) / 3.0
+        g = nu * nu * 1000.0 / (math.sqrt(0.015) * D ** 3)
+        sigma = g * D * D / 100.0
+    else:
+        nu = (p.tau - 0.5) / 3.0
+        g, sigma = -p.gravity[2], p.sigma
+        assert (p.nx, p.ny, p.nz) == (D, D, 10 * D) and p.q == 19 and p.collision == I.SRT
+        assert p.tau == pytest.approx(1.0 / 1.8)
+    mu = nu  # liquid density 1
+    assert g * mu ** 4 / sigma ** 3 == pytest.approx(0.015, rel=1e-12)
+    assert g * D * D / sigma == pytest.approx(100.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("L", [200, 400])
+def test_gravity_wave_setup(L):
+    s = I.gravity_wave_paper(L)
+    p, m = s.params, s.meta
+    g = -p.gravity[1]
+    k = 2 * math.pi / L
+    omega0 = math.sqrt(g * k * math.tanh(k * L / 2))
+    assert omega0 == pytest.approx(m["omega0"], rel=1e-12)
+    nu = (p.tau - 0.5) / 3.0
+    assert 0.01 * L * omega0 * L / nu == pytest.approx(10.0, rel=1e-12)  # Re
+    assert (p.nx, p.ny, p.nz) == (L, L, 1) and m["depth"] == L / 2 and m["amp"] == 0.01 * L
+
+
+def test_wave_model_and_errors():
+    nu, k, omega0 = 0.0185, 2 * math.pi / 200, 4.6e-4
+    t = np.linspace(0.0, 12.0, 241)
+    a = wave_model(t, nu, k, omega0)
+    assert a[0] == 1.0
+    # zero crossings at t* = pi/2 + n pi, envelope exp(-2 nu k^2 t* / omega0)
+    assert abs(wave_model(math.pi / 2, nu, k, omega0)) < 1e-15
+    env = math.exp(-2 * nu * k * k * (2 * math.pi) / omega0)
+    assert wave_model(2 * math.pi, nu, k, omega0) == pytest.approx(env, rel=1e-12)
+    r = dict(t_star=t, a_sim=a + 0.1 * (t > 6.0), a_model=a)
+    e = wave_errors(r, windows=(6.0, 12.0))
+    assert e["max_abs_err_t6"] == 0.0 and e["max_abs_err_t12"] == pytest.approx(0.1)
