@@ -1749,6 +1749,16 @@ __global__ __launch_bounds__(kBlock) void k_bub_union(Dev d, int force) {
     if (j < 0 || j == c || !bubble_cell(d.flags[j])) continue;
     const int xj = x + cx;
     if (left && xj >= 1 && xj <= nx - 1 && bubble_cell(d.flags[j - 1])) continue;
+    // an edge-diagonal link c + a + b (a, b two face steps) is implied by the
+    // face links through c + a or c + b when either is a bubble cell
+    const int cy = cyd(k), cz = czd(k);
+    if ((cx != 0) + (cy != 0) + (cz != 0) == 2) {
+      const int ax = cx != 0 ? cx : 0, ay = cx != 0 ? 0 : cy, az = cx != 0 || cy != 0 ? 0 : cz;
+      int w1, w2;
+      const int64_t m1 = nb_index(d.g, x, y, z, ax, ay, az, &w1);
+      const int64_t m2 = nb_index(d.g, x, y, z, cx - ax, cy - ay, cz - az, &w2);
+      if ((m1 >= 0 && bubble_cell(d.flags[m1])) || (m2 >= 0 && bubble_cell(d.flags[m2]))) continue;
+    }
     // already joined as far as cached reads show (they see ancestors only)
     if (find_root<false>(d.bpar, (int32_t)c, bound) == find_root<false>(d.bpar, (int32_t)j, bound))
       continue;
