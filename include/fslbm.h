@@ -229,8 +229,11 @@ int fslbm_server_submit(fslbm_server* srv, const fslbm_params* p, const uint8_t*
 /* Runs up to `ticks` batched steps (a tick advances every resident run by one
  * step), retiring finished runs and admitting queued ones between ticks as
  * slots and pool memory free up; returns early when nothing is resident or
- * queued. Waits for the device only where a run finishes. Errors:
- * FSLBM_EDEVICE (the server is unusable afterwards). */
+ * queued. Waits for the device only where a run finishes. Launch groups
+ * (runs sharing storage, lattice, collision and addressing) run side by side
+ * on streams the server owns, ordered after and before the server's stream
+ * by events, so work the caller queues on that stream still follows the
+ * ticks. Errors: FSLBM_EDEVICE (the server is unusable afterwards). */
 int fslbm_server_advance(fslbm_server* srv, int64_t ticks);
 
 /* Ids and statuses (FSLBM_OK, or FSLBM_EUNSTABLE for a run that became
