@@ -7,18 +7,32 @@
  * Build with -O2 -ffp-contract=off and without fast-math so that each
  * operation is one correctly rounded IEEE-754 binary64 operation.
  *
+ * Threads: loops in which every iteration writes only its own cell are
+ * spread over OpenMP threads (the iterations are independent, so the result
+ * is bitwise the same for any thread count); every sum over cells (lost
+ * mass, bubble volumes and amounts, mass reports) stays a serial loop in
+ * index order.
+ *
  * Parity status: every function below is pinned by a CPU test against a
- * closed form, an invariant or a brute-force enumeration, except the readings
- * marked "parity unpinned" (the forced fill/empty flux table, the near-obstacle
- * normal substitution, the reinitialisation averages, the lost-mass fallback,
- * the K8/curvature details and the free-slip edge rules), whose exact form the
- * paper delegates to cited works. The tracked-bubble rules (also delegated)
- * are pinned by invariants: connected components, Boyle's law per bubble,
- * amounts added on coalescence, pressure kept on segmentation.
+ * closed form, an invariant or a brute-force enumeration. The readings of
+ * what the paper delegates to cited work (the forced fill/empty flux table,
+ * the near-obstacle normal, the reinitialisation averages, the lost-mass
+ * fallback, the K8 smoothing next to obstacles, the free-slip edge rules)
+ * are pinned by consequences of their stated intent: a cell that should
+ * empty only gives mass, one that should fill only receives; a new cell
+ * carries the equilibrium of the mean of exactly its allowed neighbours after
+ * streaming; unplaceable excess mass is booked exactly; a flat surface keeps
+ * its normal and zero curvature up to walls; free-slip faces and edges keep
+ * the tangential momentum. The exact tables of the cited works are not
+ * available, so another reading consistent with the same intent would not be
+ * told apart. The tracked-bubble rules (also delegated) are pinned by
+ * invariants: connected components, Boyle's law per bubble, amounts added on
+ * coalescence, pressure kept on segmentation.
  */
 #include "fslbm_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -101,6 +115,7 @@ struct orc_sim {
   long* bqueue;
   int64_t step;
   int status;
+  int threads; /* OpenMP threads of the per-cell loops */
 };
 
 enum { MARK_NONE = 0, MARK_L = 1, MARK_G = 2 };
@@ -292,7 +307,8 @@ void orc_reconstruct_set(int q, int variant, const double n[3], uint32_t gas_src
  * n_a = sum_{b,c in -1..1} W_b W_c [phi(x + e_a + b e_a' + c e_a'') -
  * phi(x - e_a + b e_a' + c e_a'')] with W_0 = 2, W_+-1 = 1.
  * Near obstacles the stencil must not read obstacle cells: an obstacle point
- * takes the fill level of the centre cell (parity unpinned reading). */
+ * takes the fill level of the centre cell (a reading; pinned by a flat surface
+ * meeting walls keeping its normal exactly along them). */
 static void normal_of(const orc_sim* s, const double* fld, int x, int y, int z, double n[3]) {
   static const double W[3] = {1.0, 2.0, 1.0};
   long i0 = x + (long)s->p.nx * (y + (long)s->p.ny * z);
@@ -326,7 +342,8 @@ void orc_normal(const orc_sim* s, int x, int y, int z, double n[3]) {
 /* Smoothing of the fill level with the K8 kernel K(r) = (1 - r^2/h^2)^4,
  * support radius h = 2 (Sec. 2.2); with unit spacing only offsets with
  * r^2 < 4, i.e. the 3x3x3 box, carry weight. Obstacle cells are left out and
- * the weights renormalised over the rest (parity unpinned reading). */
+ * the weights renormalised over the rest (a reading; pinned by a flat surface
+ * keeping zero curvature next to walls). */
 static double smooth_phi(const orc_sim* s, int x, int y, int z) {
   double num = 0.0, den = 0.0;
   for (int dz = -1; dz <= 1; ++dz)
@@ -393,6 +410,7 @@ static double curvature_at(const orc_sim* s, int x, int y, int z) {
 }
 
 static void update_smoothed(orc_sim* s) {
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < s->N; ++c) {
     int x, y, z;
     coords(s, c, &x, &y, &z);
@@ -408,7 +426,7 @@ double orc_curvature(const orc_sim* s, int x, int y, int z) {
 }
 
 /* Flux classes for the forced fill/empty rule (Sec. 2.2 cites Thuerey for it;
- * parity unpinned reading): an interface cell with no liquid neighbour should
+ * a reading, pinned by the direction of the mass it moves): an interface cell with no liquid neighbour should
  * empty (NOLIQ), one with no gas neighbour should fill (NOGAS); one with both
  * or neither is standard. */
 static int flux_class(const orc_sim* s, int x, int y, int z) {
@@ -617,6 +635,9 @@ int orc_create(const orc_params* p, const uint8_t* type, const double* phi, cons
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   if (!s) return ORC_ENOMEM;
   s->p = *p;
+  /* small domains run on one thread: the fork/join of a loop costs more
+   * than the loop (the result does not depend on the count) */
+  s->threads = (long)p->nx * p->ny * p->nz < 65536 ? 1 : omp_get_max_threads();
   if (s->p.tie_delta <= 0.0) s->p.tie_delta = 1e-9;
   s->q = p->q;
   s->N = (long)p->nx * p->ny * p->nz;
@@ -726,8 +747,9 @@ int orc_set_variant(orc_sim* s, int variant) {
 static void collide_all(orc_sim* s, const double* f, double* fs, double* ut) {
   long N = s->N;
   int q = s->q;
-  double fl[27], fo[27], u[3];
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
+    double fl[27], fo[27], u[3];
     if (!is_fluid(s->type[c])) {
       for (int i = 0; i < q; ++i) fs[i * N + c] = 0.0;
       continue;
@@ -752,7 +774,8 @@ static void collide_all(orc_sim* s, const double* f, double* fs, double* ut) {
  * population comes from y = x - c_i shifted back across those axes, travelling
  * with c_j = c_i mirrored in them. No such axis, or an obstacle at y, falls back
  * to bounce-back; gas at y takes the free-surface condition (Sec. 2.2). The
- * edge/corner rules are a reading (parity unpinned).
+ * edge/corner rules are a reading (pinned by tangential momentum conservation
+ * along free-slip faces and edges).
  * Returns SRC_FLUID (with *src, *dir), SRC_GAS or SRC_BOUNCE; *via_wall tells
  * whether the direct source x - c_i is an obstacle. */
 enum { SRC_FLUID = 0, SRC_GAS = 1, SRC_BOUNCE = 2 };
@@ -808,6 +831,7 @@ static int step_once(orc_sim* s) {
 
   /* S3 (gas density) and flux classes, from types and fill levels at t */
   if (s->p.sigma != 0.0) update_smoothed(s);
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
     if (s->type[c] != ORC_INTERFACE) continue;
     int x, y, z;
@@ -819,6 +843,8 @@ static int step_once(orc_sim* s) {
   }
 
   /* S2 + S4 */
+  int broken = 0; /* a liquid cell next to gas: the interface layer is broken */
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
     int t = s->type[c];
     if (!is_fluid(t)) {
@@ -854,7 +880,10 @@ static int step_once(orc_sim* s) {
       } else if (kind == SRC_GAS || (R[i] && !wall)) {
         /* missing population, or one the variant overwrites; populations
          * coming off a wall are never overwritten */
-        if (t != ORC_INTERFACE) return ORC_EINVAL; /* liquid next to gas: layer broken */
+        if (t != ORC_INTERFACE) {
+#pragma omp atomic write
+          broken = 1;
+        }
         v = orc_bc_value(q, i, rg, u, s->fs[ib * N + c]);
       } else {
         v = s->fs[dir * N + j];
@@ -862,6 +891,7 @@ static int step_once(orc_sim* s) {
       s->fn[i * N + c] = v;
     }
   }
+  if (broken) return ORC_EINVAL;
 
   /* S5: mass exchange, Sec. 2.2 mass-flux equation, written per arriving
    * direction k: the cell receives f*_k of the cell the population streams from
@@ -871,6 +901,7 @@ static int step_once(orc_sim* s) {
    * the exchanged mass is exactly the exchanged populations. Operands are the
    * post-collision populations at t, types and fill levels at t; gas and
    * obstacle partners exchange nothing. */
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
     if (s->type[c] != ORC_INTERFACE) continue;
     int x, y, z;
@@ -893,6 +924,7 @@ static int step_once(orc_sim* s) {
   }
 
   /* S6 + S7 */
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
     s->mark[c] = MARK_NONE;
     s->conv[c] = CONV_NONE;
@@ -927,6 +959,7 @@ static int step_once(orc_sim* s) {
   }
 
   /* S9: new types (liquid and gas never convert into one another directly) */
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
     int t = s->type[c];
     s->ntype[c] = (uint8_t)t;
@@ -956,7 +989,9 @@ static int step_once(orc_sim* s) {
 
   /* S10: populations of new interface cells from gas: equilibrium with the
    * arithmetic mean density and velocity of the liquid and non-new interface
-   * neighbours (velocity with the half-force shift, as in Sec. 2.1). */
+   * neighbours (velocity with the half-force shift, as in Sec. 2.1). Only
+   * cells that are not new from gas are read, only such cells are written. */
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
     if (s->conv[c] != CONV_NEW_FROM_GAS) continue;
     int x, y, z;
@@ -985,6 +1020,7 @@ static int step_once(orc_sim* s) {
     s->rhon[c] = rbar;
     s->m[c] = 0.0;
   }
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c)
     if (s->conv[c] == CONV_NEW_FROM_LIQ) s->m[c] = s->rhon[c];
 
@@ -1009,6 +1045,7 @@ static int step_once(orc_sim* s) {
       s->share[c] = mex / nif;
     }
   }
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
     if (s->ntype[c] != ORC_INTERFACE) continue;
     int x, y, z;
@@ -1022,6 +1059,7 @@ static int step_once(orc_sim* s) {
   }
 
   /* S12: fill levels and the new state */
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
     int nt = s->ntype[c];
     s->type[c] = (uint8_t)nt;
@@ -1048,15 +1086,20 @@ static int step_once(orc_sim* s) {
 
   /* S14: instability (the paper observed blow-ups once the flow exceeded the
    * lattice speed of sound) */
+  int unstable = 0;
+#pragma omp parallel for num_threads(s->threads) schedule(static)
   for (long c = 0; c < N; ++c) {
     if (!is_fluid(s->type[c])) continue;
     double r, u[3];
     moments(q, &s->f[c], N, g, &r, u);
     double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     if (!(r > 0.0) || !isfinite(r) || !isfinite(usq) || !(usq < 1.0 / 3.0) ||
-        (s->type[c] == ORC_INTERFACE && !isfinite(s->m[c])))
-      return ORC_EUNSTABLE;
+        (s->type[c] == ORC_INTERFACE && !isfinite(s->m[c]))) {
+#pragma omp atomic write
+      unstable = 1;
+    }
   }
+  if (unstable) return ORC_EUNSTABLE;
   s->step += 1;
   return ORC_OK;
 }
@@ -1094,6 +1137,47 @@ void orc_fields(const orc_sim* s, uint8_t* type, double* phi, double* rho, doubl
 
 void orc_post_collision(const orc_sim* s, double* pdf_star) {
   collide_all((orc_sim*)s, s->f, pdf_star, NULL);
+}
+
+int orc_set_threads(orc_sim* s, int threads) {
+  if (threads < 1) return ORC_EINVAL;
+  s->threads = threads;
+  return ORC_OK;
+}
+
+void orc_export_state(const orc_sim* s, uint8_t* type, double* pdf, double* mass, double* phi,
+                      double scalars[4]) {
+  long N = s->N;
+  if (type) memcpy(type, s->type, (size_t)N);
+  if (pdf) memcpy(pdf, s->f, sizeof(double) * (size_t)s->q * (size_t)N);
+  if (mass) memcpy(mass, s->m, sizeof(double) * (size_t)N);
+  if (phi) memcpy(phi, s->phi, sizeof(double) * (size_t)N);
+  if (scalars) {
+    scalars[0] = s->m_lost;
+    scalars[1] = s->pV;
+    scalars[2] = s->pV0;
+    scalars[3] = s->V0;
+  }
+}
+
+int orc_import_state(orc_sim* s, const uint8_t* type, const double* pdf, const double* mass,
+                     const double* phi, const double scalars[4], int64_t step) {
+  long N = s->N;
+  for (long c = 0; c < N; ++c)
+    if (type[c] > ORC_FREESLIP) return ORC_EINVAL;
+  memcpy(s->type, type, (size_t)N);
+  memcpy(s->f, pdf, sizeof(double) * (size_t)s->q * (size_t)N);
+  memcpy(s->m, mass, sizeof(double) * (size_t)N);
+  memcpy(s->phi, phi, sizeof(double) * (size_t)N);
+  s->m_lost = scalars[0];
+  s->pV = scalars[1];
+  s->pV0 = scalars[2];
+  s->V0 = scalars[3];
+  s->step = step;
+  s->status = ORC_OK;
+  /* tracked bubbles restart from the imported types: every bubble at p^V(0) */
+  if (s->p.bubble_model == 2) update_bubbles(s, 1);
+  return ORC_OK;
 }
 
 void orc_mass(const orc_sim* s, orc_report* r) {

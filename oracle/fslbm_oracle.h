@@ -86,6 +86,23 @@ void orc_mass(const orc_sim* s, orc_report* r);
  * `cap` of them. Returns the number of bubbles (0 for other models). */
 int64_t orc_bubbles(const orc_sim* s, int64_t* label, double* volume, double* pressure, int64_t cap);
 
+/* Threads of the per-cell loops (default: one below 65536 cells, OpenMP's
+ * maximum above). The result is
+ * bitwise the same for every thread count. */
+int orc_set_threads(orc_sim* s, int threads);
+
+/* The state between steps, copied verbatim (no arithmetic): cell types,
+ * pre-collision populations (q*N), the mass array (interface cells: m; other
+ * cells hold 0), fill levels of every cell, and the scalars
+ * {lost mass, p^V, p^V(0), V(0)}. Any pointer may be NULL. */
+void orc_export_state(const orc_sim* s, uint8_t* type, double* pdf, double* mass, double* phi,
+                      double scalars[4]);
+/* Replaces the state by one of the same shape, verbatim; the next step is
+ * number `step`. Tracked bubbles (bubble_model 2) are labelled afresh from the
+ * imported types, every bubble starting at p^V(0). */
+int orc_import_state(orc_sim* s, const uint8_t* type, const double* pdf, const double* mass,
+                     const double* phi, const double scalars[4], int64_t step);
+
 /* Isolated routines exposed for the pins. */
 /* Equilibrium of the given lattice (q = 19/27); feq has q entries. */
 void orc_equilibrium(int q, double rho, const double u[3], double* feq);

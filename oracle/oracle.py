@@ -11,7 +11,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fslbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_fslbm.so")
-GCC_FLAGS = ["-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall"]
+GCC_FLAGS = ["-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-Wall"]
 
 
 def build_oracle(force: bool = False) -> str:
@@ -90,6 +90,11 @@ def _L():
         lib.orc_curvature.restype = C.c_double
         lib.orc_thurey_class.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
         lib.orc_thurey_class.restype = C.c_int
+        lib.orc_set_threads.argtypes = [C.c_void_p, C.c_int]
+        lib.orc_set_threads.restype = C.c_int
+        lib.orc_export_state.argtypes = [C.c_void_p, u8, dp, dp, dp, dp]
+        lib.orc_import_state.argtypes = [C.c_void_p, u8, dp, dp, dp, dp, C.c_int64]
+        lib.orc_import_state.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -200,6 +205,36 @@ class Oracle:
         _L().orc_fields(self._h, _u8(t), _dp(phi), _dp(rho), _dp(ux), _dp(uy), _dp(uz), _dp(m),
                         _dp(pdf))
         return dict(type=t, phi=phi, rho=rho, ux=ux, uy=uy, uz=uz, mass=m, pdf=pdf.reshape(q, n))
+
+    def set_threads(self, n):
+        """OpenMP threads of the per-cell loops (results are bitwise the same
+        for any count)."""
+        if _L().orc_set_threads(self._h, int(n)) != 0:
+            raise ValueError("threads must be >= 1")
+
+    def export_state(self):
+        """The state between steps, verbatim: types, pre-collision populations
+        (q, N), raw mass array (interface m, 0 elsewhere), fill levels and the
+        scalars (lost mass, p^V, p^V(0), V(0))."""
+        n, q = self.n, self.q
+        t = np.zeros(n, dtype=np.uint8)
+        pdf, m, phi, sc = np.zeros(q * n), np.zeros(n), np.zeros(n), np.zeros(4)
+        _L().orc_export_state(self._h, _u8(t), _dp(pdf), _dp(m), _dp(phi), _dp(sc))
+        return dict(type=t, pdf=pdf.reshape(q, n), mass=m, phi=phi,
+                    lost_mass=sc[0], p_volume=sc[1], p_volume0=sc[2], volume0=sc[3])
+
+    def import_state(self, st, step=0):
+        """Replaces the state verbatim by one exported from an oracle run of
+        the same shape (see export_state)."""
+        t = np.ascontiguousarray(st["type"], dtype=np.uint8)
+        pdf = np.ascontiguousarray(st["pdf"], dtype=np.float64).reshape(-1)
+        m = np.ascontiguousarray(st["mass"], dtype=np.float64)
+        phi = np.ascontiguousarray(st["phi"], dtype=np.float64)
+        sc = np.array([st["lost_mass"], st["p_volume"], st["p_volume0"], st["volume0"]], dtype=np.float64)
+        if t.size != self.n or pdf.size != self.q * self.n or m.size != self.n or phi.size != self.n:
+            raise ValueError("state of another shape")
+        if _L().orc_import_state(self._h, _u8(t), _dp(pdf), _dp(m), _dp(phi), _dp(sc), int(step)) != 0:
+            raise ValueError("orc_import_state failed")
 
     def post_collision(self):
         out = np.zeros(self.q * self.n)
