@@ -361,24 +361,175 @@ def host_cpu_model():
     return None
 
 
-def cpu_baseline(setup_fn, steps):
+def host_threads():
+    """Threads for the host leg: OMP_NUM_THREADS when set (the share of the
+    host this process is meant to use), else the CPU affinity."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(setup_fn, steps, threads):
     """FP64 oracle on the host: fluid+interface updates per second over `steps`
-    steps of the same workload (single thread)."""
+    steps of the same workload on `threads` OpenMP threads (the oracle's
+    per-cell loops; results do not depend on the count). Only the steps are
+    timed; the cell counts come from mass reports taken between them."""
     from oracle import Oracle
     s = setup_fn()
-    p = s.params
-    s.params = p.with_(storage=0)
+    s.params = s.params.with_(storage=0)
     o = Oracle(s)
-    upd = 0
-    t0 = time.perf_counter()
+    o.set_threads(threads)
+    upd, dt, done = 0, 0.0, 0
     for _ in range(steps):
         r = o.mass()
-        upd += r.n_liquid + r.n_interface
+        t0 = time.perf_counter()
         st = o.step(1)
+        dt += time.perf_counter() - t0
         if st != 0:
             break
-    dt = time.perf_counter() - t0
-    return upd / dt / 1e6, dt
+        a = o.mass()
+        upd += 0.5 * (r.n_liquid + r.n_interface + a.n_liquid + a.n_interface)
+        done += 1
+    return upd / dt / 1e6, dt, done
+
+
+def time_runs(setup, variants, steps, warmup, ksteps, graphs=True):
+    """One run per variant of the same setup on a non-default stream (step
+    graphs are replayed on it, captured before the warm-up): `warmup` untimed
+    steps, then `steps` timed steps of every run (HIP events around the whole
+    window), then `ksteps` steps with the streaming kernel's own launches
+    timed. Returns the window's duration, the fluid+interface updates in it,
+    per-run state, and the streaming kernel's mean launch time and
+    algorithmic bytes per launch."""
+    import torch
+    from paper_2207_13962_amd import inputs as I
+    from paper_2207_13962_amd.fslbm import Simulation
+
+    p = setup.params
+    sb = {I.F64: 8, I.F32: 4, I.F16S: 2}[p.storage]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sims = [Simulation(setup, variant=v, device="cuda:0", stream=stream) for v in variants]
+        for s in sims:
+            s.set_graphs(graphs)  # captures the step graph now
+        # warmup, in the same interleaving as the timed region
+        for s in sims:
+            s.step(warmup)
+        stream.synchronize()
+        before = [s.mass(check=False) for s in sims]
+        chunk = 48
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream.synchronize()
+        ev0.record(stream)
+        done = 0
+        while done < steps:
+            n = min(chunk, steps - done)
+            for s in sims:
+                s.step(n)
+            done += n
+        ev1.record(stream)
+        stream.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        after = [s.mass(check=False) for s in sims]
+        # dominant kernel: the streaming launches of a second region, each
+        # launch recording its own start/stop timestamps
+        for s in sims:
+            s.set_timing(ksteps)
+        kb = [s.mass(check=False) for s in sims]
+        for s in sims:
+            s.step(ksteps)
+        stream.synchronize()
+        ka = [s.mass(check=False) for s in sims]
+        launches, kms, liq_bytes = 0, 0.0, 0.0
+        for s, b, a in zip(sims, kb, ka):
+            n, t = s.kernel_time()
+            launches += n
+            kms += t
+            nfl = 0.5 * (b["n_liquid"] + b["n_interface"] + a["n_liquid"] + a["n_interface"])
+            liq_bytes += n * nfl * bytes_per_update(p.q, sb)
+            s.set_timing(0)
+        for s in sims:
+            s.close()
+    updates = 0.0
+    per_variant = {}
+    for v, b, a, k in zip(variants, before, after, ka):
+        nb = b["n_liquid"] + b["n_interface"]
+        na = a["n_liquid"] + a["n_interface"]
+        updates += 0.5 * (nb + na) * steps
+        per_variant[I.VARIANT_NAMES[v]] = dict(
+            fluid_cells=int(na), interface_cells=int(a["n_interface"]),
+            mass_drift=(a["total_mass"] - b["total_mass"]) / b["total_mass"],
+            status="ok" if k["status"] == 0 else "unstable (%d)" % k["status"])
+    return dict(ms=ms, updates=updates, per_variant=per_variant, launches=launches,
+                avg_launch_ms=kms / max(launches, 1), bytes_per_launch=liq_bytes / max(launches, 1),
+                bytes_per_update=bytes_per_update(p.q, sb))
+
+
+def _line(name, setup, variants, steps, warmup, ksteps, graphs):
+    from paper_2207_13962_amd import inputs as I
+    p = setup.params
+    r = time_runs(setup, variants, steps, warmup, ksteps, graphs)
+    achieved = r["bytes_per_launch"] / (r["avg_launch_ms"] * 1e-3) / 1e9
+    return {
+        "workload": name,
+        "lattice": "D3Q%d %s" % (p.q, "TRT" if p.collision else "SRT"),
+        "dtype": {I.F64: "f64", I.F32: "f32", I.F16S: "f16-shifted/f32"}[p.storage],
+        "variants": "/".join(I.VARIANT_NAMES[v] for v in variants),
+        "steps": "%d-%d of each run" % (warmup, warmup + steps),
+        "value": r["updates"] / (r["ms"] * 1e-3) / 1e6,
+        "unit": "MLUPS",
+        "ms_per_time_step": r["ms"] / (steps * len(variants)),
+        "roofline": {"kernel": "k_stream", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "bytes_per_update": r["bytes_per_update"], "bytes_per_launch": r["bytes_per_launch"],
+                     "avg_launch_ms": r["avg_launch_ms"]},
+        "per_variant": r["per_variant"],
+    }
+
+
+def extra_lines(args):
+    """Throughput of the other measured workloads (each within its stable
+    window): the dam break in FP64 (the paper's precision), the cylindrical
+    dam break (D3Q27, free-slip walls, conversion-heavy) and the Taylor bubble
+    (D3Q27, surface tension, single-bubble volume pressure) in its three
+    storage formats. Context for the headline line."""
+    from paper_2207_13962_amd import inputs as I
+    graphs = not args.no_graphs
+    les = {"smagorinsky": args.les} if args.les else {}
+    out = {}
+    cache = {}
+
+    def taylor(st):
+        if "t" not in cache:
+            cache["t"] = I.workload("taylor512", storage=I.F64)
+        t = cache["t"]
+        return I.Setup(t.params.with_(storage=st), t.type, t.phi, t.rho, t.ux, t.uy, t.uz)
+
+    todo = [
+        ("dam256_fp64", lambda: I.workload("dam256", storage=I.F64, **les), [1, 2, 3, 4], 200, 100),
+        ("cyl256_fp32", lambda: I.workload("cyl256", **les), [1, 2, 3, 4], 200, 100),
+        ("taylor512_fp64", lambda: taylor(I.F64), [3], 200, 50),
+        ("taylor512_fp32", lambda: taylor(I.F32), [3], 200, 50),
+        ("taylor512_f16s", lambda: taylor(I.F16S), [3], 200, 50),
+    ]
+    for name, fn, variants, steps, warm in todo:
+        try:
+            s = fn()
+            p = s.params
+            desc = "%s: %dx%dx%d%s%s" % (name.split("_")[0], p.nx, p.ny, p.nz,
+                                         ", Smagorinsky C_S = %g" % p.smagorinsky if p.smagorinsky else "",
+                                         ", surface tension %g, single-bubble volume pressure" % p.sigma
+                                         if p.sigma else "")
+            out[name] = _line(desc, s, variants, steps, warm, min(steps, 100), graphs)
+            print("line %s: %.0f MLUPS, k_stream %.2f of peak" % (
+                name, out[name]["value"], out[name]["roofline"]["frac"]), file=sys.stderr, flush=True)
+        except Exception as e:  # context only: never hides the headline result
+            out[name] = {"error": repr(e)}
+    return out
 
 
 def serving_section(args, reqs=None):
@@ -511,7 +662,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="dam256")
     ap.add_argument("--variants", default="1,2,3,4")
-    ap.add_argument("--cpu-steps", type=int, default=24, help="oracle steps for the CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps, single-thread CPU baseline")
+    ap.add_argument("--cpu-steps-all", type=int, default=100,
+                    help="oracle steps, CPU baseline on all host threads")
+    ap.add_argument("--no-lines", action="store_true",
+                    help="skip the FP64 dam break, cylindrical dam break and Taylor-bubble lines")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=200,
                     help="time steps per variant run of the kernel-timing region")
@@ -620,65 +775,12 @@ def main():
     setup_fn = lambda: I.workload(args.workload, **({"smagorinsky": args.les} if args.les else {}))  # noqa: E731
     base = setup_fn()
     p = base.params
-    stream = torch.cuda.Stream()  # a non-default stream: step graphs are replayed on it
     sb = {I.F64: 8, I.F32: 4, I.F16S: 2}[p.storage]
-    with torch.cuda.stream(stream):
-        sims = [Simulation(base, variant=v, device="cuda:0", stream=stream) for v in variants]
-        for s in sims:
-            s.set_graphs(not args.no_graphs)
-        # warmup, in the same interleaving as the timed region
-        for s in sims:
-            s.step(args.warmup)
-        stream.synchronize()
-        before = [s.mass(check=False) for s in sims]
-        # timed region: K bench steps = K time steps of each variant run
-        chunk = 48
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        stream.synchronize()
-        ev0.record(stream)
-        done = 0
-        while done < args.steps:
-            n = min(chunk, args.steps - done)
-            for s in sims:
-                s.step(n)
-            done += n
-        ev1.record(stream)
-        stream.synchronize()
-        ms = ev0.elapsed_time(ev1)
-        after = [s.mass(check=False) for s in sims]
-        # dominant kernel: the streaming launches of a second timed region,
-        # each launch recording its own start/stop timestamps
-        ksteps = min(args.steps, args.kernel_steps)
-        for s in sims:
-            s.set_timing(ksteps)
-        kb = [s.mass(check=False) for s in sims]
-        t0 = time.perf_counter()
-        for s in sims:
-            s.step(ksteps)
-        stream.synchronize()
-        ka = [s.mass(check=False) for s in sims]
-        launches, kms, liq_bytes = 0, 0.0, 0.0
-        for s, b, a in zip(sims, kb, ka):
-            n, t = s.kernel_time()
-            launches += n
-            kms += t
-            nfl = 0.5 * (b["n_liquid"] + b["n_interface"] + a["n_liquid"] + a["n_interface"])
-            liq_bytes += n * nfl * bytes_per_update(p.q, sb)
-            s.set_timing(0)
-    # fluid+interface updates: average of the counts before and after the window
-    updates = 0.0
-    per_variant = {}
-    for v, b, a, k in zip(variants, before, after, ka):
-        nb = b["n_liquid"] + b["n_interface"]
-        na = a["n_liquid"] + a["n_interface"]
-        updates += 0.5 * (nb + na) * args.steps
-        per_variant[I.VARIANT_NAMES[v]] = dict(
-            fluid_cells=int(na), interface_cells=int(a["n_interface"]),
-            mass_drift=(a["total_mass"] - b["total_mass"]) / b["total_mass"],
-            status="ok" if k["status"] == 0 else "unstable (%d)" % k["status"])
+    r = time_runs(base, variants, args.steps, args.warmup, min(args.steps, args.kernel_steps),
+                  not args.no_graphs)
+    ms, updates, per_variant = r["ms"], r["updates"], r["per_variant"]
     mlups = updates / (ms * 1e-3) / 1e6
-    avg_ms = kms / max(launches, 1)
-    bytes_per_launch = liq_bytes / max(launches, 1)
+    avg_ms, bytes_per_launch, launches = r["avg_launch_ms"], r["bytes_per_launch"], r["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic()
     whole_gbs = updates * bytes_per_update(p.q, sb) / (ms * 1e-3) / 1e9
@@ -690,10 +792,15 @@ def main():
     cpu = None
     if not args.no_cpu:
         try:
-            v, dt = cpu_baseline(setup_fn, args.cpu_steps)
-            cpu = {"value": v, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-                   "sample": "first %d steps of the %s workload (%dx%dx%d, FP64 oracle, variant OM),"
-                             " %.1f s" % (args.cpu_steps, args.workload, p.nx, p.ny, p.nz, dt),
+            threads = host_threads()
+            v1, dt1, n1 = cpu_baseline(setup_fn, args.cpu_steps, 1)
+            vn, dtn, nn = cpu_baseline(setup_fn, args.cpu_steps_all, threads)
+            cpu = {"value": vn, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+                   "sample": "steps 1-%d of the %s workload (%dx%dx%d, FP64 oracle, variant OM) on %d "
+                             "OpenMP threads, %.1f s; fluid+interface updates counted outside the timer"
+                             % (nn, args.workload, p.nx, p.ny, p.nz, threads, dtn),
+                   "single_thread": {"value": v1, "cores": 1,
+                                     "sample": "steps 1-%d, %.1f s" % (n1, dt1)},
                    "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model()}
         except Exception as e:  # the baseline must never hide the GPU result
             cpu = {"value": None, "error": repr(e)}
@@ -706,6 +813,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "ms_per_time_step": ms / (args.steps * len(variants)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -721,7 +829,10 @@ def main():
             "effective_whole_step_frac_of_peak": whole_gbs / HBM_PEAK_GBS,
             "copy_GBps_measured": copy_gbs,
             "smagorinsky": args.les,
-            "step_launches": "kernel by kernel" if args.no_graphs else "replayed HIP graphs of 8 steps",
+            "bench_step": "one time step of each of the %d variant runs (ms_per_time_step: one run's "
+                          "time step)" % len(variants),
+            "step_launches": "kernel by kernel" if args.no_graphs else
+                             "replayed HIP graphs of 8 steps (captured before the warm-up)",
             "per_variant": per_variant,
         },
         "roofline": {
@@ -742,6 +853,8 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if not args.no_lines:
+        out["lines"] = extra_lines(args)
     if not args.no_scale_point:
         try:
             out["roofline_dam512"] = scale_point(args)

@@ -103,7 +103,11 @@ int fslbm_workspace_bytes(const fslbm_params* p, size_t* bytes);
  * type, phi, rho, ux, uy, uz: host arrays of N elements. Populations start at the
  * equilibrium feq(rho, u) and are collided once, so the stored state is post-collision.
  * pdf_or_null: q*N host doubles of post-collision populations (as exported by
- *   fslbm_fields) for an exact resume; mass_or_null: N host doubles of interface mass.
+ *   fslbm_fields) for an exact resume; mass_or_null: N host doubles of interface mass
+ *   (entries of other cells are ignored); phi then carries the fill levels of the
+ *   saved state. The lost mass and the volume-pressure scalars start afresh (lost
+ *   mass 0, p^V = p^V(0) = rho_gas/3, V(0) = the current gas volume) until
+ *   fslbm_set_scalars restores them.
  * device_arena_or_null: caller-owned device memory of at least fslbm_workspace_bytes,
  *   kept alive until fslbm_destroy; NULL lets the library allocate (and free) it.
  * hip_stream: the hipStream_t all work is enqueued on (NULL = default stream).
@@ -166,7 +170,10 @@ int fslbm_kernel_time(fslbm_ctx* ctx, int64_t* launches, double* total_ms);
 /* Step launches: with enable = 1 (the default) fslbm_step replays a captured
  * HIP graph of 8 steps when the context's stream is not the NULL stream and
  * timing is off; enable = 0 always launches kernel by kernel. Results are
- * identical either way. Errors: FSLBM_EINVAL (NULL). */
+ * identical either way. The graph is captured on the first fslbm_step of at
+ * least 8 steps, or at once by fslbm_set_graphs(ctx, 1) (capture records the
+ * launches without running them), so that timed steps need not include it.
+ * Errors: FSLBM_EINVAL (NULL), FSLBM_ESTATE, FSLBM_EDEVICE (capture failed). */
 int fslbm_set_graphs(fslbm_ctx* ctx, int enable);
 
 /* Compaction tile size: every thread of a 1024-thread compaction tile scans
@@ -177,6 +184,21 @@ int fslbm_set_graphs(fslbm_ctx* ctx, int enable);
  * exercising every tile shape on small domains. Errors: FSLBM_EINVAL (NULL,
  * not 16 times a power of two, below the library's size, above 4096). */
 int fslbm_set_compaction_tile(fslbm_ctx* ctx, int cells_per_thread);
+
+/* Scalars of a run's state beside its fields (Sec. 2.2): out/in[0] = lost
+ * mass (excess mass of converted cells that had no interface neighbour,
+ * counted in the total mass), [1] = the volume pressure p^V, [2] = p^V(0),
+ * [3] = V(0) of the volume-pressure equation p^V = p^V(0) V(0)/V. Together with
+ * fslbm_fields (type, phi, mass, pdf) they are the state an exact resume needs:
+ * fslbm_create(pdf, mass) followed by fslbm_set_scalars continues a run with
+ * constant pressure or one bubble (bubble_model 0 or 1) as if uninterrupted;
+ * with tracked bubbles (bubble_model 2) the bubbles restart at p^V(0).
+ * fslbm_get_scalars waits for the stream; fslbm_set_scalars takes effect for
+ * the next step and waits for the stream. in/out are 4 host doubles.
+ * Errors: FSLBM_EINVAL (NULL, non-finite values, V(0) <= 0 with bubble_model 1),
+ * FSLBM_ESTATE, FSLBM_EDEVICE. */
+int fslbm_get_scalars(fslbm_ctx* ctx, double out[4]);
+int fslbm_set_scalars(fslbm_ctx* ctx, const double in[4]);
 
 /* Releases the context (NULL-safe; never fails). Does not free a caller arena. */
 void fslbm_destroy(fslbm_ctx* ctx);

@@ -223,6 +223,12 @@ class Oracle:
         return dict(type=t, pdf=pdf.reshape(q, n), mass=m, phi=phi,
                     lost_mass=sc[0], p_volume=sc[1], p_volume0=sc[2], volume0=sc[3])
 
+    def types(self):
+        """Cell types of the current state (a copy, no arithmetic)."""
+        t = np.zeros(self.n, dtype=np.uint8)
+        _L().orc_export_state(self._h, _u8(t), None, None, None, None)
+        return t
+
     def import_state(self, st, step=0):
         """Replaces the state verbatim by one exported from an oracle run of
         the same shape (see export_state)."""

@@ -125,18 +125,18 @@ void bind(fslbm_ctx* c) {
 double* stage(fslbm_ctx* c) { return reinterpret_cast<double*>(c->arena + c->L.off_stage); }
 
 // Bubble volume at t+1 (phiB, new types) and the volume pressure update.
+// (blocks of kVolCells cells: four times the mass reduction's block count,
+// which the partial buffer, sized for kRedN values per mass block, holds)
+constexpr int kVolCells = kRedCells / 4;
+static_assert(kRedN >= 4, "volume partials must fit the partial buffer");
+
 void launch_volume(fslbm_ctx* c, hipStream_t s, bool set_reference) {
-  hipLaunchKernelGGL(k_reduce_volume, dim3((unsigned)c->L.red_blocks), dim3(kBlock), 0, s, c->d,
-                     kRedCells);
+  const int64_t blocks = (c->L.N + kVolCells - 1) / kVolCells;
+  hipLaunchKernelGGL(k_reduce_volume, dim3((unsigned)blocks), dim3(kBlock), 0, s, c->d, kVolCells);
   double* out = c->d.partial + kRedN * c->L.red_blocks;
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, c->d.partial, (int)c->L.red_blocks,
-                     1, out);
-  if (set_reference) {
-    // p^V(0) = rho_gas / 3; V(0) = V
-    hipMemcpyAsync(c->d.pV + 2, out, sizeof(double), hipMemcpyDeviceToDevice, s);
-  } else {
-    hipLaunchKernelGGL(k_update_pv, dim3(1), dim3(64), 0, s, c->d.pV, out);
-  }
+  // with set_reference: p^V(0) = rho_gas / 3 was set by the caller; V(0) = V
+  hipLaunchKernelGGL(k_sum_volume, dim3(1), dim3(kBlock), 0, s, c->d.partial, (int)blocks, out, c->d.pV,
+                     set_reference ? 1 : 0);
 }
 
 // Tracked bubbles from the types and fill levels at t+1 (flags, phiB): new
@@ -186,24 +186,45 @@ void drop_graph(fslbm_ctx* c) {
   c->graph = nullptr;
 }
 
+// Captures (without running) the launches of kGraphSteps steps as a graph
+// and instantiates it. Recording the steps advances the host-side step
+// counter and swaps the buffer pointers kGraphSteps times (an even number:
+// they end where they started); the counter is set back, since nothing ran.
+int capture_graph(fslbm_ctx* c) {
+  hipStream_t s = c->stream;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+  c->graph_parity = (int)(c->step & 1);
+  enqueue_plain(c, kGraphSteps);
+  c->step -= kGraphSteps;
+  e = hipStreamEndCapture(s, &c->graph);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+  return FSLBM_OK;
+}
+
+bool graphs_usable(const fslbm_ctx* c) { return c->graphs && c->ev.empty() && c->stream != nullptr; }
+
 // Steps go to the stream as a replayed graph of kGraphSteps steps where
 // possible (one launch instead of ~5 per step), the rest as plain launches.
 // Timing runs (events per streaming launch) always use plain launches.
 int enqueue_steps(fslbm_ctx* c, int64_t n) {
   hipStream_t s = c->stream;
-  const bool use_graph = c->graphs && c->ev.empty() && s != nullptr;
+  const bool use_graph = graphs_usable(c);
   while (use_graph && n >= kGraphSteps) {
     if (!c->graph_exec) {
-      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
-      if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
-      enqueue_plain(c, kGraphSteps);  // advances the host-side state
-      e = hipStreamEndCapture(s, &c->graph);
-      if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
-    } else {
-      c->step += kGraphSteps;  // pointers are back where they were captured
+      const int st = capture_graph(c);
+      if (st != FSLBM_OK) return st;
     }
+    if ((int)(c->step & 1) != c->graph_parity) {
+      // the graph holds the buffer pointers and counter slots of the parity
+      // it was captured at: one plain step brings the run back to it
+      enqueue_plain(c, 1);
+      n -= 1;
+      continue;
+    }
+    c->step += kGraphSteps;  // pointers are back where they were captured
     hipError_t e = hipGraphLaunch(c->graph_exec, s);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
     n -= kGraphSteps;
@@ -290,9 +311,11 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   bind(c);
   {
     int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      c->cus = cus;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      c->device = dev;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        c->cus = cus;
+    }
     (void)hipGetLastError();
   }
   const Ops ops = pick(c->p);
@@ -389,9 +412,9 @@ int fslbm_mass(fslbm_ctx* c, fslbm_mass_report* r) {
   if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
   const Ops ops = pick(c->p);
   hipStream_t s = c->stream;
-  ops.reduce_mass(c, s);
+  ops.reduce_mass(c->d, c->L.red_blocks, s);
   double* out = c->d.partial + kRedN * c->L.red_blocks;
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, c->d.partial, (int)c->L.red_blocks,
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->d.partial, (int)c->L.red_blocks,
                      kRedN, out);
   double v[kRedN], pv[3];
   HIPCHK(c, hipMemcpyAsync(v, out, sizeof v, hipMemcpyDeviceToHost, s));
@@ -492,7 +515,13 @@ static void release_events(fslbm_ctx* c) {
 int fslbm_set_graphs(fslbm_ctx* c, int enable) {
   if (!c) return FSLBM_EINVAL;
   c->graphs = enable != 0;
-  if (!c->graphs) drop_graph(c);
+  if (!c->graphs) {
+    drop_graph(c);
+    return FSLBM_OK;
+  }
+  if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  // capture now, so that the first steps replay instead of capturing
+  if (graphs_usable(c) && !c->graph_exec) return capture_graph(c);
   return FSLBM_OK;
 }
 
@@ -535,6 +564,42 @@ int fslbm_kernel_time(fslbm_ctx* c, int64_t* launches, double* total_ms) {
   }
   *launches = c->ev_used;
   *total_ms = t;
+  return FSLBM_OK;
+}
+
+int fslbm_get_scalars(fslbm_ctx* c, double out[4]) {
+  if (!c || !out) return FSLBM_EINVAL;
+  if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  const Ops ops = pick(c->p);
+  hipStream_t s = c->stream;
+  ops.reduce_mass(c->d, c->L.red_blocks, s);
+  double* red = c->d.partial + kRedN * c->L.red_blocks;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, c->d.partial, (int)c->L.red_blocks,
+                     kRedN, red);
+  double v[kRedN], pv[3];
+  HIPCHK(c, hipMemcpyAsync(v, red, sizeof v, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(pv, c->d.pV, sizeof pv, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  out[0] = v[2];
+  out[1] = pv[0];
+  out[2] = pv[1];
+  out[3] = pv[2];
+  return FSLBM_OK;
+}
+
+int fslbm_set_scalars(fslbm_ctx* c, const double in[4]) {
+  if (!c || !in) return FSLBM_EINVAL;
+  if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(in[i])) return set_err(c, FSLBM_EINVAL, "non-finite scalar");
+  if (!(in[3] > 0.0) && c->p.bubble_model == 1) return set_err(c, FSLBM_EINVAL, "V(0) must be > 0");
+  hipStream_t s = c->stream;
+  // the lost mass is kept per cell and summed when reported: the whole
+  // restored amount goes to the first cell's entry
+  HIPCHK(c, hipMemsetAsync(c->d.lost, 0, 8 * c->L.N, s));
+  HIPCHK(c, hipMemcpyAsync(c->d.lost, &in[0], sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d.pV, &in[1], 3 * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
   return FSLBM_OK;
 }
 

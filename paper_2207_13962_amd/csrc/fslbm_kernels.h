@@ -1528,18 +1528,53 @@ __global__ __launch_bounds__(kBlock) void k_reduce_volume(Dev d, int cells_per_b
   block_reduce_store<1>(v, d.partial + blockIdx.x);
 }
 
-__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partial, int nblocks,
-                                                         int nv, double* out) {
-  // thread i sums value i over the partials in block order
-  if ((int)threadIdx.x < nv) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * nv + threadIdx.x];
-    out[threadIdx.x] = s;
+// Sum of per-block partials (nv values each) in a fixed order, by one block
+// of kBlock threads: thread t adds the partials t, t + kBlock, t + 2 kBlock,
+// ... in that order, then the threads' sums are added pairwise in a fixed
+// tree. The order depends only on nblocks, so every call on the same
+// partials gives the same bits.
+constexpr int kSumMaxV = 8;
+__device__ __forceinline__ void sum_partials_body(const double* partial, int nblocks, int nv, double* out) {
+  __shared__ double sh[kSumMaxV][kBlock];
+  double v[kSumMaxV];
+#pragma unroll
+  for (int i = 0; i < kSumMaxV; ++i) v[i] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+#pragma unroll
+    for (int i = 0; i < kSumMaxV; ++i)
+      if (i < nv) v[i] += partial[(int64_t)b * nv + i];
   }
+#pragma unroll
+  for (int i = 0; i < kSumMaxV; ++i) sh[i][threadIdx.x] = v[i];
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+#pragma unroll
+      for (int i = 0; i < kSumMaxV; ++i) sh[i][threadIdx.x] += sh[i][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < nv) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void k_update_pv(double* pV, const double* V) {
-  if (threadIdx.x == 0) pV[0] = pV[1] * pV[2] / V[0];
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partial, int nblocks,
+                                                         int nv, double* out) {
+  sum_partials_body(partial, nblocks, nv, out);
+}
+
+// The bubble volume V from the partials of k_reduce_volume, then the
+// volume pressure p^V = p^V(0) V(0) / V (Sec. 2.2), or, when the reference
+// is set, V(0) = V. pV: [0] p^V, [1] p^V(0), [2] V(0); out receives V.
+__global__ __launch_bounds__(kBlock) void k_sum_volume(const double* partial, int nblocks, double* out,
+                                                       double* pV, int set_reference) {
+  sum_partials_body(partial, nblocks, 1, out);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (set_reference)
+      pV[2] = out[0];
+    else
+      pV[0] = pV[1] * pV[2] / out[0];
+  }
 }
 
 // ---------------------------------------------------------------------------

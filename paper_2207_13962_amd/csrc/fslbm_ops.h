@@ -135,7 +135,9 @@ struct fslbm_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool graphs = true;
+  int graph_parity = 0;  // step parity at capture: buffers and counter slots are baked in
   int cus = 256;  // compute units of the device
+  int device = 0;  // the device current at creation (the arena's device)
 };
 
 constexpr int64_t kGraphSteps = 8;
@@ -202,7 +204,7 @@ struct Ops {
   void (*step)(fslbm_ctx*, hipStream_t);
   void (*convert)(fslbm_ctx*, hipStream_t, int rebuild_only);
   void (*classes)(fslbm_ctx*, hipStream_t);
-  void (*reduce_mass)(fslbm_ctx*, hipStream_t);
+  void (*reduce_mass)(const Dev&, int64_t blocks, hipStream_t);  // partials to d.partial
   void (*batch_step)(const BatchLaunch&, hipStream_t, int64_t tick);
   void (*init_state)(fslbm_ctx*, hipStream_t, int resume);
   void (*init_flags)(fslbm_ctx*, hipStream_t);
@@ -264,9 +266,8 @@ struct Impl {
     hipLaunchKernelGGL((kb_compact<S, Q, TRT>), dim3((unsigned)bl.blocks[2]), dim3(kCompBlock), 0, s,
                        bl.devs, bl.tab[2], bl.n, tick);
   }
-  static void reduce_mass(fslbm_ctx* c, hipStream_t s) {
-    hipLaunchKernelGGL((k_reduce_mass<S, Q>), dim3((unsigned)c->L.red_blocks), dim3(kBlock), 0, s,
-                       c->d, kRedCells);
+  static void reduce_mass(const Dev& d, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_reduce_mass<S, Q>), dim3((unsigned)blocks), dim3(kBlock), 0, s, d, kRedCells);
   }
   static void init_state(fslbm_ctx* c, hipStream_t s, int resume) {
     hipLaunchKernelGGL((k_init_state<S, Q, TRT>), dim3(grid_for(c->L.N)), dim3(kBlock), 0, s, c->d,

@@ -97,6 +97,10 @@ def load_library(path: str = LIB_PATH):
     lib.fslbm_set_graphs.restype = C.c_int
     lib.fslbm_set_compaction_tile.argtypes = [vp, C.c_int]
     lib.fslbm_set_compaction_tile.restype = C.c_int
+    lib.fslbm_get_scalars.argtypes = [vp, dp]
+    lib.fslbm_get_scalars.restype = C.c_int
+    lib.fslbm_set_scalars.argtypes = [vp, dp]
+    lib.fslbm_set_scalars.restype = C.c_int
     lib.fslbm_destroy.argtypes = [vp]
     lib.fslbm_destroy.restype = None
     lib.fslbm_strerror.argtypes = [C.c_int]
@@ -239,6 +243,14 @@ class Simulation:
             out["pdf"] = f.reshape(q, n)
         return out
 
+    def types(self, check=True):
+        """Cell types only (one copy of the flag bytes; waits for the stream)."""
+        t = np.zeros(self.n, dtype=np.uint8)
+        st = self._lib.fslbm_fields(self._h, _u8(t), None, None, None, None, None, None, None)
+        if check:
+            self._check(st)
+        return t
+
     def interface_list(self):
         cnt = C.c_int64()
         self._check(self._lib.fslbm_interface_list(self._h, None, 0, C.byref(cnt)))
@@ -262,6 +274,17 @@ class Simulation:
         if check:
             self._check(st)
         return lab[:cnt.value], vol[:cnt.value], pr[:cnt.value]
+
+    def scalars(self):
+        """(lost mass, p^V, p^V(0), V(0)) of the current state."""
+        out = np.zeros(4)
+        self._check(self._lib.fslbm_get_scalars(self._h, _dp(out)))
+        return tuple(float(x) for x in out)
+
+    def set_scalars(self, lost_mass, p_volume, p_volume0, volume0):
+        """Restore the scalars of a saved state (after a resume from pdf and mass)."""
+        v = np.array([lost_mass, p_volume, p_volume0, volume0], dtype=np.float64)
+        self._check(self._lib.fslbm_set_scalars(self._h, _dp(v)))
 
     def set_graphs(self, enable):
         """Replay captured step graphs (default) or launch kernel by kernel."""

@@ -7,9 +7,16 @@ import numpy as np
 # identical. Interface mass and fill level are compared relative to the cell's
 # mass scale max(|m|, 1) (densities are ~1): an interface cell about to empty
 # has m ~ 0, where a relative test would only measure the accumulated
-# absolute round-off.
+# absolute round-off. m and phi accumulate one step's mass-flux sum per step,
+# formed in direction order by the oracle and in a lane butterfly by the GPU,
+# so their rounding difference grows with the number of steps: long runs use
+# mass_tol(steps), 1e-14 per step (1e-12 up to 100 steps, 1e-11 at 1000).
 RTOL64 = 1e-12
 ATOL64 = 1e-15
+
+
+def mass_tol(steps):
+    return max(RTOL64, 1e-14 * steps)
 
 
 def max_rel(a, b, atol=ATOL64):
@@ -18,7 +25,7 @@ def max_rel(a, b, atol=ATOL64):
     return float(np.max(d / (scale + atol))) if d.size else 0.0
 
 
-def compare_state(gpu, orc, fluid_only=True, rtol=RTOL64, atol=ATOL64, what=""):
+def compare_state(gpu, orc, fluid_only=True, rtol=RTOL64, atol=ATOL64, what="", mtol=RTOL64):
     """gpu: Simulation; orc: Oracle. Returns a dict of the worst deviations and
     raises AssertionError with the first offending cell otherwise."""
     g = gpu.fields(pdf=True)
@@ -40,7 +47,7 @@ def compare_state(gpu, orc, fluid_only=True, rtol=RTOL64, atol=ATOL64, what=""):
             what, k, cell, pg[k, c], po[k, c]))
     for key in ("mass", "phi"):
         a, b = g[key][iface], o[key][iface]
-        okm = np.abs(a - b) <= rtol * np.maximum(np.abs(b), 1.0)
+        okm = np.abs(a - b) <= mtol * np.maximum(np.abs(b), 1.0)
         if not okm.all():
             c = np.nonzero(~okm)[0][0]
             raise AssertionError("%s: %s of interface cell %d: gpu %.17g oracle %.17g" % (

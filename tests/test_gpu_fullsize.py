@@ -6,7 +6,9 @@
   oracle;
 * cyl256 (D3Q27 TRT, free-slip walls, 8.4 M cells) in FP32: mass conservation,
   the interface list, and the mirror symmetries of the setup (in bulk); the
-  same run in FP64: the symmetries to rounding."""
+  same run in FP64: the symmetries to rounding, and 24 steps against the oracle;
+* dam256 in FP64 after 600 steps against the oracle, then 20 more steps from
+  the oracle's own state loaded through the resume path."""
 import numpy as np
 import pytest
 
@@ -105,3 +107,59 @@ def test_cyl256_fp64_symmetry():
     for differ, dphi in _mirror_diffs(f, s.params):
         assert differ == 0.0
         assert dphi.max() < 1e-11
+
+
+@pytest.mark.timeout(900)
+def test_cyl256_fp64_oracle_parity():
+    """cyl256 (D3Q27 TRT, free-slip sides and ceiling, no-slip floor, 8.4 M
+    cells) in FP64 mode against the oracle: 24 steps (three replays of the
+    8-step graph), identical types, populations, masses and fill levels within
+    1e-12."""
+    from oracle import Oracle
+    from paper_2207_13962_amd.fslbm import Simulation
+    s = I.workload("cyl256", storage=I.F64, variant=I.NBRC)
+    g = Simulation(s)
+    o = Oracle(s)
+    g.step(24)
+    assert o.step(24) == 0
+    compare_state(g, o, what="cyl256")
+    rg, ro = g.mass(), o.mass()
+    assert abs(rg["total_mass"] - ro.total_mass) <= 1e-12 * ro.total_mass
+    g.close()
+
+
+@pytest.mark.timeout(1200)
+def test_dam256_collapse_parity_and_resume():
+    """dam256 as the benchmark runs it (Smagorinsky model, graph replay on a
+    non-default stream) in FP64 mode: after 600 steps, deep into the
+    collapse with tens of conversions per step, the GPU run and the oracle
+    agree (identical types, populations, masses, fill levels within 1e-12).
+    Then the oracle's own state at step 600 - post-collision populations,
+    masses, fill levels, types, lost mass - is loaded into a new GPU context
+    (fslbm_create with pdf and mass, fslbm_set_scalars) and both codes take 20
+    more steps: again identical within 1e-12."""
+    import torch
+    from oracle import Oracle
+    from paper_2207_13962_amd.fslbm import Simulation
+    s = I.workload("dam256", smagorinsky=0.1, storage=I.F64, variant=I.OM)
+    o = Oracle(s)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = Simulation(s, stream=stream)
+        g.step(600)
+        assert o.step(600) == 0
+        compare_state(g, o, what="dam256 step 600")
+        mg, mo = g.mass(), o.mass()
+        assert abs(mg["total_mass"] - mo.total_mass) <= 1e-12 * mo.total_mass
+        g.close()
+        st = o.export_state()
+        f = o.fields()
+        init = I.Setup(s.params, st["type"], st["phi"], f["rho"], f["ux"], f["uy"], f["uz"])
+        r = Simulation(init, pdf=o.post_collision(), mass=st["mass"], stream=stream)
+        r.set_scalars(st["lost_mass"], st["p_volume"], st["p_volume0"], st["volume0"])
+        r.step(20)
+        assert o.step(20) == 0
+        compare_state(r, o, what="dam256 resumed from the oracle at step 600, +20")
+        mr, mo = r.mass(), o.mass()
+        assert abs(mr["total_mass"] - mo.total_mass) <= 1e-12 * mo.total_mass
+        r.close()
