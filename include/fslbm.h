@@ -133,6 +133,27 @@ int fslbm_step(fslbm_ctx* ctx, int64_t nsteps);
  * detected since creation (the report is still filled). */
 int fslbm_mass(fslbm_ctx* ctx, fslbm_mass_report* out);
 
+/* For callers that cannot allocate or wait (code under HIP graph capture,
+ * tight serving loops): the reduction of fslbm_mass, enqueued on the
+ * context's stream without waiting, its per-block partial sums held in a
+ * static device buffer of the library instead of the context's memory, and
+ * its result written to device memory. Allocates nothing and calls no
+ * allocating routine on success.
+ * out_device: 8 doubles of device memory (caller-owned): total mass, liquid
+ *   mass, interface mass, lost mass, bubble volume, n_liquid, n_interface,
+ *   n_gas (counts as doubles); the same values, summed in the same order, as
+ *   fslbm_mass reports for the same state. Valid once the stream reaches the
+ *   call.
+ * Limit: domains of at most 134217728 cells (16384 blocks of 8192 cells; the
+ *   static buffer is 16384 * 7 doubles = 896 KiB per GPU, held until the
+ *   process ends); larger ones get FSLBM_EINVAL and a message (use fslbm_mass).
+ * The static buffer is shared by every context on one GPU: calls that may
+ *   overlap on one GPU (different streams, different host threads) race;
+ *   calls ordered on one stream do not. No status check: an instability is
+ *   reported by the next fslbm_mass or fslbm_fields.
+ * Errors: FSLBM_EINVAL (NULL, domain too large), FSLBM_ESTATE, FSLBM_EDEVICE. */
+int fslbm_mass_noalloc(fslbm_ctx* ctx, double* out_device);
+
 /* Waits for the stream and copies fields out (any pointer may be NULL):
  * type (N bytes), phi, rho, ux, uy, uz, mass (N doubles each; mass is m for
  * interface cells, rho for liquid cells, 0 for gas), pdf (q*N doubles,

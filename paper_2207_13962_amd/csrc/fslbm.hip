@@ -24,9 +24,39 @@ using namespace fslbm;
 
 using namespace fslbm_host;
 
+#include <mutex>
+
 namespace {
 
 thread_local char g_create_error[512] = "";
+
+// Scratch of fslbm_mass_noalloc: the per-block partial sums of the mass
+// reduction (kRedN doubles for each block of kRedCells cells), for domains of
+// at most kNoAllocBlocks * kRedCells cells. Each GPU the library runs on holds
+// its own copy until the process ends. In host code `scratch` is only a
+// symbol: its device address on a GPU comes from hipGetSymbolAddress with
+// that GPU current (kept in g_scratch, filled by fslbm_create).
+constexpr int64_t kNoAllocBlocks = 16384;
+__device__ __align__(256) double scratch[kNoAllocBlocks * kRedN];
+constexpr int kMaxDevices = 64;
+double* g_scratch[kMaxDevices] = {nullptr};
+std::mutex g_scratch_mu;
+
+// Address of the scratch array on the current device (resolved once per
+// device); nullptr on failure.
+double* scratch_for_current_device(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch[dev];
+}
 
 int set_err(fslbm_ctx* c, int st, const std::string& msg) {
   if (c) c->last_error = msg;
@@ -315,6 +345,8 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
       c->device = dev;
       if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         c->cus = cus;
+      // set-up of fslbm_mass_noalloc on this device (its scratch address)
+      (void)scratch_for_current_device(dev);
     }
     (void)hipGetLastError();
   }
@@ -432,6 +464,32 @@ int fslbm_mass(fslbm_ctx* c, fslbm_mass_report* r) {
   r->n_gas = (int64_t)v[6];
   r->step = c->step;
   return st;
+}
+
+int fslbm_mass_noalloc(fslbm_ctx* c, double* out_device) {
+  if (!c || !out_device) return FSLBM_EINVAL;
+  if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  if (c->L.red_blocks > kNoAllocBlocks) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "fslbm_mass_noalloc: %lld cells exceed its scratch (at most %lld cells); use fslbm_mass",
+             (long long)c->L.N, (long long)(kNoAllocBlocks * kRedCells));
+    return set_err(c, FSLBM_EINVAL, buf);
+  }
+  double* scr = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch[c->device] : nullptr;
+  if (!scr) return set_err(c, FSLBM_EDEVICE, "fslbm_mass_noalloc: scratch address not resolved");
+  const Ops ops = pick(c->p);
+  hipStream_t s = c->stream;
+  // the reduction of fslbm_mass (same blocks, same order), partials in the scratch
+  Dev d = c->d;  // (a plain struct of pointers and numbers: no allocation)
+  d.partial = scr;
+  ops.reduce_mass(d, c->L.red_blocks, s);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, scr, (int)c->L.red_blocks, kRedN,
+                     out_device + 1);
+  hipLaunchKernelGGL(k_total_of_report, dim3(1), dim3(64), 0, s, out_device);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "fslbm_mass_noalloc launch");
+  return FSLBM_OK;
 }
 
 int fslbm_fields(fslbm_ctx* c, uint8_t* type, double* phi, double* rho, double* ux, double* uy,

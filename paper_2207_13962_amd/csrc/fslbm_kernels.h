@@ -1577,6 +1577,13 @@ __global__ __launch_bounds__(kBlock) void k_sum_volume(const double* partial, in
   }
 }
 
+// Report of fslbm_mass_noalloc: r[1..7] hold the sums of the mass reduction;
+// r[0] = liquid + interface + lost mass, added as the host does it.
+__global__ void k_total_of_report(double* r) {
+  if (threadIdx.x == 0) r[0] = r[1] + r[2] + r[3];
+}
+
+
 // ---------------------------------------------------------------------------
 // Tracked bubbles (bubble model 2; Sec. 2.2 volume pressure followed through
 // coalescence and segmentation). A bubble is a connected set of gas and

@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     lib.fslbm_set_graphs.restype = C.c_int
     lib.fslbm_set_compaction_tile.argtypes = [vp, C.c_int]
     lib.fslbm_set_compaction_tile.restype = C.c_int
+    lib.fslbm_mass_noalloc.argtypes = [vp, dp]
+    lib.fslbm_mass_noalloc.restype = C.c_int
     lib.fslbm_get_scalars.argtypes = [vp, dp]
     lib.fslbm_get_scalars.restype = C.c_int
     lib.fslbm_set_scalars.argtypes = [vp, dp]
@@ -228,6 +230,15 @@ class Simulation:
         d = r.as_dict()
         d["status"] = st
         return d
+
+    def mass_noalloc(self, out):
+        """Enqueue the mass reduction into `out`, a torch float64 device tensor
+        of 8 elements (total, liquid, interface, lost mass, bubble volume,
+        n_liquid, n_interface, n_gas); no allocation, no wait."""
+        if out.dtype != __import__("torch").float64 or out.numel() < 8 or not out.is_cuda:
+            raise ValueError("out must be a float64 device tensor of 8 elements")
+        self._check(self._lib.fslbm_mass_noalloc(self._h, C.cast(C.c_void_p(out.data_ptr()),
+                                                                 C.POINTER(C.c_double))))
 
     def fields(self, pdf=True, check=True):
         n, q = self.n, self.q
