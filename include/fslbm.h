@@ -245,8 +245,11 @@ const char* fslbm_last_error(const fslbm_ctx* ctx);
  * for fslbm_server_result, its memory and slot go to the next queued run.
  * A run's results do not depend on which other runs share the launches (each
  * run's cells are computed by the same code as in a single context).
- * Runs with surface tension (sigma > 0) or the bubble model are not served
- * (FSLBM_EINVAL at submit). The server is not thread-safe.
+ * Runs with surface tension (sigma > 0) add a smoothing and a curvature
+ * launch before the step, runs with one enclosed bubble (bubble_model 1) a
+ * volume and a volume-pressure launch after it, each covering the runs of the
+ * group that need it. Runs with tracked bubbles (bubble_model 2) are not
+ * served (FSLBM_EINVAL at submit). The server is not thread-safe.
  * ------------------------------------------------------------------------ */
 typedef struct fslbm_server fslbm_server;
 
@@ -263,8 +266,8 @@ int fslbm_server_create(size_t hbm_budget_bytes, int max_slots, void* hip_stream
 /* Queues one run of nsteps steps (> 0) from the given initial fields (the
  * arrays of fslbm_create, copied: the caller may free them on return).
  * req_id receives the run's id (increasing from 1). Errors: FSLBM_EINVAL
- * (parameters, sigma > 0, bubble model, nsteps <= 0, workspace above the
- * budget), FSLBM_ENOMEM (host memory). */
+ * (parameters, bubble_model 2, nsteps <= 0, workspace above the budget),
+ * FSLBM_ENOMEM (host memory). */
 int fslbm_server_submit(fslbm_server* srv, const fslbm_params* p, const uint8_t* type,
                         const double* phi, const double* rho, const double* ux, const double* uy,
                         const double* uz, int64_t nsteps, uint64_t* req_id);

@@ -155,13 +155,8 @@ void bind(fslbm_ctx* c) {
 double* stage(fslbm_ctx* c) { return reinterpret_cast<double*>(c->arena + c->L.off_stage); }
 
 // Bubble volume at t+1 (phiB, new types) and the volume pressure update.
-// (blocks of kVolCells cells: four times the mass reduction's block count,
-// which the partial buffer, sized for kRedN values per mass block, holds)
-constexpr int kVolCells = kRedCells / 4;
-static_assert(kRedN >= 4, "volume partials must fit the partial buffer");
-
 void launch_volume(fslbm_ctx* c, hipStream_t s, bool set_reference) {
-  const int64_t blocks = (c->L.N + kVolCells - 1) / kVolCells;
+  const int64_t blocks = vol_blocks_of(c->L.N);
   hipLaunchKernelGGL(k_reduce_volume, dim3((unsigned)blocks), dim3(kBlock), 0, s, c->d, kVolCells);
   double* out = c->d.partial + kRedN * c->L.red_blocks;
   // with set_reference: p^V(0) = rho_gas / 3 was set by the caller; V(0) = V
@@ -842,12 +837,30 @@ int rebuild_plan(fslbm_server* s) {
     bl.devs = s->d_devs;
     bl.buf = (g & 1) != 0;
     int cursor[kLaunches] = {0, 0, 0};
+    int xcursor[kAux] = {0, 0, 0, 0};
     for (const ResidentRun& r : s->resident) {
       if (r.group != g) continue;
+      // the launches beside the step, for the runs that need them
+      const fslbm_ctx* c = r.ctx;
+      const bool st = c->p.sigma != 0.0, bub = c->p.bubble_model == 1;
+      const int64_t xnb[kAux] = {smooth_tiles(c->p.nx, c->p.ny, c->p.nz), std::min<int64_t>(list_blocks(c), 64),
+                                 vol_blocks_of(c->L.N), 1};
+      for (int k = 0; k < kAux; ++k) {
+        if (!(k < AUX_VOL ? st : bub)) continue;
+        BatchEntry& e = s->h_tab[((size_t)g * kTabs + kLaunches + k) * s->max_slots + bl.aux_n[k]];
+        e.slot = r.slot;
+        e.blk0 = xcursor[k];
+        e.nblk = (int32_t)xnb[k];
+        e.a = e.b = e.pad = 0;
+        e.tick0 = r.tick0;
+        e.nsteps = r.nsteps;
+        xcursor[k] += (int)xnb[k];
+        ++bl.aux_n[k];
+      }
       int nb[kLaunches], split[2], cargs[2];
       run_blocks(r.ctx, nb, split, cargs);
       for (int k = 0; k < kLaunches; ++k) {
-        BatchEntry& e = s->h_tab[((size_t)g * kLaunches + k) * s->max_slots + bl.n];
+        BatchEntry& e = s->h_tab[((size_t)g * kTabs + k) * s->max_slots + bl.n];
         e.slot = r.slot;
         e.blk0 = cursor[k];
         e.nblk = nb[k];
@@ -861,11 +874,20 @@ int rebuild_plan(fslbm_server* s) {
       ++bl.n;
     }
     for (int k = 0; k < kLaunches; ++k) {
-      const size_t at = ((size_t)g * kLaunches + k) * s->max_slots;
+      const size_t at = ((size_t)g * kTabs + k) * s->max_slots;
       bl.blocks[k] = cursor[k];
       bl.tab[k] = s->d_tab + at;
       if (bl.n > 0 && hipMemcpyAsync(const_cast<BatchEntry*>(bl.tab[k]), s->h_tab + at, sizeof(BatchEntry) * bl.n,
                                      hipMemcpyHostToDevice, s->stream) != hipSuccess)
+        return srv_fail(s, hipErrorUnknown);
+    }
+    for (int k = 0; k < kAux; ++k) {
+      const size_t at = ((size_t)g * kTabs + kLaunches + k) * s->max_slots;
+      bl.aux_blocks[k] = xcursor[k];
+      bl.aux[k] = s->d_tab + at;
+      if (bl.aux_n[k] > 0 &&
+          hipMemcpyAsync(const_cast<BatchEntry*>(bl.aux[k]), s->h_tab + at, sizeof(BatchEntry) * bl.aux_n[k],
+                         hipMemcpyHostToDevice, s->stream) != hipSuccess)
         return srv_fail(s, hipErrorUnknown);
     }
   }
@@ -984,7 +1006,7 @@ int fslbm_server_create(size_t hbm_budget_bytes, int max_slots, void* hip_stream
   s->budget = hbm_budget_bytes;
   s->max_slots = max_slots;
   s->stream = static_cast<hipStream_t>(hip_stream);
-  const size_t tab = sizeof(BatchEntry) * (size_t)kGroups * kLaunches * (size_t)max_slots;
+  const size_t tab = sizeof(BatchEntry) * (size_t)kGroups * kTabs * (size_t)max_slots;
   if (hipMalloc(reinterpret_cast<void**>(&s->pool_mem), hbm_budget_bytes) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_devs), sizeof(Dev) * (size_t)max_slots) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&s->d_tab), tab) != hipSuccess ||
@@ -1017,7 +1039,7 @@ int fslbm_server_submit(fslbm_server* s, const fslbm_params* p, const uint8_t* t
                         int64_t nsteps, uint64_t* req_id) {
   if (!s || !req_id || !type || !phi || !rho || !ux || !uy || !uz || nsteps <= 0) return FSLBM_EINVAL;
   if (validate(p)) return FSLBM_EINVAL;
-  if (p->sigma != 0.0 || p->bubble_model != 0) return FSLBM_EINVAL;
+  if (p->bubble_model == 2) return FSLBM_EINVAL;  // tracked bubbles: single contexts only
   const size_t bytes = make_layout(*p).total;
   if ((size_t)round_up((int64_t)bytes, 256) > s->budget) return FSLBM_EINVAL;
   PendingRun q;
@@ -1081,7 +1103,21 @@ int fslbm_server_advance(fslbm_server* s, int64_t ticks) {
     for (int64_t i = 0; i < chunk; ++i)
       for (int a = 0; a < na; ++a) {
         hipStream_t st = fork ? s->gstream[active[a] % fslbm_server::kGroupStreams] : s->stream;
-        ops[a].batch_step(s->launch[active[a]], st, s->tick + i);
+        const BatchLaunch& bl = s->launch[active[a]];
+        const int64_t t = s->tick + i;
+        if (bl.aux_n[AUX_SMOOTH] > 0) {
+          hipLaunchKernelGGL(kb_smooth, dim3((unsigned)bl.aux_blocks[AUX_SMOOTH]), dim3(kBlock), 0, st, bl.devs,
+                             bl.aux[AUX_SMOOTH], bl.aux_n[AUX_SMOOTH], t);
+          hipLaunchKernelGGL(kb_curvature, dim3((unsigned)bl.aux_blocks[AUX_CURV]), dim3(kBlock), 0, st, bl.devs,
+                             bl.aux[AUX_CURV], bl.aux_n[AUX_CURV], t);
+        }
+        ops[a].batch_step(bl, st, t);
+        if (bl.aux_n[AUX_VOL] > 0) {
+          hipLaunchKernelGGL(kb_volume, dim3((unsigned)bl.aux_blocks[AUX_VOL]), dim3(kBlock), 0, st, bl.devs,
+                             bl.aux[AUX_VOL], bl.aux_n[AUX_VOL], t);
+          hipLaunchKernelGGL(kb_sum_volume, dim3((unsigned)bl.aux_blocks[AUX_SUMVOL]), dim3(kBlock), 0, st,
+                             bl.devs, bl.aux[AUX_SUMVOL], bl.aux_n[AUX_SUMVOL], t);
+        }
       }
     if (fork) {
       for (int k = 0; k < fslbm_server::kGroupStreams; ++k)

@@ -84,5 +84,41 @@ __global__ __launch_bounds__(kCompBlock) void kb_compact(const Dev* devs, const 
   compact_body<S, Q, TRT>(d, (int)blockIdx.x - e.blk0, e.nblk, 0, e.a, e.b);
 }
 
+#ifdef FSLBM_HOST_KERNELS
+// The launches of surface tension (before the streaming launch) and of the
+// single-bubble volume pressure (after the compaction) for the runs of a
+// batch that have them; their tables list only those runs. Each run's blocks
+// do what a single context's launch does with the same block index.
+__global__ __launch_bounds__(kBlock) void kb_smooth(const Dev* devs, const BatchEntry* tab, int n, int64_t tick) {
+  const BatchEntry e = batch_entry(tab, n);
+  Dev d;
+  if (!batch_dev(devs, e, tick, d)) return;
+  smooth_body(d, (int)blockIdx.x - e.blk0);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_curvature(const Dev* devs, const BatchEntry* tab, int n,
+                                                       int64_t tick) {
+  const BatchEntry e = batch_entry(tab, n);
+  Dev d;
+  if (!batch_dev(devs, e, tick, d)) return;
+  curvature_body(d, (int)blockIdx.x - e.blk0, e.nblk);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_volume(const Dev* devs, const BatchEntry* tab, int n, int64_t tick) {
+  const BatchEntry e = batch_entry(tab, n);
+  Dev d;
+  if (!batch_dev(devs, e, tick, d)) return;
+  reduce_volume_body(d, (int)blockIdx.x - e.blk0, kVolCells);
+}
+
+// one block per run
+__global__ __launch_bounds__(kBlock) void kb_sum_volume(const Dev* devs, const BatchEntry* tab, int n,
+                                                        int64_t tick) {
+  const BatchEntry e = batch_entry(tab, n);
+  Dev d;
+  if (!batch_dev(devs, e, tick, d)) return;
+  sum_volume_body(d.partial, (int)vol_blocks_of(d.g.N), d.partial + kRedN * red_blocks_of(d.g.N), d.pV, 0);
+}
+#endif  // FSLBM_HOST_KERNELS
 
 }  // namespace fslbm

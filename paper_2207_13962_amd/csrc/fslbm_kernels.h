@@ -1352,13 +1352,17 @@ __global__ __launch_bounds__(kBlock) void k_classes(Dev d) {
 // Smoothed fill level of every cell, K(r) = (1 - r^2/4)^4 over the 3x3x3 box
 // (support radius 2), obstacles left out and the weights renormalised. The
 // block stages a (64+2) x (4+2) x (1+2) halo of phi and flags in LDS.
-__global__ __launch_bounds__(kBlock) void k_smooth(Dev d) {
-  constexpr int TX = 64, TY = 4;
+constexpr int kSmoothTX = 64, kSmoothTY = 4;
+__host__ __device__ inline int64_t smooth_tiles(int nx, int ny, int nz) {
+  return (int64_t)((nx + kSmoothTX - 1) / kSmoothTX) * ((ny + kSmoothTY - 1) / kSmoothTY) * nz;
+}
+
+__device__ __forceinline__ void smooth_body(const Dev& d, int bt) {
+  constexpr int TX = kSmoothTX, TY = kSmoothTY;
   __shared__ double s_phi[3][TY + 2][TX + 2];
   __shared__ uint8_t s_obs[3][TY + 2][TX + 2];
   const Geom& g = d.g;
   const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY;
-  const int bt = blockIdx.x;
   const int tz = bt / (tiles_x * tiles_y);
   const int r = bt - tz * tiles_x * tiles_y;
   const int ty0 = (r / tiles_x) * TY, tx0 = (r % tiles_x) * TX;
@@ -1395,6 +1399,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Dev d) {
   d.phis[c] = num / den;
 }
 
+__global__ __launch_bounds__(kBlock) void k_smooth(Dev d) { smooth_body(d, (int)blockIdx.x); }
+
 __device__ __forceinline__ void unit_normal_s(const Dev& d, int64_t j, double nh[3]) {
   int x, y, z;
   coords(d.g, j, x, y, z);
@@ -1412,9 +1418,9 @@ __device__ __forceinline__ void unit_normal_s(const Dev& d, int64_t j, double nh
 
 // kappa = -div(n_hat) by central differences of the unit normals of the face
 // neighbours; rho^G = 3 (p^V + sigma kappa).
-__global__ __launch_bounds__(kBlock) void k_curvature(Dev d) {
+__device__ __forceinline__ void curvature_body(const Dev& d, int b, int nb) {
   const int nif = d.cnt[CNT_IF];
-  for (int k = blockIdx.x * kBlock + threadIdx.x; k < nif; k += gridDim.x * kBlock) {
+  for (int k = b * kBlock + threadIdx.x; k < nif; k += nb * kBlock) {
     const int64_t c = list_cell(d.if_list[k]);
     int x, y, z;
     coords(d.g, c, x, y, z);
@@ -1451,6 +1457,10 @@ __global__ __launch_bounds__(kBlock) void k_curvature(Dev d) {
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_curvature(Dev d) {
+  curvature_body(d, (int)blockIdx.x, (int)gridDim.x);
+}
+
 #endif  // FSLBM_HOST_KERNELS
 
 // ---------------------------------------------------------------------------
@@ -1479,6 +1489,14 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* out)
 // Values per cell: [0] liquid rho, [1] interface m, [2] lost, [3] bubble volume
 // contribution, [4] n_liquid, [5] n_interface, [6] n_gas.
 constexpr int kRedN = 7;
+constexpr int kRedCells = 8192;  // cells per block of the mass reduction
+// cells per block of the bubble-volume reduction: four times the mass
+// reduction's block count, which the partial buffer (kRedN values per mass
+// block) holds
+constexpr int kVolCells = kRedCells / 4;
+static_assert(kRedN >= 4, "volume partials must fit the partial buffer");
+__host__ __device__ inline int64_t red_blocks_of(int64_t N) { return (N + kRedCells - 1) / kRedCells; }
+__host__ __device__ inline int64_t vol_blocks_of(int64_t N) { return (N + kVolCells - 1) / kVolCells; }
 
 template <int S, int Q>
 __global__ __launch_bounds__(kBlock) void k_reduce_mass(Dev d, int cells_per_block) {
@@ -1513,9 +1531,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_mass(Dev d, int cells_per_blo
 #ifdef FSLBM_HOST_KERNELS
 // Bubble volume only (sum of 1 - phi over gas and interface cells) from the
 // fill levels at t+1; one block then updates p^V = p^V(0) V(0) / V.
-__global__ __launch_bounds__(kBlock) void k_reduce_volume(Dev d, int cells_per_block) {
+__device__ __forceinline__ void reduce_volume_body(const Dev& d, int blk, int cells_per_block) {
   double v[1] = {0.0};
-  const int64_t begin = (int64_t)blockIdx.x * cells_per_block;
+  const int64_t begin = (int64_t)blk * cells_per_block;
   int64_t end = begin + cells_per_block;
   if (end > d.g.N) end = d.g.N;
   for (int64_t c = begin + threadIdx.x; c < end; c += kBlock) {
@@ -1525,7 +1543,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce_volume(Dev d, int cells_per_b
     else if (t == T_IF)
       v[0] += 1.0 - d.phiB[c];
   }
-  block_reduce_store<1>(v, d.partial + blockIdx.x);
+  block_reduce_store<1>(v, d.partial + blk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_volume(Dev d, int cells_per_block) {
+  reduce_volume_body(d, (int)blockIdx.x, cells_per_block);
 }
 
 // Sum of per-block partials (nv values each) in a fixed order, by one block
@@ -1565,8 +1587,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partial, 
 // The bubble volume V from the partials of k_reduce_volume, then the
 // volume pressure p^V = p^V(0) V(0) / V (Sec. 2.2), or, when the reference
 // is set, V(0) = V. pV: [0] p^V, [1] p^V(0), [2] V(0); out receives V.
-__global__ __launch_bounds__(kBlock) void k_sum_volume(const double* partial, int nblocks, double* out,
-                                                       double* pV, int set_reference) {
+__device__ __forceinline__ void sum_volume_body(const double* partial, int nblocks, double* out, double* pV,
+                                                int set_reference) {
   sum_partials_body(partial, nblocks, 1, out);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1575,6 +1597,11 @@ __global__ __launch_bounds__(kBlock) void k_sum_volume(const double* partial, in
     else
       pV[0] = pV[1] * pV[2] / out[0];
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_volume(const double* partial, int nblocks, double* out,
+                                                       double* pV, int set_reference) {
+  sum_volume_body(partial, nblocks, out, pV, set_reference);
 }
 
 // Report of fslbm_mass_noalloc: r[1..7] hold the sums of the mass reduction;

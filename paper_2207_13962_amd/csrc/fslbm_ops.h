@@ -32,7 +32,6 @@ struct Layout {
       off_bamt, off_bpr, off_bhas, total;
 };
 
-constexpr int kRedCells = 8192;  // cells per reduction block
 
 inline Layout make_layout(const fslbm_params& p) {
   Layout L{};
@@ -191,12 +190,22 @@ inline int compact_workers(const fslbm_ctx* c) {
 // collision, addressing) group: device tables of its launches.
 constexpr int kLaunches = 3;  // streaming, re-typing, compaction and completion
 
+// Launches beside the step for the runs that need them: smoothing and
+// curvature (surface tension) before the streaming launch, the bubble volume
+// and volume pressure (single-bubble model) after the compaction.
+constexpr int kAux = 4;
+enum { AUX_SMOOTH = 0, AUX_CURV = 1, AUX_VOL = 2, AUX_SUMVOL = 3 };
+constexpr int kTabs = kLaunches + kAux;  // tables per group
+
 struct BatchLaunch {
   const Dev* devs = nullptr;
   const BatchEntry* tab[kLaunches] = {nullptr, nullptr, nullptr};  // one table per launch
   int n = 0;                                 // entries of each table (one per run)
   int blocks[kLaunches] = {0, 0, 0};         // blocks of each launch
   bool buf = true;                 // buffer addressing (every grid below 2 GiB)
+  const BatchEntry* aux[kAux] = {nullptr, nullptr, nullptr, nullptr};  // only the runs that need them
+  int aux_n[kAux] = {0, 0, 0, 0};
+  int aux_blocks[kAux] = {0, 0, 0, 0};
 };
 
 // Kernel table for one (storage, lattice, collision) combination.

@@ -132,3 +132,26 @@ def wave_errors(r, windows=(6.0, 12.0, 24.0)):
         out["max_abs_err_t%g" % w] = float(np.max(np.abs(e)))
         out["rms_err_t%g" % w] = float(np.sqrt(np.mean(e * e)))
     return out
+
+
+def paper_curve_distances(r, variant, L, curves, t_max=12.0):
+    """Distances of a simulated elevation series r (gravity_wave_elevation) to
+    the paper's own simulated series of the same variant and L (curves: the
+    plotted series of the paper's convergence figures, {variant name: {L:
+    [(t*, a*)]}}), and, for scale, the largest distance between the paper's
+    series of this variant and of any other variant at the same L, each as the
+    max and RMS over t* in (0, t_max]."""
+    name = I.VARIANT_NAMES[variant]
+    sel = (r["t_star"] > 0) & (r["t_star"] <= t_max + 1e-9) & np.isfinite(r["a_sim"])
+    t = r["t_star"][sel]
+
+    def on_t(v):
+        p = np.asarray(curves[v][str(L)], dtype=np.float64)
+        return np.interp(t, p[:, 0], p[:, 1])
+
+    mine = on_t(name)
+    d = r["a_sim"][sel] - mine
+    others = [on_t(v) - mine for v in curves if v != name]
+    return dict(max_to_paper=float(np.abs(d).max()), rms_to_paper=float(np.sqrt(np.mean(d * d))),
+                paper_variant_spread_max=float(max(np.abs(o).max() for o in others)),
+                paper_variant_spread_rms=float(max(np.sqrt(np.mean(o * o)) for o in others)))

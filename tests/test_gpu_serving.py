@@ -111,9 +111,9 @@ def test_rejects_what_it_cannot_serve():
     with pytest.raises(FslbmError):
         srv.submit(I.wave_slab(L=96), 10)  # workspace above the budget
     s = I.wave_slab(L=16)
-    s.params = s.params.with_(sigma=1e-3)
+    s.params = s.params.with_(bubble_model=2)
     with pytest.raises(FslbmError):
-        srv.submit(s, 10)  # surface tension is not served
+        srv.submit(s, 10)  # tracked bubbles are not served
     with pytest.raises(FslbmError):
         srv.submit(I.wave_slab(L=16), 0)
     srv.close()
@@ -154,3 +154,71 @@ def test_unstable_run_stops_advancing():
     for k in ("type", "phi", "mass", "pdf"):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
         assert np.array_equal(a[k], c[k], equal_nan=True), k
+
+
+def _aux_mix(storage=I.F32):
+    """Runs that need the launches beside the step: surface tension with one
+    enclosed bubble (a rising bubble in a tube), surface tension alone (a
+    resting drop), one enclosed bubble without surface tension (a closed dam
+    break), and a plain drop impact, all in one launch group."""
+    taylor = I.taylor_bubble(nx=20, ny=20, nz=40, tube_radius=8.5, bubble_radius=5.0, z0=10.0, length=10.0,
+                             g=1e-5, nu=0.01, sigma=1e-3, storage=storage, variant=I.OM, collision=I.SRT,
+                             q=19)
+    drop = I.sphere_drop_static(L=20, radius=5.0, sigma=2e-3, storage=storage)
+    dam = I.rect_dam_break(nx=32, ny=24, nz=12, wx=10, hy=18, g=2e-4, nu=5e-3, collision=I.SRT,
+                           storage=storage, variant=I.NBKC)
+    dam.params = dam.params.with_(bubble_model=1)
+    plain = I.droplet_impact(L=24, velocity=0.03, variant=I.NBRC, storage=storage)
+    return [taylor, drop, dam, plain], [70, 45, 60, 50]
+
+
+def test_surface_tension_and_bubble_runs_served():
+    """Served runs with surface tension or the single-bubble model equal
+    their single-context runs bitwise (fill levels, total mass, volume
+    pressure), alone and in the mix."""
+    from paper_2207_13962_amd.fslbm import Simulation
+    setups, steps = _aux_mix()
+    mixed, peak, _ = _serve(setups, steps)
+    assert peak == len(setups)
+    for i, s in enumerate(setups):
+        alone, _, _ = _serve([s], [steps[i]])
+        st_m, rep_m, phi_m = mixed[i]
+        st_a, rep_a, phi_a = alone[0]
+        assert st_m == st_a == 0
+        assert np.array_equal(phi_m, phi_a), i
+        sim = Simulation(s)
+        sim.step(steps[i])
+        r = sim.mass()
+        phi_s = sim.fields(pdf=False)["phi"]
+        sim.close()
+        assert np.array_equal(phi_m, phi_s), i
+        assert rep_m["total_mass"] == r["total_mass"]
+        assert rep_m["p_volume"] == r["p_volume"] == rep_a["p_volume"], i
+        assert rep_m["bubble_volume"] == r["bubble_volume"]
+
+
+def test_served_surface_tension_run_matches_oracle():
+    """A served FP64 rising bubble (surface tension, volume pressure) against
+    the oracle: fill levels and mass within 1e-12, the volume pressure too."""
+    from oracle import Oracle
+    setups, steps = _aux_mix(I.F64)
+    out, _, _ = _serve(setups[:3], steps[:3], ticks=9)
+    for i in range(3):
+        o = Oracle(setups[i])
+        assert o.step(steps[i]) == 0
+        f, r = o.fields(), o.mass()
+        st, rep, phi = out[i]
+        assert st == 0
+        ifc = f["type"] == I.INTERFACE
+        assert np.abs(phi[ifc] - f["phi"][ifc]).max() < 1e-12, i
+        assert abs(rep["total_mass"] - r.total_mass) <= 1e-12 * r.total_mass
+        assert abs(rep["p_volume"] - r.p_volume) <= 1e-12 * r.p_volume
+
+
+def test_tracked_bubble_runs_are_refused():
+    from paper_2207_13962_amd.fslbm import FslbmError, Server
+    srv = Server(64 * MB, max_slots=2)
+    s = I.bubble_pair("apart", storage=I.F32)
+    with pytest.raises(FslbmError):
+        srv.submit(s, 10)
+    srv.close()
