@@ -296,7 +296,10 @@ def validate_wave(L=200, variants=(1, 2, 3, 4)):
     surface elevation at x = 0 against the analytic model (errors over the
     first t* = 6, 12 and 24), sampled every t* = 0.05 up to t* = 40."""
     from paper_2207_13962_amd import inputs as I
-    from paper_2207_13962_amd.validation import gravity_wave_elevation, wave_errors
+    from paper_2207_13962_amd.validation import gravity_wave_elevation, paper_curve_distances, wave_errors
+
+    golden = os.path.join(ROOT, "tests", "golden", "gravity_wave_paper_curves.json")
+    curves = json.load(open(golden))["variants"] if os.path.exists(golden) else None
 
     out = {"setup": "paper gravity wave, L = %d (%dx%dx1, D3Q19 SRT, omega 1.8, Re 10, a0 0.01 L, d L/2)"
                     % (L, L, L), "variants": {}}
@@ -311,6 +314,9 @@ def validate_wave(L=200, variants=(1, 2, 3, 4)):
         e["status"] = "ok" if r["status"] == 0 else "unstable (%d)" % r["status"]
         # the elevation at every t* = 1 for plotting against the model
         e["a_sim_every_t1"] = [round(float(x), 4) for x in r["a_sim"][::20]]
+        if curves:
+            e["vs_paper_runs"] = {"t%g" % tm: paper_curve_distances(r, v, L, curves, t_max=tm)
+                                  for tm in (12.0, 24.0) if tm <= r["t_star"][-1] + 1e-9}
         out["variants"][name] = e
         print("wave L=%d %s: max err to t*=12 %.3f, to t*=24 %.3f" % (
             L, name, e["max_abs_err_t12"], e["max_abs_err_t24"]), file=sys.stderr, flush=True)

@@ -132,6 +132,7 @@ void bind(fslbm_ctx* c) {
   d.if_list = reinterpret_cast<int32_t*>(a + L.off_if_list);
   d.conv_list = reinterpret_cast<int32_t*>(a + L.off_conv_list);
   d.chunk_list = reinterpret_cast<int32_t*>(a + L.off_chunk_list);
+  d.chunk_mask = reinterpret_cast<uint64_t*>(a + L.off_chunk_mask);
   d.gen_list = reinterpret_cast<int32_t*>(a + L.off_gen_list);
   d.mark_list = reinterpret_cast<int32_t*>(a + L.off_mark_list);
   d.ng_list = reinterpret_cast<int32_t*>(a + L.off_ng_list);

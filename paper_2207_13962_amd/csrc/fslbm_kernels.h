@@ -58,6 +58,7 @@ struct Dev {
   int32_t* if_list;
   int32_t* conv_list;
   int32_t* chunk_list;  // 64-cell chunks with liquid cells, ascending
+  uint64_t* chunk_mask;  // per chunk entry: bit l = cell 64 chunk + l is liquid and not COMPLEX
   int32_t* gen_list;    // liquid cells with the BORDER flag, ascending
   int32_t* mark_list;   // cells marked in this step (unordered)
   int32_t* ng_list;     // new interface cells from gas of this step (unordered)
@@ -115,19 +116,25 @@ __device__ __forceinline__ bool unstable(R rho, R ux, R uy, R uz) {
 // buffer resources; inside the domain a wave uses one per-lane offset (the
 // cell) plus a scalar offset per direction (plane start minus the neighbour
 // offset).
+// `mine`: the cell is liquid and not COMPLEX (its chunk entry's mask bit).
+// Such a cell has no obstacle in its 3x3x3 box and meets only no-slip domain
+// faces, so it has the BORDER bit exactly when it lies on a domain face.
 template <int S, int Q, bool TRT, bool BUF>
-__device__ __forceinline__ void liquid_cell(const Dev& d, int64_t c, bool valid) {
+__device__ __forceinline__ void liquid_cell(const Dev& d, int64_t c, bool mine) {
   using St = Store<S, Q>;
   using T = typename St::T;
   using R = typename St::R;
-  const uint8_t fl = valid ? d.flags[c] : (uint8_t)T_GAS;
-  const bool mine = (fl & (T_MASK | F_COMPLEX)) == T_LIQ;
-  const bool wall = mine && (fl & F_BORDER);
+  const Geom& g = d.g;
+  bool wall = false;
+  if (mine) {
+    int x, y, z;
+    coords(g, c, x, y, z);
+    wall = x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
+  }
   const bool any_wall = __ballot(wall) != 0ull;
   if (!mine) return;
   const T* A = static_cast<const T*>(d.fA);
   T* B = static_cast<T*>(d.fB);
-  const Geom& g = d.g;
   const int64_t stride = g.stride;
   const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
   R f[Q];
@@ -364,7 +371,7 @@ __device__ __forceinline__ R gcollide(R f, int k, const CollideParams<R>& cp, R&
 // discarded); only a source reflected at a free-slip face needs a second
 // round.
 template <int S, int Q, bool TRT>
-__device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk) {
+__device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk, int nif) {
   using St = Store<S, Q>;
   using T = typename St::T;
   using R = typename St::R;
@@ -373,7 +380,6 @@ __device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk) {
   T* B = static_cast<T*>(d.fB);
   const Geom& g = d.g;
   const int64_t stride = g.stride;
-  const int nif = d.cnt[CNT_IF];
   const int l = threadIdx.x & (kG - 1);
   const bool act = l < Q;
   const int k = act ? l : 0;
@@ -581,9 +587,7 @@ __device__ __forceinline__ void border_cell(const Dev& d, int64_t c) {
 // (every transient bit is stale by now; readers in this kernel look at the
 // type bits only).
 template <int S, int Q, bool TRT>
-__device__ __forceinline__ void border_role(const Dev& d, int blk, int nblk) {
-  const int n = d.cnt[CNT_GEN];
-  const int ncv = d.cnt[CNT_CONV];
+__device__ __forceinline__ void border_role(const Dev& d, int blk, int nblk, int n, int ncv) {
   for (int i = blk * kBlock + threadIdx.x; i < n + ncv; i += nblk * kBlock) {
     if (i < n) {
       border_cell<S, Q, TRT>(d, d.gen_list[i]);
@@ -595,15 +599,23 @@ __device__ __forceinline__ void border_role(const Dev& d, int blk, int nblk) {
 }
 
 // Each wave takes 64-cell chunks from the chunk list (chunks without liquid
-// cells are never visited), one cell per lane.
+// cells are never visited), one cell per lane. The wave's entries (chunk and
+// liquid-lane mask) are loaded 64 at a time, one per lane, and read back by
+// lane index, so a chunk's population loads wait for no other load.
 template <int S, int Q, bool TRT, bool BUF>
-__device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk) {
-  const int nch = d.cnt[CNT_CHUNKS];
+__device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk, int nch) {
   const int lane = threadIdx.x & 63;
   const XcdRange q = xcd_range(nch, blk, nblk, threadIdx.x >> 6, kBlock / 64);
-  for (int w = q.first; w < q.end; w += q.step) {
-    const int64_t c = (int64_t)d.chunk_list[w] * 64 + lane;
-    liquid_cell<S, Q, TRT, BUF>(d, c, c < d.g.N);
+  for (int w0 = q.first; w0 < q.end; w0 += 64 * q.step) {
+    const int wl = w0 + lane * q.step;
+    const int32_t ch = wl < q.end ? d.chunk_list[wl] : 0;
+    const uint64_t mk = wl < q.end ? d.chunk_mask[wl] : 0ull;
+    const uint32_t mlo = (uint32_t)mk, mhi = (uint32_t)(mk >> 32);
+    for (int it = 0; it < 64 && w0 + it * q.step < q.end; ++it) {
+      const int32_t chunk = __builtin_amdgcn_readlane(ch, it);
+      const uint32_t half = lane < 32 ? __builtin_amdgcn_readlane(mlo, it) : __builtin_amdgcn_readlane(mhi, it);
+      liquid_cell<S, Q, TRT, BUF>(d, (int64_t)chunk * 64 + lane, ((half >> (lane & 31)) & 1u) != 0);
+    }
   }
 }
 
@@ -622,18 +634,22 @@ __device__ __forceinline__ bool halted(const Dev& d) { return d.cnt[CNT_HALT0 + 
 
 template <int S, int Q, bool TRT, bool BUF>
 __device__ __forceinline__ void stream_body(const Dev& d, int b, int nb, int gen, int bord) {
-  if (halted(d)) return;
+  // the halt word and the list counts in one round trip
+  const int32_t halt = d.cnt[CNT_HALT0 + (d.step & 1)];
+  const int32_t n_if = d.cnt[CNT_IF], n_gen = d.cnt[CNT_GEN], n_conv = d.cnt[CNT_CONV];
+  const int32_t n_ch = d.cnt[CNT_CHUNKS];
+  if (halt != 0) return;
   if (b == 0 && threadIdx.x == 0) {
     d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // mark slot of the next step
     d.cnt[CNT_NG] = 0;                          // new-cell lists of this step
     d.cnt[CNT_NL] = 0;
   }
   if (b < gen)
-    generic_role<S, Q, TRT>(d, b, gen);
+    generic_role<S, Q, TRT>(d, b, gen, n_if);
   else if (b < gen + bord)
-    border_role<S, Q, TRT>(d, b - gen, bord);
+    border_role<S, Q, TRT>(d, b - gen, bord, n_gen, n_conv);
   else
-    liquid_role<S, Q, TRT, BUF>(d, b - gen - bord, nb - gen - bord);
+    liquid_role<S, Q, TRT, BUF>(d, b - gen - bord, nb - gen - bord, n_ch);
 }
 
 template <int S, int Q, bool TRT, bool BUF>
@@ -1160,6 +1176,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   uint32_t keep[5][kBatch];  // the four lists, and interface cells with the BORDER bit
   uint32_t c[4] = {0, 0, 0, 0};
   uint32_t own_any = 0;
+  uint32_t own_bits = 0;  // (per < 64) liquid-lane mask of this thread's cells
   {
     uint32_t chunk_any = 0;
 #pragma unroll 1
@@ -1189,6 +1206,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
         c[1] += __popc(m[1]);
         c[3] += __popc(m[3]);
         own_any |= m[2];
+        if (per < 64 && v0 + u < nvec) own_bits |= m[2] << (16 * (v0 + u));  // nvec <= 2 here
         chunk_any |= m[2];
         if (per >= 64 && (u & 3) == 3) {
           c[2] += chunk_any ? 1u : 0u;
@@ -1197,12 +1215,19 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
       }
     }
   }
-  // chunk count: a chunk shared by tpc threads is counted by the first
+  // chunk count: a chunk shared by tpc threads is counted by the first,
+  // which also gathers the chunk's liquid-lane mask
   uint32_t lead_any = own_any ? 1u : 0u;
+  uint64_t lead_bits = 0;
   if (per < 64) {
     if (tpc >= 2) lead_any |= __shfl_xor(lead_any, 1, 64);
     if (tpc >= 4) lead_any |= __shfl_xor(lead_any, 2, 64);
     c[2] = ((threadIdx.x % tpc) == 0) ? lead_any : 0u;
+    const int lane = threadIdx.x & 63;
+    for (int k = 0; k < tpc; ++k) {
+      const uint32_t bk = (uint32_t)__shfl((int)own_bits, (lane + k) & 63, 64);
+      lead_bits |= (uint64_t)bk << (per * k);
+    }
   }
   uint32_t pre[4], tot[4];
   if (per <= 32) {
@@ -1262,6 +1287,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   // later batches reloaded: the flags are still in cache)
   {
     uint32_t chunk_any = 0;
+    uint64_t chunk_bits = 0;
 #pragma unroll 1
     for (int v0 = 0; v0 < nvec; v0 += kBatch) {
       uint32_t m[5][kBatch];
@@ -1297,15 +1323,23 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
         for (uint32_t mm = m[3][u]; mm; mm &= mm - 1) d.gen_list[off[3]++] = (int32_t)(b0 + __builtin_ctz(mm));
         if (per >= 64) {
           chunk_any |= m[2][u];
+          chunk_bits |= (uint64_t)m[2][u] << (16 * (u & 3));
           if ((u & 3) == 3 || b0 + 16 >= N) {
-            if (chunk_any) d.chunk_list[off[2]++] = (int32_t)(b0 / 64);
+            if (chunk_any) {
+              d.chunk_mask[off[2]] = chunk_bits;
+              d.chunk_list[off[2]++] = (int32_t)(b0 / 64);
+            }
             chunk_any = 0;
+            chunk_bits = 0;
           }
         }
       }
     }
   }
-  if (per < 64 && c[2]) d.chunk_list[off[2]] = (int32_t)(base / 64);
+  if (per < 64 && c[2]) {
+    d.chunk_mask[off[2]] = lead_bits;
+    d.chunk_list[off[2]] = (int32_t)(base / 64);
+  }
   if (tile == nb - workers - 1 && threadIdx.x == kCompBlock - 1) {
     d.cnt[CNT_IF] = (int32_t)off[0];
     d.cnt[CNT_CONV] = (int32_t)off[1];

@@ -26,7 +26,7 @@ inline int storage_bytes(int storage) { return storage == FSLBM_F64 ? 8 : (stora
 struct Layout {
   int64_t N, stride, tiles, conv_per, red_blocks;
   size_t off_fA, off_fB, off_flags, off_mark, off_cls, off_phiA, off_phiB, off_m, off_rho_if,
-      off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_gen_list,
+      off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_chunk_mask, off_gen_list,
       off_mark_list, off_ng_list, off_nl_list, off_cnt, off_scan_status,
       off_pv, off_partial, off_stage, off_blab, off_bpar, off_btgt, off_bV, off_bW, off_bR, off_bnn,
       off_bamt, off_bpr, off_bhas, total;
@@ -65,6 +65,7 @@ inline Layout make_layout(const fslbm_params& p) {
   L.off_if_list = take(4 * L.N);
   L.off_conv_list = take(4 * L.N);
   L.off_chunk_list = take(4 * (L.N / 64 + 1));
+  L.off_chunk_mask = take(8 * (L.N / 64 + 1));
   L.off_gen_list = take(4 * L.N);
   L.off_mark_list = take(4 * L.N);
   L.off_ng_list = take(4 * L.N);

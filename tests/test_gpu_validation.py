@@ -2,7 +2,8 @@
 variants: the Reynolds number of the rising bubble against the paper's table,
 and the variants in the paper's order (OM > OM3 > NBRC > NBKC). The paper's
 gravity wave (Sec. 4.1) at wavelength 200: the surface elevation at x = 0
-against the analytic model the paper compares with."""
+against the analytic model the paper compares with and against the paper's
+own simulated series (tests/golden/gravity_wave_paper_curves.json)."""
 import numpy as np
 import pytest
 
@@ -25,10 +26,22 @@ def test_taylor_bubble_reynolds_as_in_the_paper():
     assert re[I.OM] > re[I.OM3] > re[I.NBRC] > re[I.NBKC]
 
 
-def test_gravity_wave_follows_the_analytic_model():
-    from paper_2207_13962_amd.validation import gravity_wave_elevation, wave_errors
+def test_gravity_wave_follows_the_analytic_model_and_the_papers_runs():
+    """Besides the analytic model: the paper's own simulated elevation series
+    of the same variant and L (its Sec. 4.1 convergence figures, golden
+    fixture) lies closer to this run than the paper's series of the other
+    variants lie to it (RMS and max over t* in (0, 12])."""
+    import json
+    import os
+    from paper_2207_13962_amd.validation import gravity_wave_elevation, paper_curve_distances, wave_errors
+    curves = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                         "gravity_wave_paper_curves.json")))["variants"]
     for v in (I.NBRC, I.NBKC, I.OM, I.OM3):
         r = gravity_wave_elevation(200, variant=v, t_end=12.0)
+        dp = paper_curve_distances(r, v, 200, curves, t_max=12.0)
+        # measured: RMS 0.046-0.064 against spreads of 0.12-0.19
+        assert dp["rms_to_paper"] < dp["paper_variant_spread_rms"], (I.VARIANT_NAMES[v], dp)
+        assert dp["max_to_paper"] < dp["paper_variant_spread_max"], (I.VARIANT_NAMES[v], dp)
         assert r["status"] == 0
         assert abs(r["a_sim"][0] - 1.0) < 1e-3
         e = wave_errors(r, windows=(12.0,))
