@@ -85,6 +85,7 @@ def run_batched(reqs, arrival, budget_bytes, max_slots=64, ticks=16, device="cud
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     finished = 0
+    occupancy = []  # (s, pool bytes in use, resident runs, queued runs) after each advance
     while finished < n:
         now = time.perf_counter() - t0
         while nxt < n and arrival[order[nxt]] <= now:
@@ -99,6 +100,8 @@ def run_batched(reqs, arrival, budget_bytes, max_slots=64, ticks=16, device="cud
                 time.sleep(max(0.0, arrival[order[nxt]] - (time.perf_counter() - t0)))
             continue
         srv.advance(ticks)
+        st = srv.stats()
+        occupancy.append((time.perf_counter() - t0, st["bytes_in_use"], st["resident"], st["queued"]))
         for rid, status in srv.poll():
             i = id2idx.pop(rid)
             rep, phi = srv.result(rid, phi=keep_phi)
@@ -113,8 +116,30 @@ def run_batched(reqs, arrival, budget_bytes, max_slots=64, ticks=16, device="cud
     srv.close()
     out = _summary(arrival, done_t, t_end, "batched")
     out.update(peak_resident=peak_resident, peak_pool_bytes=st["peak_bytes_in_use"],
-               budget_bytes=st["budget_bytes"], ticks=st["ticks"])
+               budget_bytes=st["budget_bytes"], ticks=st["ticks"],
+               occupancy=occupancy_timeline(occupancy, t_end))
     return out, results
+
+
+def occupancy_timeline(samples, t_end, points=24):
+    """Pool use over time: for each of `points` equal time bins the largest
+    bytes in use, resident and queued runs seen in it (GB, counts), and the
+    time-weighted mean pool use."""
+    if not samples:
+        return {}
+    edges = np.linspace(0.0, t_end, points + 1)
+    rows = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        sel = [x for x in samples if a <= x[0] < b]
+        if sel:
+            rows.append([round(float(b), 3), round(max(x[1] for x in sel) / 1e9, 3), max(x[2] for x in sel),
+                         max(x[3] for x in sel)])
+    ts = np.array([x[0] for x in samples])
+    used = np.array([x[1] for x in samples], dtype=np.float64)
+    dt = np.diff(np.concatenate([[0.0], ts]))
+    return {"bins_t_end_s_peak_GB_resident_queued": rows,
+            "mean_GB": float((used * dt).sum() / max(dt.sum(), 1e-12) / 1e9),
+            "peak_GB": float(used.max() / 1e9)}
 
 
 def run_sequential(reqs, arrival, device="cuda:0", keep_phi=False, progress=32):
