@@ -499,7 +499,8 @@ def _line(name, setup, variants, steps, warmup, ksteps, graphs):
 
 def extra_lines(args):
     """Throughput of the other measured workloads (each within its stable
-    window): the dam break in FP64 (the paper's precision), the cylindrical
+    window): the dam break in FP64 (the paper's precision) and with one
+    population grid updated in place (FP32 and FP16-shifted), the cylindrical
     dam break (D3Q27, free-slip walls, conversion-heavy) and the Taylor bubble
     (D3Q27, surface tension, single-bubble volume pressure) in its three
     storage formats. Context for the headline line."""
@@ -515,8 +516,14 @@ def extra_lines(args):
         t = cache["t"]
         return I.Setup(t.params.with_(storage=st), t.type, t.phi, t.rho, t.ux, t.uy, t.uz)
 
+    def inplace(st):
+        d = I.workload("dam256", storage=st, **les)
+        return I.Setup(d.params.with_(layout=I.AA), d.type, d.phi, d.rho, d.ux, d.uy, d.uz)
+
     todo = [
         ("dam256_fp64", lambda: I.workload("dam256", storage=I.F64, **les), [1, 2, 3, 4], 200, 100),
+        ("dam256_inplace_fp32", lambda: inplace(I.F32), [1, 2, 3, 4], 200, 100),
+        ("dam256_inplace_f16s", lambda: inplace(I.F16S), [1, 2, 3, 4], 200, 100),
         ("cyl256_fp32", lambda: I.workload("cyl256", **les), [1, 2, 3, 4], 200, 100),
         ("taylor512_fp64", lambda: taylor(I.F64), [3], 200, 50),
         ("taylor512_fp32", lambda: taylor(I.F32), [3], 200, 50),
@@ -526,11 +533,17 @@ def extra_lines(args):
         try:
             s = fn()
             p = s.params
-            desc = "%s: %dx%dx%d%s%s" % (name.split("_")[0], p.nx, p.ny, p.nz,
-                                         ", Smagorinsky C_S = %g" % p.smagorinsky if p.smagorinsky else "",
-                                         ", surface tension %g, single-bubble volume pressure" % p.sigma
-                                         if p.sigma else "")
+            desc = "%s: %dx%dx%d%s%s%s" % (name.split("_")[0], p.nx, p.ny, p.nz,
+                                           ", Smagorinsky C_S = %g" % p.smagorinsky if p.smagorinsky else "",
+                                           ", surface tension %g, single-bubble volume pressure" % p.sigma
+                                           if p.sigma else "",
+                                           ", one population grid updated in place (AA pattern)"
+                                           if p.layout == I.AA else "")
             out[name] = _line(desc, s, variants, steps, warm, min(steps, 100), graphs)
+            if p.layout == I.AA:
+                from paper_2207_13962_amd.fslbm import workspace_bytes
+                two = workspace_bytes(p.with_(layout=I.TWO_GRID))
+                out[name]["device_bytes"] = {"in_place": workspace_bytes(p), "two_grid": two}
             print("line %s: %.0f MLUPS, k_stream %.2f of peak" % (
                 name, out[name]["value"], out[name]["roofline"]["frac"]), file=sys.stderr, flush=True)
         except Exception as e:  # context only: never hides the headline result
@@ -540,8 +553,8 @@ def extra_lines(args):
 
 def serving_section(args, reqs=None):
     """Batched serving against one-at-a-time solves on a request mix shaped
-    like the serving workload (drop impacts and wave slabs, variants uniform,
-    FP32): closed batches (every run arriving at t = 0) give each mode's
+    like the serving workload (drop impacts with FP64 populations and wave
+    slabs with FP32, variants uniform): closed batches (every run arriving at t = 0) give each mode's
     capacity in runs/s; then Poisson arrivals at `load` times the batched
     capacity are served both ways: runs/s over the makespan, p50/p99 time to
     solution (queueing included). The fill levels of every run must agree
@@ -572,7 +585,7 @@ def serving_section(args, reqs=None):
              for r in reqs]
     return {
         "workload": "%d runs: drop impacts (L^3) and wave slabs (L x L/2 x L/4), L in [%d, %d], "
-                    "%d-%d steps, D3Q19 FP32 (drops TRT, waves SRT), variants uniform" % (
+                    "%d-%d steps, D3Q19 (drops TRT with FP64 populations, waves SRT with FP32), variants uniform" % (
                         len(reqs), args.l_min, args.l_max, args.steps_min, args.steps_max),
         "cells_total": int(sum(cells)),
         "steps_total": int(sum(r["steps"] for r in reqs)),

@@ -20,7 +20,9 @@
  *  - A context is not thread-safe; separate contexts may run concurrently on
  *    separate streams.
  *  - Populations are kept in device memory as the POST-collision state f* of
- *    the current step (structure of arrays, q planes of N values); reported
+ *    the current step (structure of arrays, q planes of N values; in the
+ *    in-place layout a value's plane and cell alternate with the step parity,
+ *    see fslbm_params.layout); reported
  *    fields are the pre-collision moments rho = sum f*, u = (sum c f* - rho g/2)/rho,
  *    which equal the moments of the populations after streaming.
  */
@@ -34,14 +36,15 @@
 extern "C" {
 #endif
 
-#define FSLBM_ABI_VERSION 1
+#define FSLBM_ABI_VERSION 2
 
 typedef struct fslbm_ctx fslbm_ctx;
 
 enum {
   FSLBM_OK = 0,
   FSLBM_EINVAL = -1,    /* bad argument or parameter, or initial state violating the closed layer */
-  FSLBM_ENOMEM = -2,    /* device allocation failed, or the caller's arena is too small */
+  FSLBM_ENOMEM = -2,    /* device allocation failed, the caller's arena is too small, or
+                           (in-place layout) the interface outgrew the stash (sticky) */
   FSLBM_EDEVICE = -3,   /* HIP runtime error (launch, copy, fault reported by the runtime) */
   FSLBM_EUNSTABLE = -4, /* NaN, rho <= 0 or |u| >= c_s seen on the device (sticky) */
   FSLBM_ESTATE = -5,    /* call not valid in the context's state (e.g. after a device error) */
@@ -57,6 +60,9 @@ enum { FSLBM_SRT = 0, FSLBM_TRT = 1 };
 enum { FSLBM_F64 = 0, FSLBM_F32 = 1, FSLBM_F16S = 2 };
 /* Domain faces. */
 enum { FSLBM_PERIODIC = 0, FSLBM_WALL_NOSLIP = 1, FSLBM_WALL_FREESLIP = 2 };
+/* Population layout: two grids (each step reads one and writes the other) or one
+ * grid updated in place (AA pattern). */
+enum { FSLBM_TWO_GRID = 0, FSLBM_AA = 1 };
 
 typedef struct {
   uint32_t abi_version;  /* must equal FSLBM_ABI_VERSION */
@@ -82,6 +88,21 @@ typedef struct {
   double tie_delta;      /* |n.c_i| <= tie_delta*max|n_a| counts as n.c_i = 0; 0 -> 1e-9 */
   double smagorinsky;    /* Smagorinsky constant C_S (Sec. 2.1 turbulence model), 0 = off;
                             the local tau replaces tau (TRT keeps trt_lambda) */
+  int32_t layout;        /* FSLBM_TWO_GRID, or FSLBM_AA: one population grid, updated in
+                            place (not in the paper, which does not fix a layout). A step
+                            from an even step count pulls from the neighbours and writes
+                            each outgoing value into the slot its opposite came from; a
+                            step from an odd count reads and writes the cell's own slots.
+                            The interface cells' own post-collision populations, which
+                            the free-surface condition and the mass exchange (Sec. 2.2)
+                            need after neighbours have overwritten them, are kept in two
+                            stash buffers of max(N/8, 65536) cells (at most N) with a
+                            per-cell entry index; a domain whose interface outgrows them
+                            fails (at creation, or the run stops) with
+                            FSLBM_ENOMEM. fslbm_create refuses (FSLBM_EINVAL) walls and
+                            obstacles for which pull streaming takes some population
+                            twice (free-slip faces or obstacles meeting obstacles at
+                            corners). Results are bitwise those of FSLBM_TWO_GRID. */
 } fslbm_params;
 
 typedef struct {

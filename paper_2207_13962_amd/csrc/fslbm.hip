@@ -117,7 +117,11 @@ void bind(fslbm_ctx* c) {
   d.thurey = c->p.thurey_flux;
   d.bubble = c->p.bubble_model;
   d.fA = a + L.off_fA;
-  d.fB = a + L.off_fB;
+  d.fB = a + L.off_fB;  // the same grid in place
+  d.aa = c->p.layout == FSLBM_AA ? 1 : 0;
+  d.stash_cap = (int32_t)L.stash_cap;
+  d.stash = d.aa ? a + L.off_stash : nullptr;
+  d.prevpos = d.aa ? reinterpret_cast<int32_t*>(a + L.off_prevpos) : nullptr;
   d.flags = reinterpret_cast<uint8_t*>(a + L.off_flags);
   d.mark = reinterpret_cast<uint8_t*>(a + L.off_mark);
   d.cls = reinterpret_cast<uint8_t*>(a + L.off_cls);
@@ -274,6 +278,14 @@ int read_status(fslbm_ctx* c) {
     c->status = FSLBM_EDEVICE;
     return set_err(c, FSLBM_EDEVICE, "bubble labelling did not complete");
   }
+  if (err & ERR_STASH) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "in-place layout: more interface cells than a stash buffer holds (%lld) by step %lld; the "
+             "run stopped",
+             (long long)c->L.stash_cap, (long long)c->step);
+    return set_err(c, FSLBM_ENOMEM, buf);
+  }
   if (err & (ERR_UNSTABLE | ERR_LAYER)) {
     char buf[160];
     snprintf(buf, sizeof buf, "instability detected by step %lld (%s)", (long long)c->step,
@@ -376,6 +388,12 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   INITCHK(hipMemcpyAsync(c->d.phiB, uz, 8 * N, hipMemcpyHostToDevice, s));
   ops.init_flags(c, s);
   hipLaunchKernelGGL(k_apply_border, dim3(grid_for(N)), dim3(kBlock), 0, s, c->d);
+  if (c->d.aa) {
+    // every slot of the in-place layout has one (cell, direction) pair
+    const size_t words = ((size_t)c->p.q * c->L.stride + 31) / 32;
+    INITCHK(hipMemsetAsync(stage(c), 0, 4 * words, s));
+    ops.aa_check(c, s, reinterpret_cast<uint32_t*>(stage(c)));
+  }
   int32_t cnt[CNT_N];
   INITCHK(hipMemcpyAsync(cnt, c->d.cnt, sizeof cnt, hipMemcpyDeviceToHost, s));
   INITCHK(hipStreamSynchronize(s));
@@ -385,6 +403,12 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   }
   if (cnt[CNT_ERR] & ERR_LAYER) {
     c->last_error = "a liquid cell touches a gas cell: the interface layer is not closed";
+    return fail(FSLBM_EINVAL);
+  }
+  if (cnt[CNT_ERR] & ERR_SLOTS) {
+    c->last_error =
+        "in-place layout: with these walls and obstacles pull streaming takes some population twice "
+        "(free-slip faces or obstacles meeting other obstacles); use FSLBM_TWO_GRID";
     return fail(FSLBM_EINVAL);
   }
   const bool resume = pdf_or_null != nullptr;
@@ -403,6 +427,7 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   c->d.step = 0;
   ops.convert(c, s, 1);
   ops.classes(c, s);
+  if (c->d.aa) ops.stash_init(c, s);  // the interface cells' own populations
   const double pv0[3] = {c->p.rho_gas / 3.0, c->p.rho_gas / 3.0, 0.0};
   INITCHK(hipMemcpyAsync(c->d.pV, pv0, sizeof pv0, hipMemcpyHostToDevice, s));
   // V(0) from phiB == phiA at this point
@@ -414,6 +439,17 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
   }
   INITCHK(hipGetLastError());
   INITCHK(hipStreamSynchronize(s));
+  if (c->d.aa) {
+    INITCHK(hipMemcpyAsync(cnt, c->d.cnt, sizeof cnt, hipMemcpyDeviceToHost, s));
+    INITCHK(hipStreamSynchronize(s));
+    if (cnt[CNT_ERR] & ERR_STASH) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "in-place layout: more interface cells than a stash buffer holds (%lld)",
+               (long long)c->L.stash_cap);
+      c->last_error = buf;
+      return fail(FSLBM_ENOMEM);
+    }
+  }
 #undef INITCHK
   *out = c;
   return FSLBM_OK;
@@ -438,6 +474,7 @@ int fslbm_step(fslbm_ctx* c, int64_t nsteps) {
 int fslbm_mass(fslbm_ctx* c, fslbm_mass_report* r) {
   if (!c || !r) return FSLBM_EINVAL;
   if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  c->d.step = c->step;  // kernels below read the state before step c->step
   const Ops ops = pick(c->p);
   hipStream_t s = c->stream;
   ops.reduce_mass(c->d, c->L.red_blocks, s);
@@ -478,6 +515,7 @@ int fslbm_mass_noalloc(fslbm_ctx* c, double* out_device) {
   hipStream_t s = c->stream;
   // the reduction of fslbm_mass (same blocks, same order), partials in the scratch
   Dev d = c->d;  // (a plain struct of pointers and numbers: no allocation)
+  d.step = c->step;  // the state before step c->step
   d.partial = scr;
   ops.reduce_mass(d, c->L.red_blocks, s);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, scr, (int)c->L.red_blocks, kRedN,
@@ -492,6 +530,7 @@ int fslbm_fields(fslbm_ctx* c, uint8_t* type, double* phi, double* rho, double* 
                  double* uz, double* mass, double* pdf) {
   if (!c) return FSLBM_EINVAL;
   if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  c->d.step = c->step;  // kernels below read the state before step c->step
   const Ops ops = pick(c->p);
   hipStream_t s = c->stream;
   const int64_t N = c->L.N;
@@ -624,6 +663,7 @@ int fslbm_kernel_time(fslbm_ctx* c, int64_t* launches, double* total_ms) {
 int fslbm_get_scalars(fslbm_ctx* c, double out[4]) {
   if (!c || !out) return FSLBM_EINVAL;
   if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
+  c->d.step = c->step;  // kernels below read the state before step c->step
   const Ops ops = pick(c->p);
   hipStream_t s = c->stream;
   ops.reduce_mass(c->d, c->L.red_blocks, s);
@@ -761,11 +801,12 @@ struct DoneRun {
   std::vector<double> phi;
 };
 
-// launch groups: storage (3) x lattice (2) x collision (2) x addressing (2)
-constexpr int kGroups = 24;
+// launch groups: storage (3) x lattice (2) x collision (2) x layout (2) x addressing (2)
+constexpr int kGroups = 48;
 
 int group_of(const fslbm_params& p, bool buf) {
-  return ((p.storage * 2 + (p.q == 27 ? 1 : 0)) * 2 + (p.collision == FSLBM_TRT ? 1 : 0)) * 2 + (buf ? 1 : 0);
+  return (((p.storage * 2 + (p.q == 27 ? 1 : 0)) * 2 + (p.collision == FSLBM_TRT ? 1 : 0)) * 2 +
+          (p.layout == FSLBM_AA ? 1 : 0)) * 2 + (buf ? 1 : 0);
 }
 
 bool grid_fits_buffer(const fslbm_ctx* c) {
@@ -837,6 +878,7 @@ int rebuild_plan(fslbm_server* s) {
     bl = BatchLaunch{};
     bl.devs = s->d_devs;
     bl.buf = (g & 1) != 0;
+    bl.aa = (g & 2) != 0;
     int cursor[kLaunches] = {0, 0, 0};
     int xcursor[kAux] = {0, 0, 0, 0};
     for (const ResidentRun& r : s->resident) {

@@ -37,7 +37,8 @@ __device__ __forceinline__ BatchEntry batch_entry(const BatchEntry* tab, int n) 
   return tab[lo];
 }
 
-// The run's Dev at this tick (grids and fill levels swapped on odd steps);
+// The run's Dev at this tick (grids and fill levels swapped on odd steps; the
+// two grid pointers of an in-place run are the same);
 // false when the block lies past the run's range or the run is done.
 __device__ __forceinline__ bool batch_dev(const Dev* devs, const BatchEntry& e, int64_t tick, Dev& d) {
   const int b = (int)blockIdx.x - e.blk0;
@@ -57,14 +58,15 @@ __device__ __forceinline__ bool batch_dev(const Dev* devs, const BatchEntry& e, 
   return true;
 }
 
-template <int S, int Q, bool TRT, bool BUF>
+template <int S, int Q, bool TRT, bool BUF, bool AA>
 __global__ __launch_bounds__(kBlock) void kb_stream(const Dev* devs, const BatchEntry* tab, int n,
                                                     int64_t tick) {
   const BatchEntry e = batch_entry(tab, n);
   Dev d;
   if (!batch_dev(devs, e, tick, d)) return;
-  stream_body<S, Q, TRT, BUF>(d, (int)blockIdx.x - e.blk0, e.nblk, e.a, e.b);
+  stream_body<S, Q, TRT, BUF, AA>(d, (int)blockIdx.x - e.blk0, e.nblk, e.a, e.b);
 }
+
 
 template <int Q>
 __global__ __launch_bounds__(kBlock) void kb_retype(const Dev* devs, const BatchEntry* tab, int n,
@@ -75,13 +77,13 @@ __global__ __launch_bounds__(kBlock) void kb_retype(const Dev* devs, const Batch
   retype_body<Q>(d, (int)blockIdx.x - e.blk0, e.nblk, 0);
 }
 
-template <int S, int Q, bool TRT>
+template <int S, int Q, bool TRT, bool AA>
 __global__ __launch_bounds__(kCompBlock) void kb_compact(const Dev* devs, const BatchEntry* tab, int n,
                                                          int64_t tick) {
   const BatchEntry e = batch_entry(tab, n);
   Dev d;
   if (!batch_dev(devs, e, tick, d)) return;
-  compact_body<S, Q, TRT>(d, (int)blockIdx.x - e.blk0, e.nblk, 0, e.a, e.b);
+  compact_body<S, Q, TRT, AA>(d, (int)blockIdx.x - e.blk0, e.nblk, 0, e.a, e.b);
 }
 
 #ifdef FSLBM_HOST_KERNELS

@@ -79,9 +79,14 @@ enum {
   CNT_NG = 9,      // new interface cells from gas in this step
   CNT_HALT0 = 10,  // halt words, slot (step & 1): the run stopped after an instability
   CNT_NL = 12,     // new interface cells from liquid in this step
+  CNT_SBASE = 13,  // in place: interface cells of this step (stash entries written by the step)
+  CNT_SNEW = 14,   // in place: stash entries taken by this step's new interface cells
   CNT_N = 16
 };
-enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8, ERR_BUBBLE = 16 };
+// ERR_STASH: in-place layout, more interface cells than a stash buffer holds;
+// ERR_SLOTS: in-place layout, two (cell, direction) pairs stream through one slot
+enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8, ERR_BUBBLE = 16, ERR_STASH = 32,
+       ERR_SLOTS = 64 };
 
 // ---------------------------------------------------------------------------
 // Population storage. R is the arithmetic type; kShift tells whether the
@@ -267,10 +272,14 @@ __device__ __forceinline__ int nb_type(const Geom& g, const uint8_t* flags, int 
 // (directly or after reflection) is reported as SRC_GAS.
 enum { SRC_FLUID = 0, SRC_GAS = 1, SRC_BOUNCE = 2 };
 
-// Specular part of resolve_source (free-slip source).
+// Mirrored source at a free-slip obstacle: the axes along which the one-axis
+// step back from x is an obstacle are mirrored. False when no axis is (a
+// diagonal obstacle) or the mirrored point is an obstacle: bounce-back.
+// Otherwise *src, *dir (the direction the population leaves *src in) and
+// *type (gas or fluid) of the mirrored cell.
 template <int Q>
-__device__ __forceinline__ int reflect_source(const Geom& g, const uint8_t* flags, int x, int y, int z,
-                                           int k, int64_t* src, int* dir) {
+__device__ __forceinline__ bool mirror_source(const Geom& g, const uint8_t* flags, int x, int y, int z, int k,
+                                              int64_t* src, int* dir, int* type) {
   const int c[3] = {cxd(k), cyd(k), czd(k)};
   int d[3] = {-c[0], -c[1], -c[2]};
   int cj[3] = {c[0], c[1], c[2]};
@@ -286,17 +295,56 @@ __device__ __forceinline__ int reflect_source(const Geom& g, const uint8_t* flag
       any = true;
     }
   }
-  if (!any) return SRC_BOUNCE;
+  if (!any) return false;
   int64_t yi;
-  int ty = nb_type(g, flags, x, y, z, d[0], d[1], d[2], &yi);
-  if (is_obst(ty)) return SRC_BOUNCE;
-  if (ty == T_GAS) return SRC_GAS;
-  *src = yi;
+  const int ty = nb_type(g, flags, x, y, z, d[0], d[1], d[2], &yi);
+  if (is_obst(ty)) return false;
   int r = 0;
   for (int i = 0; i < Q; ++i)
     if (cxd(i) == cj[0] && cyd(i) == cj[1] && czd(i) == cj[2]) r = i;
+  *src = yi;
+  *dir = r;
+  *type = ty;
+  return true;
+}
+
+// Specular part of resolve_source (free-slip source).
+template <int Q>
+__device__ __forceinline__ int reflect_source(const Geom& g, const uint8_t* flags, int x, int y, int z,
+                                           int k, int64_t* src, int* dir) {
+  int64_t yi;
+  int r, ty;
+  if (!mirror_source<Q>(g, flags, x, y, z, k, &yi, &r, &ty)) return SRC_BOUNCE;
+  if (ty == T_GAS) return SRC_GAS;
+  *src = yi;
   *dir = r;
   return SRC_FLUID;
+}
+
+// In-place (AA) layout: the element through which the population arriving at
+// cell c = (x, y, z) in direction k streams. A step from an even step count
+// reads it there and stores the cell's outgoing population of direction
+// opp(k) into it; the step from an odd count finds the arriving population in
+// the cell's own entry of plane opp(k). The slot is the plane-k entry of the
+// source c - c_k inside the domain (after periodic wrap; gas or fluid), the
+// cell's own plane-opp(k) entry where the source is a no-slip wall or
+// obstacle (bounce-back), or the mirrored cell's entry at a free-slip one.
+// Obstacles are static, so a slot never changes during a run, and the map
+// (cell, k) -> slot is one to one, as pull streaming with these walls
+// consumes every post-collision population once.
+template <int Q>
+__device__ __forceinline__ int64_t aa_slot(const Geom& g, const uint8_t* flags, int x, int y, int z,
+                                           int64_t c, int k) {
+  int w;
+  const int64_t j = nb_index(g, x, y, z, -cxd(k), -cyd(k), -czd(k), &w);
+  const int st = j >= 0 ? (flags[j] & T_MASK) : w;
+  if (!is_obst(st)) return (int64_t)k * g.stride + j;
+  if (st == T_FREESLIP) {
+    int64_t yi;
+    int r, ty;
+    if (mirror_source<Q>(g, flags, x, y, z, k, &yi, &r, &ty)) return (int64_t)r * g.stride + yi;
+  }
+  return (int64_t)opp(k) * g.stride + c;
 }
 
 template <int Q>

@@ -27,6 +27,8 @@
 // device, so a step needs no host synchronisation.
 #pragma once
 
+#include <type_traits>
+
 #include "fslbm_device.h"
 
 namespace fslbm {
@@ -44,7 +46,15 @@ struct Dev {
   int variant, thurey, bubble;
   // state
   void* fA;  // post-collision populations at t (read)
-  void* fB;  // post-collision populations at t+1 (written)
+  void* fB;  // post-collision populations at t+1 (written); in place (aa): fA
+  int aa;    // 1: one grid updated in place (AA pattern), slots as aa_slot
+  int32_t stash_cap;  // in place: entries of one stash buffer
+  // in place: two stash buffers (by step parity) of stash_cap entries of q
+  // populations: each interface cell's own post-collision populations, which
+  // its neighbours overwrite in the grid during the step; prevpos[c] is the
+  // entry of cell c in the buffer the step reads
+  void* stash;
+  int32_t* prevpos;
   uint8_t* flags;
   uint8_t* mark;
   uint8_t* cls;
@@ -182,6 +192,130 @@ __device__ __forceinline__ void liquid_cell(const Dev& d, int64_t c, bool mine) 
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
+  }
+}
+
+// In-place layout: element of the post-collision population f*_k(c) of the
+// state before a step of parity `par` (cell c with flag byte fl): plane k of c
+// after an odd step (or at the start), else the slot through which the cell's
+// arrival from direction opp(k) streamed, where the even step stored it (for
+// a cell without the BORDER bit, plane opp(k) of its neighbour c + c_k).
+template <int Q>
+__device__ __forceinline__ int64_t own_slot(const Dev& d, int64_t c, uint8_t fl, int k, int par) {
+  const int64_t stride = d.g.stride;
+  if (!d.aa || par == 0) return (int64_t)k * stride + c;
+  if (!(fl & F_BORDER))
+    return (int64_t)opp(k) * stride + c + cxd(k) + cyd(k) * (int64_t)d.g.nx + czd(k) * (int64_t)d.g.nx * d.g.ny;
+  int x, y, z;
+  coords(d.g, c, x, y, z);
+  return aa_slot<Q>(d.g, d.flags, x, y, z, c, opp(k));
+}
+
+// In-place layout: entry e of the stash buffer of step parity par.
+template <int S, int Q>
+__device__ __forceinline__ typename Store<S, Q>::T* stash_buf(const Dev& d, int par) {
+  return static_cast<typename Store<S, Q>::T*>(d.stash) + (int64_t)par * d.stash_cap * Q;
+}
+
+// liquid_cell in the in-place layout. Even step: the arrival from direction
+// k is read from its slot (the pull source, or the cell's own opposite
+// population on a no-slip face), and the outgoing population of direction
+// opp(k) is stored into that slot after the collision. Odd step: arrivals are
+// the cell's own plane-opp(k) entries, outgoing populations go to its own
+// plane-k entries (walls were handled by the even step's placement).
+template <int S, int Q, bool TRT, bool BUF>
+__device__ __forceinline__ void liquid_cell_aa(const Dev& d, int64_t c, bool mine) {
+  using St = Store<S, Q>;
+  using T = typename St::T;
+  using R = typename St::R;
+  const Geom& g = d.g;
+  const bool odd = (d.step & 1) != 0;
+  bool wall = false;
+  if (mine && !odd) {
+    int x, y, z;
+    coords(g, c, x, y, z);
+    wall = x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
+  }
+  const bool any_wall = !odd && __ballot(wall) != 0ull;
+  if (!mine) return;
+  T* F = static_cast<T*>(d.fA);
+  const int64_t stride = g.stride;
+  const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
+  const uint32_t bytes = (uint32_t)(BUF ? Q * stride * (int64_t)sizeof(T) : 0);
+  const uint32_t vo = (uint32_t)c * (uint32_t)sizeof(T);
+  R f[Q];
+  if (odd) {
+    // own entries only: arrival k in plane opp(k)
+    if constexpr (BUF) {
+      const __amdgpu_buffer_rsrc_t ra = make_rsrc(F, bytes);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) f[k] = St::bld(ra, vo, (uint32_t)(opp(k) * stride * (int64_t)sizeof(T)));
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) f[k] = St::ld(F, opp(k) * stride + c, k);
+    }
+  } else if (!any_wall) {
+    // the pull sources, as the two-grid liquid cell
+    if constexpr (BUF) {
+      const __amdgpu_buffer_rsrc_t ra = make_rsrc(F, bytes);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const int64_t off = cxd(k) + cyd(k) * nx + czd(k) * nxy;
+        f[k] = St::bld(ra, vo, (uint32_t)((k * stride - off) * (int64_t)sizeof(T)));
+      }
+    } else {
+      load_plain<S, Q>(F, stride, c, g.nx, nxy, f);
+    }
+  } else {
+    int x, y, z;
+    coords(g, c, x, y, z);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int64_t off = cxd(k) + cyd(k) * nx + czd(k) * nxy;
+      const bool in = (unsigned)(x - cxd(k)) < (unsigned)g.nx && (unsigned)(y - cyd(k)) < (unsigned)g.ny &&
+                      (unsigned)(z - czd(k)) < (unsigned)g.nz;
+      f[k] = St::ld(F, in ? k * stride + c - off : opp(k) * stride + c, k);
+    }
+  }
+  CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
+  R rho, ux, uy, uz;
+  collide_any<R, Q, TRT, St::kShift>(f, cp, rho, ux, uy, uz);
+  if (unstable(rho, ux, uy, uz)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
+  if (odd) {
+    if constexpr (BUF) {
+      const __amdgpu_buffer_rsrc_t rb = make_rsrc(F, bytes);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) St::bst(rb, vo, (uint32_t)(k * stride * (int64_t)sizeof(T)), f[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) St::st(F, k * stride + c, k, f[k]);
+    }
+  } else if (!any_wall) {
+    // outgoing opp(k) into the slot arrival k came from
+    if constexpr (BUF) {
+      const __amdgpu_buffer_rsrc_t rb = make_rsrc(F, bytes);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const int64_t off = cxd(k) + cyd(k) * nx + czd(k) * nxy;
+        St::bst(rb, vo, (uint32_t)((k * stride - off) * (int64_t)sizeof(T)), f[opp(k)]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const int64_t off = cxd(k) + cyd(k) * nx + czd(k) * nxy;
+        St::st(F, k * stride + c - off, k, f[opp(k)]);
+      }
+    }
+  } else {
+    int x, y, z;
+    coords(g, c, x, y, z);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int64_t off = cxd(k) + cyd(k) * nx + czd(k) * nxy;
+      const bool in = (unsigned)(x - cxd(k)) < (unsigned)g.nx && (unsigned)(y - cyd(k)) < (unsigned)g.ny &&
+                      (unsigned)(z - czd(k)) < (unsigned)g.nz;
+      St::st(F, in ? k * stride + c - off : opp(k) * stride + c, k, f[opp(k)]);
+    }
   }
 }
 
@@ -370,7 +504,33 @@ __device__ __forceinline__ R gcollide(R f, int k, const CollideParams<R>& cp, R&
 // neighbours beyond a wall are replaced by the cell itself and the values
 // discarded); only a source reflected at a free-slip face needs a second
 // round.
-template <int S, int Q, bool TRT>
+// In-place layout, conversion of step `step`: a stash entry of the next
+// step's buffer for a new interface cell (after the entries of the cells
+// that were interface in this step), recorded in prevpos; -1 (and ERR_STASH)
+// when the buffer is full. Lane 0 of the calling group takes it.
+__device__ __forceinline__ int32_t new_stash_entry(const Dev& d, int64_t c, int l) {
+  int32_t pos = -1;
+  if (l == 0) {
+    pos = d.cnt[CNT_SBASE] + atomicAdd(&d.cnt[CNT_SNEW], 1);
+    if (pos >= d.stash_cap) {
+      atomicOr(&d.cnt[CNT_ERR], ERR_STASH);
+      pos = -1;
+    } else {
+      d.prevpos[c] = pos;
+    }
+  }
+  return __shfl(pos, 0, kG);
+}
+
+// AA: in-place layout. The cell's own post-collision populations come from
+// its stash entry (prevpos) of this step's buffer, written by the previous
+// step, since neighbours overwrite them in the grid during this launch; the
+// new ones also go to entry `item` of the next step's buffer. An even step
+// reads arrivals from their slots as the two-grid pull does and stores the
+// outgoing population of direction opp(k) into the slot of lane k; an odd
+// step reads arrivals from the cell's own plane-opp(k) entries and stores into
+// its own plane-k entries.
+template <int S, int Q, bool TRT, bool AA>
 __device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk, int nif) {
   using St = Store<S, Q>;
   using T = typename St::T;
@@ -378,6 +538,7 @@ __device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk, in
   constexpr bool SH = St::kShift;
   const T* A = static_cast<const T*>(d.fA);
   T* B = static_cast<T*>(d.fB);
+  const bool odd = AA && (d.step & 1) != 0;
   const Geom& g = d.g;
   const int64_t stride = g.stride;
   const int l = threadIdx.x & (kG - 1);
@@ -411,8 +572,15 @@ __device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk, in
     }
     const int64_t js = jd >= 0 ? jd : c, jbs = jb >= 0 ? jb : c;
     // the batch
-    const R fo = act ? St::ld(A, k * stride + c, k) : R(0);
-    const R fpull = act ? St::ld(A, k * stride + js, k) : R(0);
+    R fo, fpull;
+    if constexpr (AA) {
+      const int32_t pp = d.prevpos[c];
+      fo = act ? St::ld(stash_buf<S, Q>(d, (int)(d.step & 1)), (int64_t)pp * Q + k, k) : R(0);
+      fpull = act ? St::ld(A, odd ? opp(k) * stride + c : k * stride + js, k) : R(0);
+    } else {
+      fo = act ? St::ld(A, k * stride + c, k) : R(0);
+      fpull = act ? St::ld(A, k * stride + js, k) : R(0);
+    }
     const uint8_t flb = d.flags[jbs];
     const double phib = d.phiA[jbs];
     const uint8_t clsb = d.cls[jbs];
@@ -447,7 +615,8 @@ __device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk, in
     } else {
       kind = reflect_source<Q>(g, d.flags, x, y, z, k, &src, &dir);
       if (act && kind == SRC_FLUID) {
-        in_val = St::ld(A, dir * stride + src, dir);
+        // (in place, odd step: the even step put it into the cell's own entry)
+        in_val = odd ? fpull : St::ld(A, dir * stride + src, dir);
         fl_src = d.flags[src];
         cls_src = d.cls[src];
         phi_src = d.phiA[src];
@@ -543,6 +712,16 @@ __device__ __forceinline__ void generic_role(const Dev& d, int blk, int nblk, in
     R rho, vx, vy, vz;
     const R fs = gcollide<R, Q, TRT, SH>(f, l, cp, rho, vx, vy, vz);
     if (l == 0 && unstable(rho, vx, vy, vz)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
+    if constexpr (AA) {
+      if (act) St::st(stash_buf<S, Q>(d, (int)((d.step + 1) & 1)), (int64_t)item * Q + k, k, fs);
+      if (l == 0) d.prevpos[c] = item;
+      if (!odd) {
+        const R fsb = __shfl(fs, kb, kG);
+        const int64_t sl = list_border(e) ? aa_slot<Q>(g, d.flags, x, y, z, c, k) : k * stride + c - offd;
+        if (act) St::st(B, sl, k, fsb);
+        continue;
+      }
+    }
     if (act) St::st(B, k * stride + c, k, fs);
   }
 }
@@ -583,14 +762,74 @@ __device__ __forceinline__ void border_cell(const Dev& d, int64_t c) {
   for (int k = 0; k < Q; ++k) St::st(B, k * stride + c, k, f[k]);
 }
 
+// border_cell in the in-place layout: an even step reads each arrival from
+// its slot (for a liquid cell, whose box holds no gas, the resolved source is
+// the slot of aa_slot) and stores the outgoing population of the opposite
+// direction into it; an odd step uses the cell's own entries only. The even
+// step's stores resolve one slot at a time (not unrolled: wall cells are few,
+// and unrolled resolution would hold q addresses over the collision and cost
+// the whole launch a quarter of its waves).
+template <int S, int Q, bool TRT>
+__device__ __forceinline__ void border_cell_aa(const Dev& d, int64_t c) {
+  using St = Store<S, Q>;
+  using T = typename St::T;
+  using R = typename St::R;
+  T* F = static_cast<T*>(d.fA);
+  const Geom& g = d.g;
+  const int64_t stride = g.stride;
+  const bool odd = (d.step & 1) != 0;
+  R f[Q];
+  if (odd) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = St::ld(F, opp(k) * stride + c, k);
+  } else {
+    int x, y, z;
+    coords(g, c, x, y, z);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      int64_t src;
+      int dir;
+      bool wall;
+      const int kind = resolve_source<Q>(g, d.flags, x, y, z, k, &src, &dir, &wall);
+      if (kind == SRC_GAS) atomicOr(&d.cnt[CNT_ERR], ERR_LAYER);
+      if (kind != SRC_FLUID) {
+        src = c;
+        dir = opp(k);
+      }
+      f[k] = St::ld(F, dir * stride + src, dir);
+    }
+  }
+  CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
+  R rho, ux, uy, uz;
+  collide_any<R, Q, TRT, St::kShift>(f, cp, rho, ux, uy, uz);
+  if (unstable(rho, ux, uy, uz)) atomicOr(&d.cnt[CNT_ERR], ERR_UNSTABLE);
+  if (odd) {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) St::st(F, k * stride + c, k, f[k]);
+  } else {
+    int x, y, z;
+    coords(g, c, x, y, z);
+#pragma unroll 1
+    for (int k = 0; k < Q; ++k) {
+      R v = f[0];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v = (opp(k) == i) ? f[i] : v;
+      St::st(F, aa_slot<Q>(g, d.flags, x, y, z, c, k), k, v);
+    }
+  }
+}
+
 // Also clears the transient bits of the cells of the last converted list
 // (every transient bit is stale by now; readers in this kernel look at the
 // type bits only).
-template <int S, int Q, bool TRT>
+template <int S, int Q, bool TRT, bool AA>
 __device__ __forceinline__ void border_role(const Dev& d, int blk, int nblk, int n, int ncv) {
   for (int i = blk * kBlock + threadIdx.x; i < n + ncv; i += nblk * kBlock) {
     if (i < n) {
-      border_cell<S, Q, TRT>(d, d.gen_list[i]);
+      if constexpr (AA)
+        border_cell_aa<S, Q, TRT>(d, d.gen_list[i]);
+      else
+        border_cell<S, Q, TRT>(d, d.gen_list[i]);
     } else {
       const int32_t z = d.conv_list[i - n];
       d.flags[z] = (uint8_t)(d.flags[z] & ~F_TRANSIENT);
@@ -602,7 +841,7 @@ __device__ __forceinline__ void border_role(const Dev& d, int blk, int nblk, int
 // cells are never visited), one cell per lane. The wave's entries (chunk and
 // liquid-lane mask) are loaded 64 at a time, one per lane, and read back by
 // lane index, so a chunk's population loads wait for no other load.
-template <int S, int Q, bool TRT, bool BUF>
+template <int S, int Q, bool TRT, bool BUF, bool AA>
 __device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk, int nch) {
   const int lane = threadIdx.x & 63;
   const XcdRange q = xcd_range(nch, blk, nblk, threadIdx.x >> 6, kBlock / 64);
@@ -614,7 +853,10 @@ __device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk, int
     for (int it = 0; it < 64 && w0 + it * q.step < q.end; ++it) {
       const int32_t chunk = __builtin_amdgcn_readlane(ch, it);
       const uint32_t half = lane < 32 ? __builtin_amdgcn_readlane(mlo, it) : __builtin_amdgcn_readlane(mhi, it);
-      liquid_cell<S, Q, TRT, BUF>(d, (int64_t)chunk * 64 + lane, ((half >> (lane & 31)) & 1u) != 0);
+      if constexpr (AA)
+        liquid_cell_aa<S, Q, TRT, BUF>(d, (int64_t)chunk * 64 + lane, ((half >> (lane & 31)) & 1u) != 0);
+      else
+        liquid_cell<S, Q, TRT, BUF>(d, (int64_t)chunk * 64 + lane, ((half >> (lane & 31)) & 1u) != 0);
     }
   }
 }
@@ -632,29 +874,84 @@ __device__ __forceinline__ void liquid_role(const Dev& d, int blk, int nblk, int
 // value), and the state stays that of the failing step.
 __device__ __forceinline__ bool halted(const Dev& d) { return d.cnt[CNT_HALT0 + (d.step & 1)] != 0; }
 
-template <int S, int Q, bool TRT, bool BUF>
+template <int S, int Q, bool TRT, bool BUF, bool AA>
 __device__ __forceinline__ void stream_body(const Dev& d, int b, int nb, int gen, int bord) {
   // the halt word and the list counts in one round trip
   const int32_t halt = d.cnt[CNT_HALT0 + (d.step & 1)];
   const int32_t n_if = d.cnt[CNT_IF], n_gen = d.cnt[CNT_GEN], n_conv = d.cnt[CNT_CONV];
   const int32_t n_ch = d.cnt[CNT_CHUNKS];
+  const int32_t err = AA ? d.cnt[CNT_ERR] : 0;
   if (halt != 0) return;
+  // in place: the last conversions outgrew a stash buffer; the step does
+  // nothing (no marks, empty new-cell lists) and the run halts after it
+  const bool stash_full = AA && (n_if > d.stash_cap || (err & ERR_STASH) != 0);
   if (b == 0 && threadIdx.x == 0) {
     d.cnt[CNT_MARK0 + ((d.step + 1) & 1)] = 0;  // mark slot of the next step
     d.cnt[CNT_NG] = 0;                          // new-cell lists of this step
     d.cnt[CNT_NL] = 0;
+    if (AA) {
+      d.cnt[CNT_SBASE] = n_if;  // stash entries of the next step's buffer
+      d.cnt[CNT_SNEW] = 0;
+      if (stash_full) atomicOr(&d.cnt[CNT_ERR], ERR_STASH);
+    }
   }
+  if (stash_full) return;
   if (b < gen)
-    generic_role<S, Q, TRT>(d, b, gen, n_if);
+    generic_role<S, Q, TRT, AA>(d, b, gen, n_if);
   else if (b < gen + bord)
-    border_role<S, Q, TRT>(d, b - gen, bord, n_gen, n_conv);
+    border_role<S, Q, TRT, AA>(d, b - gen, bord, n_gen, n_conv);
   else
-    liquid_role<S, Q, TRT, BUF>(d, b - gen - bord, nb - gen - bord, n_ch);
+    liquid_role<S, Q, TRT, BUF, AA>(d, b - gen - bord, nb - gen - bord, n_ch);
 }
 
-template <int S, int Q, bool TRT, bool BUF>
+template <int S, int Q, bool TRT, bool BUF, bool AA>
 __global__ __launch_bounds__(kBlock) void k_stream(Dev d, int gen, int bord) {
-  stream_body<S, Q, TRT, BUF>(d, (int)blockIdx.x, (int)gridDim.x, gen, bord);
+  stream_body<S, Q, TRT, BUF, AA>(d, (int)blockIdx.x, (int)gridDim.x, gen, bord);
+}
+
+// In-place layout, at creation (after the interface list is built): each
+// interface cell's q own post-collision populations, copied into entry `item`
+// (its list position) of the stash buffer of the current step parity, and
+// prevpos[c] = item. From then on the streaming launch keeps the buffers.
+template <int S, int Q>
+__global__ __launch_bounds__(kBlock) void k_stash_init(Dev d) {
+  using St = Store<S, Q>;
+  const int32_t nif = d.cnt[CNT_IF];
+  if (nif > d.stash_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&d.cnt[CNT_ERR], ERR_STASH);
+    return;
+  }
+  const int par = (int)(d.step & 1);
+  const typename St::T* F = static_cast<const typename St::T*>(d.fA);
+  const int l = threadIdx.x & (kG - 1);
+  const int k = l < Q ? l : 0;
+  const int64_t groups = (int64_t)gridDim.x * (kBlock / kG);
+  for (int64_t it = (int64_t)blockIdx.x * (kBlock / kG) + threadIdx.x / kG; it < nif; it += groups) {
+    const int32_t e = d.if_list[it];
+    const int64_t c = list_cell(e);
+    if (l < Q)
+      St::st(stash_buf<S, Q>(d, par), it * Q + k, k,
+             St::ld(F, own_slot<Q>(d, c, list_border(e) ? F_BORDER : (uint8_t)0, k, par), k));
+    if (l == 0) d.prevpos[c] = (int32_t)it;
+  }
+}
+
+// In-place layout, at creation: every non-obstacle cell marks the slots of its
+// q arrivals in a bitmap (bits over q * stride elements, cleared by the
+// caller); a slot marked twice sets ERR_SLOTS (walls and obstacles for which
+// pull streaming takes some population twice; such runs need two grids).
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_aa_check(Dev d, uint32_t* bits) {
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= d.g.N) return;
+  if (is_obst(d.flags[c] & T_MASK)) return;
+  int x, y, z;
+  coords(d.g, c, x, y, z);
+  for (int k = 0; k < Q; ++k) {
+    const int64_t e = aa_slot<Q>(d.g, d.flags, x, y, z, c, k);
+    const uint32_t bit = 1u << (uint32_t)(e & 31);
+    if (atomicOr(&bits[e >> 5], bit) & bit) atomicOr(&d.cnt[CNT_ERR], ERR_SLOTS);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -942,7 +1239,7 @@ __device__ __forceinline__ void finish_converted(const Dev& d, int64_t z, int l)
 // of this step), then the collision of this step; rho = the mean density, m =
 // the shares of its converted neighbours (added in direction order), fill
 // level m / rho, flux classes from the neighbour types.
-template <int S, int Q, bool TRT>
+template <int S, int Q, bool TRT, bool AA>
 __device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) {
   using St = Store<S, Q>;
   using T = typename St::T;
@@ -965,11 +1262,54 @@ __device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) 
   const int tj = j >= 0 ? (fj & T_MASK) : -1;
   const bool use = j >= 0 && is_fluid(tj) && !(fj & F_NEW_GAS);
   const bool cv = j >= 0 && (fj & F_CONV);
+  // (in place: the state after this step's streaming has parity step + 1)
+  const int par = (int)((d.step + 1) & 1);
   R r = R(0), a = R(0), b = R(0), cc = R(0);
-  if (use) {
-    R fn[Q];
+  // in place after an even step, a neighbour next to walls or obstacles keeps
+  // its populations in slots that need aa_slot: the group reads them one
+  // neighbour at a time, lane i taking population i, and the lane of that
+  // neighbour sums them in post_moments' order (few cells; per lane and
+  // unrolled, the slot resolution would hold too many registers)
+  const bool slow = AA && use && par && (fj & F_BORDER);
+  if constexpr (AA) {
+    uint32_t need = gballot(slow);
+    while (need) {
+      const int m = __ffs(need) - 1;
+      need &= need - 1;
+      const int64_t jm = (int64_t)__shfl((int)j, m, kG);
+      const uint8_t fm = (uint8_t)__shfl((int)fj, m, kG);
+      const R v = l < Q ? St::ld(B, own_slot<Q>(d, jm, fm, l, par), l) : R(0);
+      R s0 = R(0), s1 = R(0), s2 = R(0), s3 = R(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) fn[i] = St::ld(B, i * stride + j, i);
+      for (int i = 0; i < Q; ++i) {
+        const R vi = __shfl(v, i, kG);
+        s0 += vi;
+        if (cxd(i) > 0) s1 += vi;
+        if (cxd(i) < 0) s1 += -vi;
+        if (cyd(i) > 0) s2 += vi;
+        if (cyd(i) < 0) s2 += -vi;
+        if (czd(i) > 0) s3 += vi;
+        if (czd(i) < 0) s3 += -vi;
+      }
+      if (l == m) {
+        r = SH ? R(1) + s0 : s0;
+        a = (s1 - R(0.5) * (r * R(d.gx))) / r;
+        b = (s2 - R(0.5) * (r * R(d.gy))) / r;
+        cc = (s3 - R(0.5) * (r * R(d.gz))) / r;
+      }
+    }
+  }
+  if (use && !slow) {
+    R fn[Q];
+    if (AA && par) {
+      const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        fn[i] = St::ld(B, opp(i) * stride + j + cxd(i) + cyd(i) * nx + czd(i) * nxy, i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) fn[i] = St::ld(B, i * stride + j, i);
+    }
     post_moments<R, Q, SH>(fn, R(d.gx), R(d.gy), R(d.gz), r, a, b, cc);
   }
   const double share = cv ? excess_share<Q>(d, j, tj == T_LIQ) : 0.0;
@@ -982,7 +1322,16 @@ __device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) 
   CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
   R rr, vx, vy, vz;
   const R fs = gcollide<R, Q, TRT, SH>(fe, l, cp, rr, vx, vy, vz);
-  if (act) St::st(B, k * stride + c, k, fs);
+  if constexpr (AA) {
+    if (act) St::st(B, own_slot<Q>(d, c, par ? d.flags[c] : (uint8_t)0, k, par), k, fs);
+  } else {
+    if (act) St::st(B, k * stride + c, k, fs);
+  }
+  if constexpr (AA) {
+    // (in place: the next step reads the cell's own populations from the stash)
+    const int32_t pos = new_stash_entry(d, c, l);
+    if (act && pos >= 0) St::st(stash_buf<S, Q>(d, par), (int64_t)pos * Q + k, k, fs);
+  }
   double mass = 0.0;
   for (int i = 1; i < Q; ++i) {
     const double si = __shfl(share, i, kG);
@@ -1007,7 +1356,7 @@ __device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) 
 // whose source is the first source around c in direction order (c itself
 // first) completes it; the others stop after the flag loads. Pairs from the
 // mark list whose cell did not convert are no source and never complete.
-template <int S, int Q, bool TRT>
+template <int S, int Q, bool TRT, bool AA>
 __device__ __forceinline__ void complete_pair(const Dev& d, int64_t z, int k, int l) {
   using St = Store<S, Q>;
   using T = typename St::T;
@@ -1038,8 +1387,18 @@ __device__ __forceinline__ void complete_pair(const Dev& d, int64_t z, int k, in
   if (__ffs(src) - 1 != opp(k)) return;  // another pair completes c (or z is no source)
   const double share = cv ? excess_share<Q>(d, j, t == T_LIQ) : 0.0;
   const bool new_liq = (fc & F_NEW_LIQ) != 0;
+  const int par = (int)((d.step + 1) & 1);
   double pop = 0.0;
-  if (new_liq && l < Q) pop = (double)St::ld(static_cast<const T*>(d.fB), l * g.stride + c, l);
+  typename St::R popr = typename St::R(0);
+  if (new_liq && l < Q) {
+    popr = St::ld(static_cast<const T*>(d.fB), AA ? own_slot<Q>(d, c, fc, l, par) : l * g.stride + c, l);
+    pop = (double)popr;
+  }
+  if (AA && new_liq) {
+    // (in place: the next step reads the cell's own populations from the stash)
+    const int32_t pos = new_stash_entry(d, c, l);
+    if (l < Q && pos >= 0) St::st(stash_buf<S, Q>(d, par), (int64_t)pos * Q + l, l, popr);
+  }
   double mass = m_old, rho_n = r_old;
   if (new_liq) {
     double r = 0.0;
@@ -1085,7 +1444,7 @@ __device__ __forceinline__ unsigned long long pack2(uint32_t epoch, uint32_t a, 
 // converted cells, new interface cells, and the interface cells next to any
 // of them. Each of these reads only flags, and masses and populations of
 // cells other than the ones written in this launch.
-template <int S, int Q, bool TRT>
+template <int S, int Q, bool TRT, bool AA>
 __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int rebuild_only, int per,
                                              int workers) {
   __shared__ int s_tile, s_run;
@@ -1097,7 +1456,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   // in this step (its slot is not read by this launch)
   if (!rebuild_only && b == 0 && threadIdx.x == 0)
     d.cnt[CNT_HALT0 + ((d.step + 1) & 1)] =
-        (d.cnt[CNT_HALT0 + (d.step & 1)] != 0 || (d.cnt[CNT_ERR] & ERR_UNSTABLE) != 0) ? 1 : 0;
+        (d.cnt[CNT_HALT0 + (d.step & 1)] != 0 || (d.cnt[CNT_ERR] & (ERR_UNSTABLE | ERR_STASH)) != 0) ? 1 : 0;
   if (!rebuild_only && halted(d)) return;
   if (b < workers) {
     // worker blocks, beside the compaction, over one index space of 32-lane
@@ -1122,7 +1481,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
     for (; it < g_cv * kG; it += stride) {
       const int64_t gi = it / kG;
       if (gi < nng)
-        reinit_from_gas<S, Q, TRT>(d, d.ng_list[gi], l);
+        reinit_from_gas<S, Q, TRT, AA>(d, d.ng_list[gi], l);
       else
         finish_converted<Q>(d, d.mark_list[gi - nng], l);
     }
@@ -1137,7 +1496,7 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
         z = d.ng_list[si - nmk];
       else
         z = d.nl_list[si - nmk - nng];
-      complete_pair<S, Q, TRT>(d, z, k, l);
+      complete_pair<S, Q, TRT, AA>(d, z, k, l);
     }
     return;
   }
@@ -1348,9 +1707,9 @@ __device__ __forceinline__ void compact_body(const Dev& d, int b, int nb, int re
   }
 }
 
-template <int S, int Q, bool TRT>
+template <int S, int Q, bool TRT, bool AA>
 __global__ __launch_bounds__(kCompBlock) void k_compact(Dev d, int rebuild_only, int per, int workers) {
-  compact_body<S, Q, TRT>(d, (int)blockIdx.x, (int)gridDim.x, rebuild_only, per, workers);
+  compact_body<S, Q, TRT, AA>(d, (int)blockIdx.x, (int)gridDim.x, rebuild_only, per, workers);
 }
 
 // ---------------------------------------------------------------------------
@@ -1542,11 +1901,17 @@ __global__ __launch_bounds__(kBlock) void k_reduce_mass(Dev d, int cells_per_blo
   int64_t end = begin + cells_per_block;
   if (end > d.g.N) end = d.g.N;
   for (int64_t c = begin + threadIdx.x; c < end; c += kBlock) {
-    const int t = d.flags[c] & T_MASK;
+    const uint8_t fl = d.flags[c];
+    const int t = fl & T_MASK;
     if (t == T_LIQ) {
       typename St::R f[Q];
+      if (d.aa && (d.step & 1)) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) f[k] = St::ld(A, k * d.g.stride + c, k);
+        for (int k = 0; k < Q; ++k) f[k] = St::ld(A, own_slot<Q>(d, c, fl, k, 1), k);
+      } else {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) f[k] = St::ld(A, k * d.g.stride + c, k);
+      }
       v[0] += density64<typename St::R, Q, St::kShift>(f);
       v[4] += 1.0;
     } else if (t == T_IF) {
@@ -2024,7 +2389,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_border(Dev d) {
 #endif  // FSLBM_HOST_KERNELS
 
 // Populations feq(rho, u) collided once; interface mass phi*rho; fill levels.
-// On entry: rho in rho_if, u in (m, lost, phiB), phi in phiA.
+// On entry: rho in rho_if, u in (m, lost, phiB), phi in phiA. (At creation
+// the step count is 0, where the in-place layout keeps f*_k(c) in plane k of
+// c as the two-grid layout does.)
 template <int S, int Q, bool TRT>
 __global__ __launch_bounds__(kBlock) void k_init_state(Dev d, int resume) {
   using St = Store<S, Q>;
@@ -2089,11 +2456,13 @@ __global__ __launch_bounds__(kBlock) void k_export(Dev d, double* out, int what)
   const Geom& g = d.g;
   if (c >= g.N) return;
   const T* A = static_cast<const T*>(d.fA);
-  const int t = d.flags[c] & T_MASK;
+  const uint8_t fb = d.flags[c];
+  const int t = fb & T_MASK;
   const bool fl = is_fluid(t);
+  const int par = (int)(d.step & 1);
   if (what >= 10) {
     const int k = what - 10;
-    const double v = (double)St::ld(A, k * g.stride + c, k);
+    const double v = fl ? (double)St::ld(A, own_slot<Q>(d, c, fb, k, par), k) : 0.0;
     out[c] = fl ? (St::kShift ? weight<Q>(k) + v : v) : 0.0;
     return;
   }
@@ -2107,8 +2476,13 @@ __global__ __launch_bounds__(kBlock) void k_export(Dev d, double* out, int what)
       v = d.m[c];
     } else {
       R f[Q];
+      if (d.aa && par) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) f[k] = St::ld(A, k * g.stride + c, k);
+        for (int k = 0; k < Q; ++k) f[k] = St::ld(A, own_slot<Q>(d, c, fb, k, par), k);
+      } else {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) f[k] = St::ld(A, k * g.stride + c, k);
+      }
       R rho, ux, uy, uz;
       post_moments<R, Q, St::kShift>(f, R(d.gx), R(d.gy), R(d.gz), rho, ux, uy, uz);
       v = what == 0 || what == 4 ? density64<R, Q, St::kShift>(f)

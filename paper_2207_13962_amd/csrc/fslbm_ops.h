@@ -25,6 +25,8 @@ inline int storage_bytes(int storage) { return storage == FSLBM_F64 ? 8 : (stora
 // Device memory layout (one arena, 256-byte aligned sub-buffers).
 struct Layout {
   int64_t N, stride, tiles, conv_per, red_blocks;
+  int64_t stash_cap;  // in place: entries of one stash buffer (0: two grids)
+  size_t off_stash, off_prevpos;
   size_t off_fA, off_fB, off_flags, off_mark, off_cls, off_phiA, off_phiB, off_m, off_rho_if,
       off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_chunk_mask, off_gen_list,
       off_mark_list, off_ng_list, off_nl_list, off_cnt, off_scan_status,
@@ -49,8 +51,15 @@ inline Layout make_layout(const fslbm_params& p) {
     return at;
   };
   const size_t pdf = (size_t)p.q * (size_t)L.stride * storage_bytes(p.storage);
+  const bool aa = p.layout == FSLBM_AA;
   L.off_fA = take(pdf);
-  L.off_fB = take(pdf);
+  L.off_fB = aa ? L.off_fA : take(pdf);
+  // in place: two stash buffers of the interface cells' own populations,
+  // each an eighth of the domain (at least 65536 cells, at most all), and the
+  // per-cell entry index
+  L.stash_cap = aa ? std::min<int64_t>(L.N, std::max<int64_t>(L.N / 8, 65536)) : 0;
+  L.off_stash = take(2 * (size_t)L.stash_cap * p.q * storage_bytes(p.storage));
+  L.off_prevpos = take(aa ? 4 * (size_t)L.N : 0);
   L.off_flags = take(L.N + 16);
   L.off_mark = take(L.N);
   L.off_cls = take(L.N);
@@ -74,7 +83,9 @@ inline Layout make_layout(const fslbm_params& p) {
   L.off_scan_status = take(16 * L.tiles);
   L.off_pv = take(8 * 8);
   L.off_partial = take(8 * kRedN * L.red_blocks + 8 * 16);
-  L.off_stage = take(8 * L.N);
+  // staging of one population plane; at creation also the slot bitmap of
+  // the in-place layout (q * stride bits)
+  L.off_stage = take(std::max<size_t>(8 * L.N, (size_t)p.q * L.stride / 8 + 8));
   L.off_blab = take(tracked ? 4 * L.N : 0);
   L.off_bpar = take(tracked ? 4 * L.N : 0);
   L.off_btgt = take(tracked ? 4 * L.N : 0);
@@ -111,6 +122,7 @@ inline const char* validate(const fslbm_params* p) {
   if (p->sigma < 0.0) return "sigma must be >= 0";
   if (!(p->smagorinsky >= 0.0)) return "smagorinsky must be >= 0";
   if (p->bubble_model < 0 || p->bubble_model > 2) return "bubble_model must be 0, 1 or 2";
+  if (p->layout != FSLBM_TWO_GRID && p->layout != FSLBM_AA) return "unknown layout";
   return nullptr;
 }
 
@@ -204,6 +216,7 @@ struct BatchLaunch {
   int n = 0;                                 // entries of each table (one per run)
   int blocks[kLaunches] = {0, 0, 0};         // blocks of each launch
   bool buf = true;                 // buffer addressing (every grid below 2 GiB)
+  bool aa = false;                 // in-place layout
   const BatchEntry* aux[kAux] = {nullptr, nullptr, nullptr, nullptr};  // only the runs that need them
   int aux_n[kAux] = {0, 0, 0, 0};
   int aux_blocks[kAux] = {0, 0, 0, 0};
@@ -220,6 +233,8 @@ struct Ops {
   void (*init_flags)(fslbm_ctx*, hipStream_t);
   void (*import_plane)(fslbm_ctx*, hipStream_t, const double*, int);
   void (*export_field)(fslbm_ctx*, hipStream_t, double*, int);
+  void (*aa_check)(fslbm_ctx*, hipStream_t, uint32_t*);
+  void (*stash_init)(fslbm_ctx*, hipStream_t);
 };
 
 template <int S, int Q, bool TRT>
@@ -247,34 +262,58 @@ struct Impl {
     const int bord = xr(std::min<int64_t>(border_blocks(c), cap / 8));
     const int liq = xr(std::min<int64_t>(liquid_blocks(c), cap * 5 / 8));
     const dim3 grid((unsigned)(gen + bord + liq));
-    if (buf)
-      hipExtLaunchKernelGGL((k_stream<S, Q, TRT, true>), grid, dim3(kBlock), 0, s, e0, e1, 0, c->d, gen,
-                            bord);
-    else
-      hipExtLaunchKernelGGL((k_stream<S, Q, TRT, false>), grid, dim3(kBlock), 0, s, e0, e1, 0, c->d, gen,
-                            bord);
+    if (c->d.aa) {
+      if (buf)
+        hipExtLaunchKernelGGL((k_stream<S, Q, TRT, true, true>), grid, dim3(kBlock), 0, s, e0, e1, 0, c->d,
+                              gen, bord);
+      else
+        hipExtLaunchKernelGGL((k_stream<S, Q, TRT, false, true>), grid, dim3(kBlock), 0, s, e0, e1, 0, c->d,
+                              gen, bord);
+    } else if (buf) {
+      hipExtLaunchKernelGGL((k_stream<S, Q, TRT, true, false>), grid, dim3(kBlock), 0, s, e0, e1, 0, c->d,
+                            gen, bord);
+    } else {
+      hipExtLaunchKernelGGL((k_stream<S, Q, TRT, false, false>), grid, dim3(kBlock), 0, s, e0, e1, 0, c->d,
+                            gen, bord);
+    }
   }
   static void convert(fslbm_ctx* c, hipStream_t s, int rebuild) {
     hipLaunchKernelGGL((k_retype<Q>), dim3(retype_blocks(c)), dim3(kBlock), 0, s, c->d, rebuild);
     const int workers = rebuild ? 0 : compact_workers(c);
-    hipLaunchKernelGGL((k_compact<S, Q, TRT>), dim3((unsigned)(c->L.tiles + workers)), dim3(kCompBlock),
-                       0, s, c->d, rebuild, (int)c->L.conv_per, workers);
+    if (c->d.aa)
+      hipLaunchKernelGGL((k_compact<S, Q, TRT, true>), dim3((unsigned)(c->L.tiles + workers)),
+                         dim3(kCompBlock), 0, s, c->d, rebuild, (int)c->L.conv_per, workers);
+    else
+      hipLaunchKernelGGL((k_compact<S, Q, TRT, false>), dim3((unsigned)(c->L.tiles + workers)),
+                         dim3(kCompBlock), 0, s, c->d, rebuild, (int)c->L.conv_per, workers);
   }
   static void classes(fslbm_ctx* c, hipStream_t s) {
     hipLaunchKernelGGL((k_classes<Q>), dim3(list_blocks(c)), dim3(kBlock), 0, s, c->d);
   }
   static void batch_step(const BatchLaunch& bl, hipStream_t s, int64_t tick) {
     if (bl.n == 0) return;
-    if (bl.buf)
-      hipLaunchKernelGGL((kb_stream<S, Q, TRT, true>), dim3((unsigned)bl.blocks[0]), dim3(kBlock), 0, s,
+    if (bl.aa) {
+      if (bl.buf)
+        hipLaunchKernelGGL((kb_stream<S, Q, TRT, true, true>), dim3((unsigned)bl.blocks[0]), dim3(kBlock), 0,
+                           s, bl.devs, bl.tab[0], bl.n, tick);
+      else
+        hipLaunchKernelGGL((kb_stream<S, Q, TRT, false, true>), dim3((unsigned)bl.blocks[0]), dim3(kBlock), 0,
+                           s, bl.devs, bl.tab[0], bl.n, tick);
+    } else if (bl.buf) {
+      hipLaunchKernelGGL((kb_stream<S, Q, TRT, true, false>), dim3((unsigned)bl.blocks[0]), dim3(kBlock), 0, s,
                          bl.devs, bl.tab[0], bl.n, tick);
-    else
-      hipLaunchKernelGGL((kb_stream<S, Q, TRT, false>), dim3((unsigned)bl.blocks[0]), dim3(kBlock), 0, s,
+    } else {
+      hipLaunchKernelGGL((kb_stream<S, Q, TRT, false, false>), dim3((unsigned)bl.blocks[0]), dim3(kBlock), 0, s,
                          bl.devs, bl.tab[0], bl.n, tick);
+    }
     hipLaunchKernelGGL((kb_retype<Q>), dim3((unsigned)bl.blocks[1]), dim3(kBlock), 0, s, bl.devs, bl.tab[1],
                        bl.n, tick);
-    hipLaunchKernelGGL((kb_compact<S, Q, TRT>), dim3((unsigned)bl.blocks[2]), dim3(kCompBlock), 0, s,
-                       bl.devs, bl.tab[2], bl.n, tick);
+    if (bl.aa)
+      hipLaunchKernelGGL((kb_compact<S, Q, TRT, true>), dim3((unsigned)bl.blocks[2]), dim3(kCompBlock), 0, s,
+                         bl.devs, bl.tab[2], bl.n, tick);
+    else
+      hipLaunchKernelGGL((kb_compact<S, Q, TRT, false>), dim3((unsigned)bl.blocks[2]), dim3(kCompBlock), 0, s,
+                         bl.devs, bl.tab[2], bl.n, tick);
   }
   static void reduce_mass(const Dev& d, int64_t blocks, hipStream_t s) {
     hipLaunchKernelGGL((k_reduce_mass<S, Q>), dim3((unsigned)blocks), dim3(kBlock), 0, s, d, kRedCells);
@@ -294,9 +333,15 @@ struct Impl {
     hipLaunchKernelGGL((k_export<S, Q>), dim3(grid_for(c->L.N)), dim3(kBlock), 0, s, c->d, out,
                        what);
   }
+  static void aa_check(fslbm_ctx* c, hipStream_t s, uint32_t* bits) {
+    hipLaunchKernelGGL((k_aa_check<Q>), dim3(grid_for(c->L.N)), dim3(kBlock), 0, s, c->d, bits);
+  }
+  static void stash_init(fslbm_ctx* c, hipStream_t s) {
+    hipLaunchKernelGGL((k_stash_init<S, Q>), dim3(if_blocks(c)), dim3(kBlock), 0, s, c->d);
+  }
   static constexpr Ops ops() {
     return Ops{&step, &convert, &classes, &reduce_mass, &batch_step, &init_state, &init_flags, &import_plane,
-               &export_field};
+               &export_field, &aa_check, &stash_init};
   }
 };
 

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfslbm.so")
 
-FSLBM_ABI_VERSION = 1
+FSLBM_ABI_VERSION = 2
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE, EBUDGET = 0, -1, -2, -3, -4, -5, -6
 
 
@@ -33,7 +33,7 @@ class Params(C.Structure):
                 ("thurey_flux", C.c_int32), ("bubble_model", C.c_int32), ("tau", C.c_double),
                 ("trt_lambda", C.c_double), ("gravity", C.c_double * 3), ("rho_gas", C.c_double),
                 ("sigma", C.c_double), ("eps_phi", C.c_double), ("tie_delta", C.c_double),
-                ("smagorinsky", C.c_double)]
+                ("smagorinsky", C.c_double), ("layout", C.c_int32)]
 
 
 class MassReport(C.Structure):
@@ -143,6 +143,7 @@ def make_params(p) -> Params:
         cp.gravity[k] = p.gravity[k]
     cp.rho_gas, cp.sigma, cp.eps_phi, cp.tie_delta = p.rho_gas, p.sigma, p.eps_phi, p.tie_delta
     cp.smagorinsky = p.smagorinsky
+    cp.layout = p.layout
     return cp
 
 

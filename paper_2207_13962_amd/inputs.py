@@ -22,6 +22,8 @@ PERIODIC, WALL_NOSLIP, WALL_FREESLIP = 0, 1, 2
 NBRC, NBKC, OM, OM3 = 1, 2, 3, 4
 SRT, TRT = 0, 1
 F64, F32, F16S = 0, 1, 2
+# population layout: two grids, or one grid updated in place (AA pattern)
+TWO_GRID, AA = 0, 1
 VARIANT_NAMES = {NBRC: "NBRC", NBKC: "NBKC", OM: "OM", OM3: "OM3"}
 
 
@@ -50,6 +52,7 @@ class Params:
     eps_phi: float = 1e-2
     tie_delta: float = 0.0
     smagorinsky: float = 0.0
+    layout: int = TWO_GRID
 
     @property
     def n(self) -> int:
@@ -552,12 +555,15 @@ def serving_mix(n_requests=512, seed=1234, rate=None, l_min=48, l_max=192, steps
 SERVING_DROP_TAU = 0.52
 
 
-def build_request(req: dict, storage=F32) -> Setup:
+def build_request(req: dict, storage=F32, drop_storage=F64) -> Setup:
     """Setup of one serving request: drops run TRT at SERVING_DROP_TAU, waves
-    SRT."""
+    SRT. Drops keep FP64 populations by default: of the 48 fastest drops of
+    the 512-request mix (L up to 192, up to 10000 steps), 16 went unstable
+    with FP32 storage (all OM or OM3, late in the splash; still 2 at tau 0.55
+    and 2 at 0.53 with the Smagorinsky model), none with FP64."""
     if req["kind"] == "drop":
         return droplet_impact(L=req["L"], velocity=req["extra"], variant=req["variant"],
-                              storage=storage, steps=req["steps"], collision=TRT,
+                              storage=drop_storage, steps=req["steps"], collision=TRT,
                               tau=SERVING_DROP_TAU)
     return wave_slab(L=req["L"], amp_frac=req["extra"], variant=req["variant"], storage=storage,
                      steps=req["steps"])

@@ -24,7 +24,8 @@ def _build(r):
 
 def make_mix(n_requests=48, seed=1234, l_min=32, l_max=64, steps_min=200, steps_max=800, workers=1):
     """A request mix shaped like the serving workload (drop impacts and
-    standing-wave slabs, variant uniform, FP32 populations), with setups built
+    standing-wave slabs, variant uniform; FP64 populations for the drops, FP32
+for the waves, see inputs.build_request), with setups built
     up front (in `workers` processes); arrival times are assigned by
     `poisson_arrivals`."""
     reqs = I.serving_mix(n_requests=n_requests, seed=seed, l_min=l_min, l_max=l_max,

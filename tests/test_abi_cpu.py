@@ -48,11 +48,32 @@ def test_workspace_bytes_and_validation():
     assert fs.workspace_bytes(p.with_(bubble_model=1)) == n
     bad = [p.with_(q=15), p.with_(tau=0.5), p.with_(variant=7), p.with_(nx=0),
            p.with_(storage=9), p.with_(boundary=(0, 1, 1, 1, 1, 1)), p.with_(bubble_model=3),
-           p.with_(bubble_model=-1)]
+           p.with_(bubble_model=-1), p.with_(layout=2)]
     for b in bad:
         with pytest.raises(fs.FslbmError) as e:
             fs.workspace_bytes(b)
         assert e.value.status == fs.EINVAL
+
+
+def test_inplace_layout_needs_one_grid_less():
+    """The in-place layout drops the second population grid and adds two
+    stash buffers of max(N/8, 65536) entries (at most N) of q populations and
+    an int32 entry index per cell."""
+    fs = _lib()
+    for st, sb in ((I.F64, 8), (I.F32, 4), (I.F16S, 2)):
+        for dims in ((256, 128, 64), (40, 40, 40), (16, 16, 16)):
+            p = I.Params(*dims, q=19, storage=st, collision=I.TRT, tau=0.503)
+            two = fs.workspace_bytes(p)
+            aa = fs.workspace_bytes(p.with_(layout=I.AA))
+            n, q = p.n, p.q
+            stride = (n + 255) // 256 * 256
+            cap = min(n, max(n // 8, 65536))
+            # grids and stash are 256-byte-rounded; the staging buffer grows
+            # to the slot bitmap (q * stride bits) on tiny domains
+            diff = q * stride * sb - (2 * cap * q * sb + 255) // 256 * 256 - (4 * n + 255) // 256 * 256
+            assert abs((two - aa) - diff) <= max(256, q * stride // 8), (st, dims, two - aa, diff)
+    big = I.Params(256, 128, 64, q=19, storage=I.F32, collision=I.TRT, tau=0.503)
+    assert fs.workspace_bytes(big.with_(layout=I.AA)) < 0.8 * fs.workspace_bytes(big)
 
 
 def test_strerror_and_abi_version():

@@ -1,0 +1,236 @@
+"""The in-place population layout (FSLBM_AA: one grid, AA pattern) through
+the C ABI. Its arithmetic is that of the two-grid layout in the same order,
+so runs must agree bitwise with two-grid runs (types, fill levels, masses,
+exported populations, mass reports) after odd and even step counts, with
+and without replayed step graphs; FP64 runs match the oracle; resumes cross
+layouts exactly; served in-place runs equal their single-context runs; the
+stash limit and unsupported wall/obstacle combinations fail with an error."""
+import numpy as np
+import pytest
+
+from paper_2207_13962_amd import inputs as I
+
+from ._parity import compare_state, mass_tol
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(setup, **kw):
+    from paper_2207_13962_amd.fslbm import Simulation
+    return Simulation(setup, **kw)
+
+
+def _aa(setup):
+    s = I.Setup(setup.params.with_(layout=I.AA), setup.type, setup.phi, setup.rho, setup.ux, setup.uy,
+                setup.uz)
+    return s
+
+
+def _cases():
+    w, fs = I.WALL_NOSLIP, I.WALL_FREESLIP
+    out = {}
+    out["wave_f64_nbrc"] = I.wave_slab(L=32, amp_frac=0.02, storage=I.F64, variant=I.NBRC)
+    dam = I.rect_dam_break(nx=40, ny=28, nz=12, wx=14, hy=20, g=2e-4, nu=5e-3, storage=I.F32, variant=I.OM)
+    dam.params = dam.params.with_(smagorinsky=0.1)
+    out["dam_f32_trt_les_om"] = dam
+    out["dam_q27_f16s_nbkc"] = I.rect_dam_break(nx=36, ny=24, nz=10, wx=12, hy=18, g=2e-4, nu=5e-3, q=27,
+                                                 storage=I.F16S, variant=I.NBKC)
+    out["dam_freeslip_q27_f64_om3"] = I.rect_dam_break(nx=36, ny=24, nz=12, wx=12, hy=18, g=2e-4, nu=5e-3,
+                                                        q=27, storage=I.F64, variant=I.OM3,
+                                                        boundary=(fs, fs, w, w, fs, fs))
+    out["cyl_freeslip_f32_om"] = I.cyl_dam_break(nx=40, ny=40, nz=24, radius=8.0, height=16.0, g=2e-4,
+                                                  nu=5e-3, storage=I.F32, variant=I.OM)
+    out["drop_f64_srt_nbrc"] = I.droplet_impact(L=28, velocity=0.04, storage=I.F64, variant=I.NBRC)
+    out["taylor_sigma_bubble1_f32"] = I.taylor_bubble(nx=20, ny=20, nz=40, tube_radius=8.5, bubble_radius=5.0,
+                                                      z0=10.0, length=10.0, g=1e-5, nu=0.01, sigma=1e-3,
+                                                      storage=I.F32, variant=I.OM, collision=I.SRT, q=19)
+    out["bubbles_tracked_f64"] = I.bubble_pair("merge", storage=I.F64)
+    return out
+
+
+CASES = _cases()
+
+
+def _state(sim):
+    f = sim.fields(pdf=True, check=False)
+    r = sim.mass(check=False)
+    return f, r
+
+
+def _same(a, b, what, rtol=0.0):
+    """Bitwise (rtol 0), or within rtol where atomic sums decide the last bits."""
+    fa, ra = a
+    fb, rb = b
+    assert fa["status"] == fb["status"] == 0, what
+
+    def eq(x, y):
+        return np.array_equal(x, y) if rtol == 0.0 else np.allclose(x, y, rtol=rtol, atol=1e-15)
+    assert np.array_equal(fa["type"], fb["type"]), "%s: type" % what
+    for key in ("phi", "pdf"):
+        assert eq(fa[key], fb[key]), "%s: %s" % (what, key)
+    ifc = fa["type"] == I.INTERFACE
+    assert eq(fa["mass"][ifc], fb["mass"][ifc]), what
+    for key in ("total_mass", "interface_mass", "liquid_mass", "p_volume", "bubble_volume", "n_interface"):
+        assert eq(np.float64(ra[key]), np.float64(rb[key])), "%s: %s %r vs %r" % (what, key, ra[key], rb[key])
+
+
+@pytest.mark.parametrize("name", [k for k in CASES if CASES[k] is not None])
+def test_inplace_equals_two_grid(name):
+    s = CASES[name]
+    print("case", name, flush=True)
+    two, aa = _sim(s), _sim(_aa(s))
+    # tracked-bubble sums are atomic: equal to rounding only
+    rtol = 1e-12 if s.params.bubble_model == 2 else 0.0
+    done = 0
+    for n in (1, 2, 7, 30, 9):  # odd and even counts; 30 replays step graphs
+        two.step(n)
+        aa.step(n)
+        done += n
+        _same(_state(two), _state(aa), "%s step %d" % (name, done), rtol)
+    if s.params.bubble_model == 2:
+        for x, y in zip(two.bubbles(), aa.bubbles()):
+            assert np.allclose(x, y, rtol=1e-12, atol=0)
+    two.close()
+    aa.close()
+
+
+def test_inplace_graphs_and_plain_agree():
+    s = _aa(CASES["dam_f32_trt_les_om"])
+    a, b = _sim(s), _sim(s)
+    b.set_graphs(False)
+    for n in (3, 16, 5):
+        a.step(n)
+        b.step(n)
+        _same(_state(a), _state(b), "graphs vs plain")
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("variant", [I.NBRC, I.NBKC, I.OM, I.OM3])
+def test_inplace_fp64_matches_oracle(variant):
+    from oracle import Oracle
+    s = _aa(I.rect_dam_break(nx=32, ny=24, nz=10, wx=12, hy=18, g=2e-4, nu=5e-3, storage=I.F64,
+                             variant=variant))
+    g, o = _sim(s), Oracle(s)
+    done = 0
+    for n in (1, 50, 101):
+        g.step(n)
+        assert o.step(n) == 0
+        done += n
+        compare_state(g, o, what="inplace v%d step %d" % (variant, done), mtol=mass_tol(done))
+        rg, ro = g.mass(), o.mass()
+        assert abs(rg["total_mass"] - ro.total_mass) <= 1e-12 * ro.total_mass
+    g.close()
+
+
+@pytest.mark.parametrize("src_layout,dst_layout", [(I.AA, I.AA), (I.TWO_GRID, I.AA), (I.AA, I.TWO_GRID)])
+def test_inplace_resume_across_layouts(src_layout, dst_layout):
+    base = I.rect_dam_break(nx=40, ny=28, nz=12, wx=14, hy=20, g=2e-4, nu=5e-3, storage=I.F64, variant=I.NBKC)
+    base.params = base.params.with_(bubble_model=1)
+    src = I.Setup(base.params.with_(layout=src_layout), base.type, base.phi, base.rho, base.ux, base.uy, base.uz)
+    ref = _sim(src)
+    ref.step(301)
+    a = ref.fields(pdf=True)
+    part = _sim(src)
+    part.step(151)  # odd: the in-place state sits in its shifted slots
+    mid = part.fields(pdf=True)
+    sc = part.scalars()
+    part.close()
+    dst = I.Setup(base.params.with_(layout=dst_layout), mid["type"], mid["phi"], mid["rho"], mid["ux"],
+                  mid["uy"], mid["uz"])
+    g = _sim(dst, pdf=mid["pdf"], mass=mid["mass"])
+    g.set_scalars(*sc)
+    g.step(150)
+    b = g.fields(pdf=True)
+    for key in ("type", "phi", "pdf"):
+        assert np.array_equal(a[key], b[key]), key
+    ifc = a["type"] == I.INTERFACE
+    assert np.array_equal(a["mass"][ifc], b["mass"][ifc])
+    assert g.scalars()[1:] == ref.scalars()[1:]
+    ref.close()
+    g.close()
+
+
+def test_inplace_rejects_double_slots():
+    """No-slip and free-slip obstacle cells meeting at corners make pull
+    streaming take some population twice (5 x 4 x 4 liquid box): the
+    in-place layout refuses it at creation, the two-grid layout runs it."""
+    from paper_2207_13962_amd.fslbm import FslbmError
+    nx, ny, nz = 5, 4, 4
+    p = I.Params(nx, ny, nz, q=19, storage=I.F64, boundary=(I.WALL_NOSLIP,) * 6, tau=0.6, layout=I.AA)
+    t = np.full(p.n, I.LIQUID, np.uint8)
+    for (x, y, z), k in {(3, 3, 0): I.NOSLIP, (2, 1, 0): I.FREESLIP, (0, 0, 0): I.FREESLIP,
+                         (3, 1, 3): I.NOSLIP, (4, 1, 3): I.NOSLIP, (4, 1, 2): I.FREESLIP}.items():
+        t[x + nx * (y + ny * z)] = k
+    fluid = (t == I.LIQUID).astype(np.float64)
+    n = p.n
+    bad = I.Setup(p, t, fluid, np.ones(n), np.zeros(n), np.zeros(n), np.zeros(n))
+    ok = I.Setup(p.with_(layout=I.TWO_GRID), t, fluid, np.ones(n), np.zeros(n), np.zeros(n), np.zeros(n))
+    with pytest.raises(FslbmError) as e:
+        _sim(bad)
+    assert e.value.status == -1
+    _sim(ok).close()  # the two-grid layout takes it
+
+
+def test_inplace_stash_limit():
+    """More interface cells than a stash buffer holds (every cell interface,
+    70^3 cells, buffers of an eighth): creation fails with FSLBM_ENOMEM; a
+    domain with a smaller interface is taken."""
+    from paper_2207_13962_amd.fslbm import FslbmError
+    L = 70
+    p = I.Params(L, L, L, storage=I.F32, tau=0.6, layout=I.AA)
+    n = p.n
+    s = I.Setup(p, np.full(n, I.INTERFACE, np.uint8), np.full(n, 0.5), np.ones(n), np.zeros(n), np.zeros(n),
+                np.zeros(n))
+    with pytest.raises(FslbmError) as e:
+        _sim(s)
+    assert e.value.status == -2
+    t = np.full(n, I.LIQUID, np.uint8).reshape(L, L, L)
+    t[L // 2:] = I.GAS
+    t[L // 2] = I.INTERFACE
+    pw = p.with_(boundary=(I.WALL_NOSLIP,) * 6)  # (periodic z would put gas next to liquid)
+    ok = I.Setup(pw, t.reshape(-1), (t != I.GAS).reshape(-1) * 1.0, np.ones(n), np.zeros(n), np.zeros(n),
+                 np.zeros(n))
+    g = _sim(ok)
+    g.step(3)
+    assert g.mass()["status"] == 0
+    g.close()
+
+
+def test_inplace_runs_served():
+    """In-place and two-grid runs in one server (separate launch groups):
+    each equals its single-context run bitwise."""
+    from paper_2207_13962_amd.fslbm import Server
+    MB = 1 << 20
+    setups = [
+        _aa(I.droplet_impact(L=24, velocity=0.03, variant=I.NBRC)),
+        I.droplet_impact(L=24, velocity=0.03, variant=I.NBRC),
+        _aa(I.wave_slab(L=32, amp_frac=0.02, variant=I.OM3)),
+        _aa(CASES["taylor_sigma_bubble1_f32"]),
+        _aa(I.cyl_dam_break(nx=32, ny=32, nz=20, radius=7.0, height=12.0, g=2e-4, nu=5e-3, storage=I.F32,
+                            variant=I.OM)),
+    ]
+    steps = [61, 61, 40, 47, 52]
+    srv = Server(512 * MB, max_slots=8)
+    ids = {srv.submit(s, n): i for i, (s, n) in enumerate(zip(setups, steps))}
+    out = {}
+    for _ in range(400):
+        if len(out) == len(setups):
+            break
+        srv.advance(7)
+        for rid, st in srv.poll():
+            out[ids[rid]] = (st, *srv.result(rid))
+    srv.close()
+    assert len(out) == len(setups)
+    for i, s in enumerate(setups):
+        st, rep, phi = out[i]
+        assert st == 0
+        g = _sim(s)
+        g.step(steps[i])
+        r = g.mass()
+        f = g.fields(pdf=False)
+        g.close()
+        assert np.array_equal(phi, f["phi"]), i
+        assert rep["total_mass"] == r["total_mass"], i
+        assert rep["p_volume"] == r["p_volume"], i
+    assert np.array_equal(out[0][2], out[1][2])  # in place == two grids
