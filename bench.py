@@ -851,7 +851,7 @@ def main():
             "bench_step": "one time step of each of the %d variant runs (ms_per_time_step: one run's "
                           "time step)" % len(variants),
             "step_launches": "kernel by kernel" if args.no_graphs else
-                             "replayed HIP graphs of 8 steps (captured before the warm-up)",
+                             "replayed HIP graphs of 8 and 2 steps, both step parities (captured before the warm-up)",
             "per_variant": per_variant,
         },
         "roofline": {

@@ -209,13 +209,15 @@ int fslbm_bubbles(fslbm_ctx* ctx, int64_t* label, double* volume, double* pressu
 int fslbm_set_timing(fslbm_ctx* ctx, int64_t capacity);
 int fslbm_kernel_time(fslbm_ctx* ctx, int64_t* launches, double* total_ms);
 
-/* Step launches: with enable = 1 (the default) fslbm_step replays a captured
- * HIP graph of 8 steps when the context's stream is not the NULL stream and
- * timing is off; enable = 0 always launches kernel by kernel. Results are
- * identical either way. The graph is captured on the first fslbm_step of at
- * least 8 steps, or at once by fslbm_set_graphs(ctx, 1) (capture records the
- * launches without running them), so that timed steps need not include it.
- * Errors: FSLBM_EINVAL (NULL), FSLBM_ESTATE, FSLBM_EDEVICE (capture failed). */
+/* Step launches: with enable = 1 (the default) fslbm_step replays captured
+ * HIP graphs of 8 steps, then of 2 steps, when the context's stream is not the
+ * NULL stream and timing is off (an odd last step is launched kernel by
+ * kernel); enable = 0 always launches kernel by kernel. Results are identical
+ * either way. There is one graph per length and step parity; each is captured
+ * on first use, or all four at once by fslbm_set_graphs(ctx, 1) (capture
+ * records the launches without running them), so that timed steps need not
+ * include it. Errors: FSLBM_EINVAL (NULL), FSLBM_ESTATE, FSLBM_EDEVICE
+ * (capture failed). */
 int fslbm_set_graphs(fslbm_ctx* ctx, int enable);
 
 /* Compaction tile size: every thread of a 1024-thread compaction tile scans

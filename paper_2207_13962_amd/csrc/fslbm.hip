@@ -210,54 +210,76 @@ void enqueue_plain(fslbm_ctx* c, int64_t n) {
 }
 
 void drop_graph(fslbm_ctx* c) {
-  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  c->graph_exec = nullptr;
-  c->graph = nullptr;
+  for (int li = 0; li < 2; ++li)
+    for (int par = 0; par < 2; ++par) {
+      if (c->graph_exec[li][par]) (void)hipGraphExecDestroy(c->graph_exec[li][par]);
+      if (c->graph[li][par]) (void)hipGraphDestroy(c->graph[li][par]);
+      c->graph_exec[li][par] = nullptr;
+      c->graph[li][par] = nullptr;
+    }
 }
 
-// Captures (without running) the launches of kGraphSteps steps as a graph
-// and instantiates it. Recording the steps advances the host-side step
-// counter and swaps the buffer pointers kGraphSteps times (an even number:
-// they end where they started); the counter is set back, since nothing ran.
-int capture_graph(fslbm_ctx* c) {
+constexpr int64_t kGraphLen[2] = {kGraphSteps, 2};
+
+// Captures (without running) the launches of kGraphLen[li] steps starting at
+// step parity `par` as a graph and instantiates it. Recording the steps
+// advances the host-side step counter and swaps the buffer pointers an even
+// number of times, so both end where they started; for the other parity the
+// host view is first moved one step on (counter and pointers, nothing runs)
+// and moved back afterwards.
+int capture_graph(fslbm_ctx* c, int li, int par) {
   hipStream_t s = c->stream;
+  const bool flip = (int)(c->step & 1) != par;
+  auto turn = [&](int64_t d) {
+    c->step += d;
+    std::swap(c->d.fA, c->d.fB);
+    std::swap(c->d.phiA, c->d.phiB);
+  };
+  if (flip) turn(1);
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
-  if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
-  c->graph_parity = (int)(c->step & 1);
-  enqueue_plain(c, kGraphSteps);
-  c->step -= kGraphSteps;
-  e = hipStreamEndCapture(s, &c->graph);
-  if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+  if (e == hipSuccess) {
+    enqueue_plain(c, kGraphLen[li]);
+    c->step -= kGraphLen[li];
+    e = hipStreamEndCapture(s, &c->graph[li][par]);
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec[li][par], c->graph[li][par], nullptr, nullptr, 0);
+  }
+  if (flip) turn(-1);
+  if (e != hipSuccess) return hip_fail(c, e, "step graph capture");
   return FSLBM_OK;
 }
 
 bool graphs_usable(const fslbm_ctx* c) { return c->graphs && c->ev.empty() && c->stream != nullptr; }
 
-// Steps go to the stream as a replayed graph of kGraphSteps steps where
-// possible (one launch instead of ~5 per step), the rest as plain launches.
-// Timing runs (events per streaming launch) always use plain launches.
+// Every graph a run can replay, captured now (so that no later step of a
+// timed region pays for a capture).
+int capture_all(fslbm_ctx* c) {
+  for (int li = 0; li < 2; ++li)
+    for (int par = 0; par < 2; ++par)
+      if (!c->graph_exec[li][par]) {
+        const int st = capture_graph(c, li, par);
+        if (st != FSLBM_OK) return st;
+      }
+  return FSLBM_OK;
+}
+
+// Steps go to the stream as replayed graphs of kGraphSteps steps, then of 2
+// steps, where possible (one launch instead of ~5 per step); an odd last step
+// as plain launches. Timing runs (events per streaming launch) always use
+// plain launches.
 int enqueue_steps(fslbm_ctx* c, int64_t n) {
   hipStream_t s = c->stream;
   const bool use_graph = graphs_usable(c);
-  while (use_graph && n >= kGraphSteps) {
-    if (!c->graph_exec) {
-      const int st = capture_graph(c);
+  while (use_graph && n >= 2) {
+    const int li = n >= kGraphSteps ? 0 : 1;
+    const int par = (int)(c->step & 1);
+    if (!c->graph_exec[li][par]) {
+      const int st = capture_graph(c, li, par);
       if (st != FSLBM_OK) return st;
     }
-    if ((int)(c->step & 1) != c->graph_parity) {
-      // the graph holds the buffer pointers and counter slots of the parity
-      // it was captured at: one plain step brings the run back to it
-      enqueue_plain(c, 1);
-      n -= 1;
-      continue;
-    }
-    c->step += kGraphSteps;  // pointers are back where they were captured
-    hipError_t e = hipGraphLaunch(c->graph_exec, s);
+    c->step += kGraphLen[li];  // pointers are back where they were captured
+    hipError_t e = hipGraphLaunch(c->graph_exec[li][par], s);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
-    n -= kGraphSteps;
+    n -= kGraphLen[li];
   }
   enqueue_plain(c, n);
   hipError_t e = hipGetLastError();
@@ -614,7 +636,7 @@ int fslbm_set_graphs(fslbm_ctx* c, int enable) {
   }
   if (c->status != FSLBM_OK) return set_err(c, FSLBM_ESTATE, "context failed earlier: " + c->last_error);
   // capture now, so that the first steps replay instead of capturing
-  if (graphs_usable(c) && !c->graph_exec) return capture_graph(c);
+  if (graphs_usable(c)) return capture_all(c);
   return FSLBM_OK;
 }
 

@@ -141,13 +141,14 @@ struct fslbm_ctx {
   // optional events around the liquid stream-collide launches
   std::vector<hipEvent_t> ev;
   int64_t ev_used = 0;
-  // captured launch sequence of kGraphSteps steps (an even number, so the
-  // grid and fill-level buffers and the counter slots return to where they
-  // started); replayed while no parameter changes
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  // captured launch sequences of kGraphSteps and of 2 steps (even counts, so
+  // the grid and fill-level buffers and the counter slots return to where
+  // they started), one of each per step parity (the parity decides which
+  // buffers and counter slots the captured launches use); replayed while no
+  // parameter changes
+  hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};            // [length][parity]
+  hipGraphExec_t graph_exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   bool graphs = true;
-  int graph_parity = 0;  // step parity at capture: buffers and counter slots are baked in
   int cus = 256;  // compute units of the device
   int device = 0;  // the device current at creation (the arena's device)
 };
