@@ -1180,7 +1180,16 @@ __device__ __forceinline__ uint8_t flux_class(bool has_liq, bool has_gas) {
 // Interface neighbours (new types) of cell z, its q-1 flag loads issued
 // together (a wall neighbour reads z itself and is ignored).
 template <int Q>
-__device__ __forceinline__ int count_if_nb(const Dev& d, int64_t z) {
+__device__ __forceinline__ int count_if_nb(const Dev& d, int64_t z, uint8_t fz) {
+  if (!(fz & F_BORDER)) {
+    // the whole box lies inside the domain and holds no obstacle: plain
+    // offsets, no per-direction wall tests between the loads
+    const int64_t nx = d.g.nx, nxy = (int64_t)d.g.nx * d.g.ny;
+    int n = 0;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) n += ((d.flags[z + kCX[k] + kCY[k] * nx + kCZ[k] * nxy] & T_MASK) == T_IF) ? 1 : 0;
+    return n;
+  }
   int x, y, zz;
   coords(d.g, z, x, y, zz);
   uint8_t t[Q];
@@ -1197,13 +1206,13 @@ __device__ __forceinline__ int count_if_nb(const Dev& d, int64_t z) {
   return n;
 }
 
-// Excess mass of a converted cell z (Sec. 2.2): m - rho when it filled, m
-// when it emptied; each of its interface neighbours (new types) receives an
-// equal share.
+// Excess mass of a converted cell z (flag byte fz) (Sec. 2.2): m - rho when
+// it filled, m when it emptied; each of its interface neighbours (new types)
+// receives an equal share.
 template <int Q>
-__device__ __forceinline__ double excess_share(const Dev& d, int64_t z, bool filled) {
+__device__ __forceinline__ double excess_share(const Dev& d, int64_t z, uint8_t fz, bool filled) {
   const double mz = d.m[z], rz = d.rho_if[z];
-  const int n = count_if_nb<Q>(d, z);
+  const int n = count_if_nb<Q>(d, z, fz);
   return (filled ? mz - rz : mz) / (double)n;
 }
 
@@ -1264,6 +1273,9 @@ __device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) 
   const bool cv = j >= 0 && (fj & F_CONV);
   // (in place: the state after this step's streaming has parity step + 1)
   const int par = (int)((d.step + 1) & 1);
+  // the excess share of a converted neighbour, requested before the
+  // neighbours' populations, so that both sets of loads are in flight at once
+  const double share = cv ? excess_share<Q>(d, j, fj, tj == T_LIQ) : 0.0;
   R r = R(0), a = R(0), b = R(0), cc = R(0);
   // in place after an even step, a neighbour next to walls or obstacles keeps
   // its populations in slots that need aa_slot: the group reads them one
@@ -1312,7 +1324,6 @@ __device__ __forceinline__ void reinit_from_gas(const Dev& d, int64_t c, int l) 
     }
     post_moments<R, Q, SH>(fn, R(d.gx), R(d.gy), R(d.gz), r, a, b, cc);
   }
-  const double share = cv ? excess_share<Q>(d, j, tj == T_LIQ) : 0.0;
   const uint32_t liq = gballot(tj == T_LIQ), gas = gballot(tj == T_GAS), cvm = gballot(cv);
   const int cnt = __popc(gballot(use));
   const R rb = gsum(r, Q) / R(cnt);
@@ -1385,7 +1396,7 @@ __device__ __forceinline__ void complete_pair(const Dev& d, int64_t z, int k, in
   const uint32_t liq = gballot(t == T_LIQ), gas = gballot(t == T_GAS), cvm = gballot(cv);
   const uint32_t src = gballot(j >= 0 && (f & F_TRANSIENT)) | ((fc & F_NEW_LIQ) ? 1u : 0u);
   if (__ffs(src) - 1 != opp(k)) return;  // another pair completes c (or z is no source)
-  const double share = cv ? excess_share<Q>(d, j, t == T_LIQ) : 0.0;
+  const double share = cv ? excess_share<Q>(d, j, f, t == T_LIQ) : 0.0;
   const bool new_liq = (fc & F_NEW_LIQ) != 0;
   const int par = (int)((d.step + 1) & 1);
   double pop = 0.0;

@@ -184,3 +184,23 @@ def test_mini_dam_break_smagorinsky(q, coll):
         g.step(50)
         assert o.step(50) == 0
         compare_state(g, o, what="les q%d c%d step %d" % (q, coll, 50 * (k + 1)))
+
+
+@pytest.mark.parametrize("layout", [I.TWO_GRID, I.AA])
+def test_variant_switch_mid_run(layout):
+    """fslbm_set_variant between steps: a dam break that changes its variant
+    three times (after step counts of both parities, with replayed graphs)
+    against the oracle switching at the same steps."""
+    s = I.rect_dam_break(nx=40, ny=28, nz=12, wx=14, hy=20, g=2e-4, nu=5e-3, storage=I.F64, variant=I.NBRC)
+    s.params = s.params.with_(layout=layout)
+    g, o = _sim(s), _oracle(s)
+    done = 0
+    for n, v in ((37, I.OM3), (24, I.NBKC), (51, I.OM), (40, None)):
+        g.step(n)
+        assert o.step(n) == 0
+        done += n
+        compare_state(g, o, what="switch step %d" % done, mtol=mass_tol(done))
+        if v is not None:
+            g.set_variant(v)
+            o.set_variant(v)
+    g.close()
