@@ -148,10 +148,14 @@ void bind(fslbm_ctx* c) {
   d.blab = tracked ? reinterpret_cast<int32_t*>(a + L.off_blab) : nullptr;
   d.bpar = tracked ? reinterpret_cast<int32_t*>(a + L.off_bpar) : nullptr;
   d.btgt = tracked ? reinterpret_cast<int32_t*>(a + L.off_btgt) : nullptr;
-  d.bV = tracked ? reinterpret_cast<double*>(a + L.off_bV) : nullptr;
-  d.bW = tracked ? reinterpret_cast<double*>(a + L.off_bW) : nullptr;
-  d.bR = tracked ? reinterpret_cast<double*>(a + L.off_bR) : nullptr;
-  d.bnn = tracked ? reinterpret_cast<double*>(a + L.off_bnn) : nullptr;
+  d.bV = tracked ? reinterpret_cast<int64_t*>(a + L.off_bV) : nullptr;
+  d.bW = tracked ? reinterpret_cast<int64_t*>(a + L.off_bW) : nullptr;
+  d.bR = tracked ? reinterpret_cast<int64_t*>(a + L.off_bR) : nullptr;
+  d.bnn = tracked ? reinterpret_cast<int64_t*>(a + L.off_bnn) : nullptr;
+  d.bVl = tracked ? reinterpret_cast<uint64_t*>(a + L.off_bVl) : nullptr;
+  d.bWl = tracked ? reinterpret_cast<uint64_t*>(a + L.off_bWl) : nullptr;
+  d.bRl = tracked ? reinterpret_cast<uint64_t*>(a + L.off_bRl) : nullptr;
+  d.bnnl = tracked ? reinterpret_cast<uint64_t*>(a + L.off_bnnl) : nullptr;
   d.bamt = tracked ? reinterpret_cast<double*>(a + L.off_bamt) : nullptr;
   d.bpr = tracked ? reinterpret_cast<double*>(a + L.off_bpr) : nullptr;
   d.bhas = tracked ? reinterpret_cast<uint8_t*>(a + L.off_bhas) : nullptr;
@@ -602,9 +606,12 @@ int fslbm_bubbles(fslbm_ctx* c, int64_t* label, double* volume, double* pressure
   if (c->p.bubble_model != 2) return FSLBM_OK;
   const int64_t N = c->L.N;
   std::vector<int32_t> lab(N);
-  std::vector<double> V(N), P(N);
+  std::vector<double> P(N);
+  std::vector<int64_t> Vh(N);
+  std::vector<uint64_t> Vl(N);
   HIPCHK(c, hipMemcpyAsync(lab.data(), c->d.blab, 4 * N, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(V.data(), c->d.bV, 8 * N, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(Vh.data(), c->d.bV, 8 * N, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(Vl.data(), c->d.bVl, 8 * N, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(P.data(), c->d.bpr, 8 * N, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   int64_t n = 0;
@@ -612,7 +619,7 @@ int fslbm_bubbles(fslbm_ctx* c, int64_t* label, double* volume, double* pressure
     if (lab[i] != (int32_t)i) continue;
     if (n < max) {
       label[n] = i;
-      volume[n] = V[i];
+      volume[n] = fix_value(Vh[i], Vl[i]);
       pressure[n] = P[i];
     }
     ++n;

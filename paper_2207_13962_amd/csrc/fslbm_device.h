@@ -89,6 +89,18 @@ enum { ERR_UNSTABLE = 1, ERR_LAYER = 2, ERR_SCAN = 4, ERR_TYPE = 8, ERR_BUBBLE =
        ERR_SLOTS = 64 };
 
 // ---------------------------------------------------------------------------
+// Order-free sums (tracked-bubble totals). A value x is kept as hi = floor(x)
+// (int64) and lo = (x - hi) 2^64 (uint64, rounded toward zero); the parts of
+// many values are added as integers, exactly (lo modulo 2^64, its carries
+// into hi), so a total built from atomic adds does not depend on their order.
+// It is read back as hi + lo 2^-64 (two roundings, the same on host and
+// device). Totals must stay below 2^63 in magnitude.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double fix_value(int64_t hi, uint64_t lo) {
+  return (double)hi + (double)lo * 0x1p-64;
+}
+
+// ---------------------------------------------------------------------------
 // Population storage. R is the arithmetic type; kShift tells whether the
 // values handled by the kernels are f_k or h_k = f_k - w_k.
 // ---------------------------------------------------------------------------

@@ -83,7 +83,11 @@ struct Dev {
   int32_t* blab;
   int32_t* bpar;
   int32_t* btgt;  // at an old bubble's label: the smallest new label among its cells
-  double *bV, *bW, *bR, *bnn, *bamt, *bpr;
+  // (the sums bV, bW, bR, bnn as order-free totals: integer part, fraction
+  // times 2^64; fix_value reads them)
+  int64_t *bV, *bW, *bR, *bnn;
+  uint64_t *bVl, *bWl, *bRl, *bnnl;
+  double *bamt, *bpr;
   uint8_t* bhas;
   double* partial;  // reduction partials
   int64_t step;  // parity selects the mark-counter slot
@@ -2091,17 +2095,38 @@ __device__ __forceinline__ bool unite(int32_t* par, int32_t a, int32_t b, int64_
 // Per-wave running sums for one key at a time (all lanes hold the same
 // state): consecutive cells mostly belong to one bubble, so a wave walking a
 // stretch of cells issues one atomic per change of key, not one per cell.
+// Adds x to the order-free total (hi[k], lo[k]) (see fix_value).
+__device__ __forceinline__ void fix_add(int64_t* hi, uint64_t* lo, int64_t k, double x) {
+  if (!(fabs(x) < 0x1p62)) x = 0.0;  // (NaN only in a run already flagged unstable)
+  double h = floor(x);
+  double f = (x - h) * 0x1p64;
+  if (!(f < 0x1p64)) {  // (a fraction within 2^-64 of 1)
+    h += 1.0;
+    f = 0.0;
+  }
+  const uint64_t l = (uint64_t)f;
+  const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&lo[k]), (unsigned long long)l);
+  const int64_t carry = old + l < old ? 1 : 0;
+  atomicAdd(reinterpret_cast<unsigned long long*>(&hi[k]), (unsigned long long)((int64_t)h + carry));
+}
+
+__device__ __forceinline__ double fix_get(const int64_t* hi, const uint64_t* lo, int64_t k) {
+  return fix_value(hi[k], lo[k]);
+}
+
+// A wave's running sum for one key, flushed into an order-free total when
+// the key changes (the wave's own additions come in a fixed order).
 struct WaveSum {
   int32_t key = -1;
   double sum = 0.0;
-  __device__ __forceinline__ void flush(double* base) {
-    if (key >= 0 && (threadIdx.x & 63) == 0) atomicAdd(&base[key], sum);
+  __device__ __forceinline__ void flush(int64_t* hi, uint64_t* lo) {
+    if (key >= 0 && (threadIdx.x & 63) == 0) fix_add(hi, lo, key, sum);
     key = -1;
     sum = 0.0;
   }
-  __device__ __forceinline__ void add(double* base, int32_t k, double x) {
+  __device__ __forceinline__ void add(int64_t* hi, uint64_t* lo, int32_t k, double x) {
     if (k != key) {
-      flush(base);
+      flush(hi, lo);
       key = k;
     }
     sum += x;
@@ -2124,7 +2149,8 @@ struct WaveMin {
 };
 
 // Sum of v over the wave's active lanes of each distinct key, handed to acc.
-__device__ __forceinline__ void wave_add(WaveSum& acc, double* base, int32_t key, double v, bool act) {
+__device__ __forceinline__ void wave_add(WaveSum& acc, int64_t* hi, uint64_t* lo, int32_t key, double v,
+                                         bool act) {
   const int lane = threadIdx.x & 63;
   unsigned long long pending = __ballot(act);
   while (pending) {
@@ -2135,7 +2161,7 @@ __device__ __forceinline__ void wave_add(WaveSum& acc, double* base, int32_t key
     double x = mine ? v : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    acc.add(base, k, x);
+    acc.add(hi, lo, k, x);
     pending &= ~m;
   }
 }
@@ -2172,10 +2198,8 @@ __global__ __launch_bounds__(kBlock) void k_bub_init(Dev d, int force) {
   if (!bub_relabel(d, force)) {
     if (c >= d.g.N) return;
     d.bpar[c] = d.blab[c];
-    d.bV[c] = 0.0;
-    d.bW[c] = 0.0;
-    d.bR[c] = 0.0;
-    d.bnn[c] = 0.0;
+    d.bV[c] = d.bW[c] = d.bR[c] = d.bnn[c] = 0;
+    d.bVl[c] = d.bWl[c] = d.bRl[c] = d.bnnl[c] = 0;
     d.bhas[c] = 0;
     d.btgt[c] = INT32_MAX;
     return;
@@ -2191,10 +2215,8 @@ __global__ __launch_bounds__(kBlock) void k_bub_init(Dev d, int force) {
   const int first = upto ? 63 - __clzll((long long)upto) : lane;  // a bubble lane always has one
   if (!in) return;
   d.bpar[c] = bub ? (int32_t)(c - (lane - first)) : -1;
-  d.bV[c] = 0.0;
-  d.bW[c] = 0.0;
-  d.bR[c] = 0.0;
-  d.bnn[c] = 0.0;
+  d.bV[c] = d.bW[c] = d.bR[c] = d.bnn[c] = 0;
+  d.bVl[c] = d.bWl[c] = d.bRl[c] = d.bnnl[c] = 0;
   d.bhas[c] = 0;
   d.btgt[c] = INT32_MAX;
 }
@@ -2269,15 +2291,15 @@ __global__ __launch_bounds__(kBlock) void k_bub_volume(Dev d) {
     const bool ok = bub && r >= 0;
     const double w = ok ? ((f & T_MASK) == T_GAS ? 1.0 : 1.0 - d.phiB[c]) : 0.0;
     const int32_t old = ok ? d.blab[c] : -1;
-    wave_add(aV, d.bV, r, w, ok);
-    wave_add(aW, d.bW, old, w, old >= 0);
+    wave_add(aV, d.bV, d.bVl, r, w, ok);
+    wave_add(aW, d.bW, d.bWl, old, w, old >= 0);
     wave_min(aT, d.btgt, old, r, old >= 0);
     // a root stays its own parent and r is an ancestor of c, so other
     // threads' finds through c still end at the same root
     if (ok) __hip_atomic_store(&d.bpar[c], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  aV.flush(d.bV);
-  aW.flush(d.bW);
+  aV.flush(d.bV, d.bVl);
+  aW.flush(d.bW, d.bWl);
   aT.flush(d.btgt);
 }
 
@@ -2295,7 +2317,7 @@ __global__ __launch_bounds__(kBlock) void k_bub_amount(Dev d) {
     double share = 0.0, w = 0.0;
     bool act = false;
     if (old >= 0) {
-      const double W = d.bW[old];
+      const double W = fix_get(d.bW, d.bWl, old);
       if (W > 0.0) {
         d.bhas[r] = 1;
         if (r != d.btgt[old]) {
@@ -2305,11 +2327,11 @@ __global__ __launch_bounds__(kBlock) void k_bub_amount(Dev d) {
         }
       }
     }
-    wave_add(aN, d.bnn, r, share, act);
-    wave_add(aR, d.bR, old, w, act);
+    wave_add(aN, d.bnn, d.bnnl, r, share, act);
+    wave_add(aR, d.bR, d.bRl, old, w, act);
   }
-  aN.flush(d.bnn);
-  aR.flush(d.bR);
+  aN.flush(d.bnn, d.bnnl);
+  aR.flush(d.bR, d.bRl);
 }
 
 // Each old bubble's target receives the rest of its amount.
@@ -2317,16 +2339,17 @@ __global__ __launch_bounds__(kBlock) void k_bub_target(Dev d) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (c >= d.g.N) return;
   const int32_t t = d.btgt[c];
-  if (t == INT32_MAX || !(d.bW[c] > 0.0)) return;
-  atomicAdd(&d.bnn[t], d.bamt[c] * (1.0 - d.bR[c] / d.bW[c]));
+  const double W = fix_get(d.bW, d.bWl, c);
+  if (t == INT32_MAX || !(W > 0.0)) return;
+  fix_add(d.bnn, d.bnnl, t, d.bamt[c] * (1.0 - fix_get(d.bR, d.bRl, c) / W));
 }
 
 // Amount and pressure of each new bubble, at its root.
 __global__ __launch_bounds__(kBlock) void k_bub_pressure(Dev d) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (c >= d.g.N || d.bpar[c] != (int32_t)c) return;
-  const double p0 = d.pV[1], V = d.bV[c];
-  const double n = d.bhas[c] ? d.bnn[c] : p0 * V;
+  const double p0 = d.pV[1], V = fix_get(d.bV, d.bVl, c);
+  const double n = d.bhas[c] ? fix_get(d.bnn, d.bnnl, c) : p0 * V;
   d.bamt[c] = n;
   d.bpr[c] = V > 0.0 ? n / V : p0;
 }

@@ -31,6 +31,7 @@ struct Layout {
       off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_chunk_mask, off_gen_list,
       off_mark_list, off_ng_list, off_nl_list, off_cnt, off_scan_status,
       off_pv, off_partial, off_stage, off_blab, off_bpar, off_btgt, off_bV, off_bW, off_bR, off_bnn,
+      off_bVl, off_bWl, off_bRl, off_bnnl,
       off_bamt, off_bpr, off_bhas, total;
 };
 
@@ -93,6 +94,10 @@ inline Layout make_layout(const fslbm_params& p) {
   L.off_bW = take(tracked ? 8 * L.N : 0);
   L.off_bR = take(tracked ? 8 * L.N : 0);
   L.off_bnn = take(tracked ? 8 * L.N : 0);
+  L.off_bVl = take(tracked ? 8 * L.N : 0);
+  L.off_bWl = take(tracked ? 8 * L.N : 0);
+  L.off_bRl = take(tracked ? 8 * L.N : 0);
+  L.off_bnnl = take(tracked ? 8 * L.N : 0);
   L.off_bamt = take(tracked ? 8 * L.N : 0);
   L.off_bpr = take(tracked ? 8 * L.N : 0);
   L.off_bhas = take(tracked ? L.N : 0);

@@ -79,8 +79,7 @@ def test_inplace_equals_two_grid(name):
     s = CASES[name]
     print("case", name, flush=True)
     two, aa = _sim(s), _sim(_aa(s))
-    # tracked-bubble sums are atomic: equal to rounding only
-    rtol = 1e-12 if s.params.bubble_model == 2 else 0.0
+    rtol = 0.0
     done = 0
     for n in (1, 2, 7, 30, 9):  # odd and even counts; 30 replays step graphs
         two.step(n)
@@ -89,7 +88,7 @@ def test_inplace_equals_two_grid(name):
         _same(_state(two), _state(aa), "%s step %d" % (name, done), rtol)
     if s.params.bubble_model == 2:
         for x, y in zip(two.bubbles(), aa.bubbles()):
-            assert np.allclose(x, y, rtol=1e-12, atol=0)
+            assert np.array_equal(x, y)
     two.close()
     aa.close()
 
