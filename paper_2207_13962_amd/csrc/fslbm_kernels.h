@@ -2195,11 +2195,17 @@ __device__ __forceinline__ bool bub_relabel(const Dev& d, int force) {
 // a relabelling the parents are the current labels.
 __global__ __launch_bounds__(kBlock) void k_bub_init(Dev d, int force) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // the per-bubble totals are kept at bubble roots: only bubble cells (the
+  // new roots are among them) and the old roots (their label is their own
+  // index) need clearing; the other entries are never read
   if (!bub_relabel(d, force)) {
     if (c >= d.g.N) return;
-    d.bpar[c] = d.blab[c];
-    d.bV[c] = d.bW[c] = d.bR[c] = d.bnn[c] = 0;
-    d.bVl[c] = d.bWl[c] = d.bRl[c] = d.bnnl[c] = 0;
+    const int32_t lab = d.blab[c];
+    d.bpar[c] = lab;
+    if (lab >= 0) {
+      d.bV[c] = d.bW[c] = d.bR[c] = d.bnn[c] = 0;
+      d.bVl[c] = d.bWl[c] = d.bRl[c] = d.bnnl[c] = 0;
+    }
     d.bhas[c] = 0;
     d.btgt[c] = INT32_MAX;
     return;
@@ -2215,8 +2221,10 @@ __global__ __launch_bounds__(kBlock) void k_bub_init(Dev d, int force) {
   const int first = upto ? 63 - __clzll((long long)upto) : lane;  // a bubble lane always has one
   if (!in) return;
   d.bpar[c] = bub ? (int32_t)(c - (lane - first)) : -1;
-  d.bV[c] = d.bW[c] = d.bR[c] = d.bnn[c] = 0;
-  d.bVl[c] = d.bWl[c] = d.bRl[c] = d.bnnl[c] = 0;
+  if (bub || d.blab[c] == (int32_t)c) {
+    d.bV[c] = d.bW[c] = d.bR[c] = d.bnn[c] = 0;
+    d.bVl[c] = d.bWl[c] = d.bRl[c] = d.bnnl[c] = 0;
+  }
   d.bhas[c] = 0;
   d.btgt[c] = INT32_MAX;
 }
@@ -2339,8 +2347,9 @@ __global__ __launch_bounds__(kBlock) void k_bub_target(Dev d) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (c >= d.g.N) return;
   const int32_t t = d.btgt[c];
+  if (t == INT32_MAX) return;  // (not an old bubble's root)
   const double W = fix_get(d.bW, d.bWl, c);
-  if (t == INT32_MAX || !(W > 0.0)) return;
+  if (!(W > 0.0)) return;
   fix_add(d.bnn, d.bnnl, t, d.bamt[c] * (1.0 - fix_get(d.bR, d.bRl, c) / W));
 }
 
