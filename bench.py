@@ -36,7 +36,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 KERNEL_SOURCES = ["paper_2207_13962_amd/csrc/fslbm_kernels.h", "paper_2207_13962_amd/csrc/fslbm_device.h",
                   "paper_2207_13962_amd/csrc/fslbm_ops.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_dam256_traffic.txt")
+LAYOUTS = ("two_grid", "in_place")
+
+
+def traffic_file(layout="two_grid"):
+    """Committed counter summary of the streaming kernel on dam256 for one
+    population layout."""
+    name = "k_stream_dam256_traffic.txt" if layout == "two_grid" else "k_stream_dam256_inplace_traffic.txt"
+    return os.path.join(ROOT, "profiles", name)
 
 
 def kernel_source_hash():
@@ -46,13 +53,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(layout="two_grid"):
     """HBM bytes per launch of the streaming kernel from the committed rocprofv3
     counter summary, or None if it is missing or was taken on other kernel code."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(layout)
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -99,7 +107,7 @@ def _copy_counter(path, counter):
     return top[len(top) // 2]
 
 
-def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, last, command):
+def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, last, command, layout="two_grid"):
     """Turns two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of the
     benchmark, and the same two counters over the copy calibration, into the
     traffic summary read back by measured_traffic(): the mean over the last
@@ -114,9 +122,12 @@ def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, last, command):
     cf, cw = _copy_counter(cfetch_csv, "FETCH_SIZE"), _copy_counter(cwrite_csv, "WRITE_SIZE")
     fscale, wscale = COPY_BYTES / (1024.0 * cf), COPY_BYTES / (1024.0 * cw)
     hbm = fscale * 1024 * f_kib + wscale * 1024 * w_kib
-    with open(TRAFFIC_FILE, "w") as fh:
+    path = traffic_file(layout)
+    with open(path, "w") as fh:
         fh.write("# HBM traffic of the streaming kernel (k_stream), dam256 workload (D3Q19 TRT + LES,\n")
-        fh.write("# FP32 populations), from rocprofv3 counters. Commands (run from the repository root):\n")
+        fh.write("# FP32 populations, %s), from rocprofv3 counters.\n"
+                 % ("two population grids" if layout == "two_grid" else "one grid updated in place"))
+        fh.write("# Commands (run from the repository root):\n")
         for c in command:
             fh.write("#   %s\n" % c)
         fh.write("# dispatches averaged: the last %d of each benchmark run (kernel-timing region)\n" % len(fe))
@@ -129,7 +140,7 @@ def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, last, command):
         fh.write("fetch_scale: %.4f\n" % fscale)
         fh.write("write_scale: %.4f\n" % wscale)
         fh.write("hbm_bytes_per_launch: %.0f\n" % hbm)
-    print(open(TRAFFIC_FILE).read())
+    print(open(path).read())
 
 
 def write_trace_summary(trace_dir, out_path, last, command,
@@ -551,6 +562,40 @@ def extra_lines(args):
     return out
 
 
+def serving_density(args, reqs):
+    """What the in-place layout buys a server: the same closed batch (every run
+    submitted at t = 0) served with two population grids and in place, under
+    the same pool budget (--budget-gb): peak resident runs, peak pool use and
+    runs/s. With a pool smaller than the mix, more resident runs share each
+    batched launch. Fill levels must agree bitwise between the layouts."""
+    import numpy as np
+    from paper_2207_13962_amd import inputs as I
+    from paper_2207_13962_amd import serving as SV
+    from paper_2207_13962_amd.fslbm import workspace_bytes
+
+    budget = int(args.budget_gb * (1 << 30))
+    zero = [0.0] * len(reqs)
+    out = {"workload": "%d runs: drop impacts (L^3, FP64) and wave slabs (L x L/2 x L/4, FP32), L in [%d, %d], "
+                       "%d-%d steps, closed batch, pool %.2f GiB" % (
+                           len(reqs), args.l_min, args.l_max, args.steps_min, args.steps_max, args.budget_gb)}
+    phis = {}
+    for name, lay in (("two_grid", I.TWO_GRID), ("in_place", I.AA)):
+        for r in reqs:
+            r["setup"].params = r["setup"].params.with_(layout=lay)
+        SV.run_batched(reqs[:4], zero[:4], budget, max_slots=args.slots)  # warm-up (code load)
+        res, runs = SV.run_batched(reqs, zero, budget, max_slots=args.slots, keep_phi=True)
+        phis[name] = runs
+        out[name] = {"runs_per_s": res["runs_per_s"], "makespan_s": res["makespan_s"],
+                     "peak_resident": res["peak_resident"], "peak_pool_GB": res["peak_pool_bytes"] / 1e9,
+                     "mix_bytes_GB": sum(workspace_bytes(r["setup"].params) for r in reqs) / 1e9}
+        print("serving density: %s %.1f runs/s, peak resident %d" % (name, res["runs_per_s"], res["peak_resident"]),
+              file=sys.stderr, flush=True)
+    out["identical_results"] = all(a[0] == b[0] and np.array_equal(a[2], b[2], equal_nan=True)
+                                   for a, b in zip(phis["two_grid"], phis["in_place"]))
+    out["speedup_runs_per_s"] = out["in_place"]["runs_per_s"] / out["two_grid"]["runs_per_s"]
+    return out
+
+
 def serving_section(args, reqs=None):
     """Batched serving against one-at-a-time solves on a request mix shaped
     like the serving workload (drop impacts with FP64 populations and wave
@@ -681,6 +726,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="dam256")
     ap.add_argument("--variants", default="1,2,3,4")
+    ap.add_argument("--layout", choices=LAYOUTS, default="two_grid",
+                    help="population layout of the main run: two grids, or one grid updated in place")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps, single-thread CPU baseline")
     ap.add_argument("--cpu-steps-all", type=int, default=100,
                     help="oracle steps, CPU baseline on all host threads")
@@ -718,6 +765,8 @@ def main():
     ap.add_argument("--scale-only", action="store_true",
                     help="only the streaming kernel on the dam break scaled 2x per axis (kernel by kernel)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving measurement")
+    ap.add_argument("--serving-density", action="store_true",
+                    help="only the same closed batch served with two grids and in place under --budget-gb")
     ap.add_argument("--requests", type=int, default=48, help="serving: runs in the mix")
     ap.add_argument("--l-min", type=int, default=32, help="serving: smallest domain edge")
     ap.add_argument("--l-max", type=int, default=64, help="serving: largest domain edge")
@@ -732,12 +781,14 @@ def main():
     args = ap.parse_args()
     last = len(args.variants.split(",")) * min(args.steps, args.kernel_steps)
     if args.write_traffic:
-        write_traffic(*args.write_traffic, last, args.profile_command)
+        write_traffic(*args.write_traffic, last, args.profile_command, args.layout)
         return
     if args.write_trace_summary:
         kw = {"title": args.trace_title} if args.trace_title else {}
         write_trace_summary(args.write_trace_summary,
-                            args.trace_out or os.path.join(ROOT, "profiles", "k_stream_dam256_trace.txt"), last,
+                            args.trace_out or os.path.join(ROOT, "profiles", "k_stream_dam256_%strace.txt"
+                                                           % ("" if args.layout == "two_grid" else "inplace_")),
+                            last,
                             args.profile_command, **kw)
         return
     if args.copy_calibration:
@@ -749,7 +800,7 @@ def main():
         sys.exit(2)
 
     reqs = None
-    if args.serving_only:
+    if args.serving_only or args.serving_density:
         # the request setups are built on the host before the GPU is touched
         # (worker processes are forked from a process without GPU state)
         from paper_2207_13962_amd import serving as SV
@@ -765,6 +816,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.serving_only:
         print(json.dumps(serving_section(args, reqs)))
+        return
+    if args.serving_density:
+        print(json.dumps(serving_density(args, reqs)))
         return
     if args.precision_study:
         print(json.dumps(precision_study(args)))
@@ -793,6 +847,8 @@ def main():
     variants = [int(v) for v in args.variants.split(",")]
     setup_fn = lambda: I.workload(args.workload, **({"smagorinsky": args.les} if args.les else {}))  # noqa: E731
     base = setup_fn()
+    if args.layout == "in_place":
+        base.params = base.params.with_(layout=I.AA)
     p = base.params
     sb = {I.F64: 8, I.F32: 4, I.F16S: 2}[p.storage]
     r = time_runs(base, variants, args.steps, args.warmup, min(args.steps, args.kernel_steps),
@@ -801,7 +857,7 @@ def main():
     mlups = updates / (ms * 1e-3) / 1e6
     avg_ms, bytes_per_launch, launches = r["avg_launch_ms"], r["bytes_per_launch"], r["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(args.layout)
     whole_gbs = updates * bytes_per_update(p.q, sb) / (ms * 1e-3) / 1e9
     try:
         copy_gbs = copy_rate()
@@ -839,9 +895,11 @@ def main():
         "dtype": {I.F64: "f64", I.F32: "f32", I.F16S: "f16-shifted/f32"}[p.storage],
         "data": "synthetic",
         "config": {
-            "workload": "%s: rectangular dam break %dx%dx%d, D3Q%d %s, variants %s, %d steps per variant run"
+            "workload": "%s: rectangular dam break %dx%dx%d, D3Q%d %s, variants %s, %d steps per variant run%s"
                         % (args.workload, p.nx, p.ny, p.nz, p.q, "TRT" if p.collision else "SRT",
-                           "/".join(I.VARIANT_NAMES[v] for v in variants), args.steps),
+                           "/".join(I.VARIANT_NAMES[v] for v in variants), args.steps,
+                           "" if args.layout == "two_grid" else ", one population grid updated in place"),
+            "layout": args.layout,
             "cells": p.n,
             "parallelism": "single GPU",
             "effective_GBps_whole_step": whole_gbs,

@@ -96,8 +96,9 @@ typedef struct {
                             The interface cells' own post-collision populations, which
                             the free-surface condition and the mass exchange (Sec. 2.2)
                             need after neighbours have overwritten them, are kept in two
-                            stash buffers of max(N/8, 65536) cells (at most N) with a
-                            per-cell entry index; a domain whose interface outgrows them
+                            stash buffers of max(N/8, 2F, 1024) cells (F the largest
+                            face nx*ny, ny*nz or nx*nz; at most N) with a per-cell
+                            entry index; a domain whose interface outgrows them
                             fails (at creation, or the run stops) with
                             FSLBM_ENOMEM. fslbm_create refuses (FSLBM_EINVAL) walls and
                             obstacles for which pull streaming takes some population

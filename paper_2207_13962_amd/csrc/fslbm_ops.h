@@ -55,10 +55,12 @@ inline Layout make_layout(const fslbm_params& p) {
   const bool aa = p.layout == FSLBM_AA;
   L.off_fA = take(pdf);
   L.off_fB = aa ? L.off_fA : take(pdf);
-  // in place: two stash buffers of the interface cells' own populations,
-  // each an eighth of the domain (at least 65536 cells, at most all), and the
-  // per-cell entry index
-  L.stash_cap = aa ? std::min<int64_t>(L.N, std::max<int64_t>(L.N / 8, 65536)) : 0;
+  // in place: two stash buffers of the interface cells' own populations and
+  // the per-cell entry index. A buffer holds an eighth of the domain, or twice
+  // its largest face for flat domains (a surface spanning that face), at
+  // least 1024 cells and at most all.
+  const int64_t face = std::max({(int64_t)p.nx * p.ny, (int64_t)p.ny * p.nz, (int64_t)p.nx * p.nz});
+  L.stash_cap = aa ? std::min<int64_t>(L.N, std::max({L.N / 8, 2 * face, (int64_t)1024})) : 0;
   L.off_stash = take(2 * (size_t)L.stash_cap * p.q * storage_bytes(p.storage));
   L.off_prevpos = take(aa ? 4 * (size_t)L.N : 0);
   L.off_flags = take(L.N + 16);

@@ -57,17 +57,18 @@ def test_workspace_bytes_and_validation():
 
 def test_inplace_layout_needs_one_grid_less():
     """The in-place layout drops the second population grid and adds two
-    stash buffers of max(N/8, 65536) entries (at most N) of q populations and
-    an int32 entry index per cell."""
+    stash buffers of max(N/8, 2F, 1024) entries (F the largest face, at most
+    N) of q populations and an int32 entry index per cell."""
     fs = _lib()
     for st, sb in ((I.F64, 8), (I.F32, 4), (I.F16S, 2)):
-        for dims in ((256, 128, 64), (40, 40, 40), (16, 16, 16)):
+        for dims in ((256, 128, 64), (40, 40, 40), (48, 24, 12), (16, 16, 16)):
             p = I.Params(*dims, q=19, storage=st, collision=I.TRT, tau=0.503)
             two = fs.workspace_bytes(p)
             aa = fs.workspace_bytes(p.with_(layout=I.AA))
             n, q = p.n, p.q
             stride = (n + 255) // 256 * 256
-            cap = min(n, max(n // 8, 65536))
+            face = max(dims[0] * dims[1], dims[1] * dims[2], dims[0] * dims[2])
+            cap = min(n, max(n // 8, 2 * face, 1024))
             # grids and stash are 256-byte-rounded; the staging buffer grows
             # to the slot bitmap (q * stride bits) on tiny domains
             diff = q * stride * sb - (2 * cap * q * sb + 255) // 256 * 256 - (4 * n + 255) // 256 * 256
