@@ -57,3 +57,32 @@ def test_odd_plain_steps_between_replays():
     for k in ("type", "pdf", "mass", "phi"):
         assert np.array_equal(fa[k], fb[k]), k
     assert a.mass() == b.mass()
+
+
+def test_runs_on_separate_streams_side_by_side():
+    """Runs stepped side by side on streams of their own (their launches
+    overlap on the device) equal the same runs stepped in turn on one stream,
+    bitwise: each context owns its arena, lists and counters."""
+    import torch
+    from paper_2207_13962_amd.fslbm import Simulation
+    setups = [I.rect_dam_break(nx=48, ny=32, nz=16, wx=16, hy=24, g=1e-4, nu=0.005, storage=I.F32, variant=v)
+              for v in (I.NBRC, I.NBKC, I.OM, I.OM3)]
+    setups.append(I.Setup(setups[2].params.with_(layout=I.AA), setups[2].type, setups[2].phi, setups[2].rho,
+                          setups[2].ux, setups[2].uy, setups[2].uz))
+    one = torch.cuda.Stream()
+    seq = [Simulation(s, stream=one) for s in setups]
+    streams = [torch.cuda.Stream() for _ in setups]
+    par = [Simulation(s, stream=st) for s, st in zip(setups, streams)]
+    for _ in range(4):
+        for s in seq:
+            s.step(37)
+        for s in par:
+            s.step(37)
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(seq, par)):
+        fa, fb = a.fields(), b.fields()
+        for k in ("type", "pdf", "mass", "phi"):
+            assert np.array_equal(fa[k], fb[k]), (i, k)
+        assert a.mass() == b.mass()
+        a.close()
+        b.close()
