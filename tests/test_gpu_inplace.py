@@ -45,6 +45,8 @@ def _cases():
                                                       z0=10.0, length=10.0, g=1e-5, nu=0.01, sigma=1e-3,
                                                       storage=I.F32, variant=I.OM, collision=I.SRT, q=19)
     out["bubbles_tracked_f64"] = I.bubble_pair("merge", storage=I.F64)
+    # a flat slab: its stash is sized by twice its largest face, not by N/8
+    out["wave_slab48_f32_om3"] = I.build_request(dict(kind="wave", L=48, variant=I.OM3, steps=200, extra=0.02))
     return out
 
 
