@@ -202,9 +202,13 @@ inline unsigned list_blocks(const fslbm_ctx* c) {
 }
 
 // worker blocks of the compaction: about one thread per (changed cell,
-// direction) pair at typical conversion rates
+// direction) pair at typical conversion rates, growing with the domain, but
+// fewer where the tiles already take most of the GPU (whole step with 256
+// workers beside 128 tiles 2 % faster than with 128 on a 2.1 M-cell domain;
+// 128 beside 512 tiles 2 % faster than 256 on an 8.4 M-cell one)
 inline int compact_workers(const fslbm_ctx* c) {
-  return (int)std::max<int64_t>(8, std::min<int64_t>(grid_for(c->L.N) / 64, 256));
+  const int64_t room = std::min<int64_t>(256, std::max<int64_t>(128, 512 - c->L.tiles));
+  return (int)std::max<int64_t>(8, std::min<int64_t>(grid_for(c->L.N) / 32, room));
 }
 
 // One batched step over the resident runs of one (storage, lattice,
