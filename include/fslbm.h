@@ -272,8 +272,9 @@ const char* fslbm_last_error(const fslbm_ctx* ctx);
  * Runs with surface tension (sigma > 0) add a smoothing and a curvature
  * launch before the step, runs with one enclosed bubble (bubble_model 1) a
  * volume and a volume-pressure launch after it, each covering the runs of the
- * group that need it. Runs with tracked bubbles (bubble_model 2) are not
- * served (FSLBM_EINVAL at submit). The server is not thread-safe.
+ * group that need it, and runs with tracked bubbles (bubble_model 2) the
+ * seven bubble passes after it (Sec. 2.2 volume-pressure equation for every
+ * bubble), again only over those runs. The server is not thread-safe.
  * ------------------------------------------------------------------------ */
 typedef struct fslbm_server fslbm_server;
 
@@ -290,7 +291,7 @@ int fslbm_server_create(size_t hbm_budget_bytes, int max_slots, void* hip_stream
 /* Queues one run of nsteps steps (> 0) from the given initial fields (the
  * arrays of fslbm_create, copied: the caller may free them on return).
  * req_id receives the run's id (increasing from 1). Errors: FSLBM_EINVAL
- * (parameters, bubble_model 2, nsteps <= 0, workspace above the budget),
+ * (parameters, nsteps <= 0, workspace above the budget),
  * FSLBM_ENOMEM (host memory). */
 int fslbm_server_submit(fslbm_server* srv, const fslbm_params* p, const uint8_t* type,
                         const double* phi, const double* rho, const double* ux, const double* uy,

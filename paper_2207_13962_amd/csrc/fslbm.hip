@@ -183,7 +183,7 @@ void launch_bubbles(fslbm_ctx* c, hipStream_t s, bool force) {
     hipLaunchKernelGGL(k_bub_union<19>, grid, block, 0, s, c->d, force ? 1 : 0);
   else
     hipLaunchKernelGGL(k_bub_union<27>, grid, block, 0, s, c->d, force ? 1 : 0);
-  const dim3 walk((unsigned)((c->L.N + kBlock * kBubIters - 1) / (kBlock * kBubIters)));
+  const dim3 walk((unsigned)bub_walk_blocks(c->L.N));
   hipLaunchKernelGGL(k_bub_volume, walk, block, 0, s, c->d);
   hipLaunchKernelGGL(k_bub_amount, walk, block, 0, s, c->d);
   hipLaunchKernelGGL(k_bub_target, grid, block, 0, s, c->d);
@@ -908,17 +908,18 @@ int rebuild_plan(fslbm_server* s) {
     bl.devs = s->d_devs;
     bl.buf = (g & 1) != 0;
     bl.aa = (g & 2) != 0;
+    bl.q = ((g >> 3) & 1) != 0 ? 27 : 19;
     int cursor[kLaunches] = {0, 0, 0};
-    int xcursor[kAux] = {0, 0, 0, 0};
+    int xcursor[kAux] = {};
     for (const ResidentRun& r : s->resident) {
       if (r.group != g) continue;
       // the launches beside the step, for the runs that need them
       const fslbm_ctx* c = r.ctx;
-      const bool st = c->p.sigma != 0.0, bub = c->p.bubble_model == 1;
+      const bool st = c->p.sigma != 0.0, bub = c->p.bubble_model == 1, tracked = c->p.bubble_model == 2;
       const int64_t xnb[kAux] = {smooth_tiles(c->p.nx, c->p.ny, c->p.nz), std::min<int64_t>(list_blocks(c), 64),
-                                 vol_blocks_of(c->L.N), 1};
+                                 vol_blocks_of(c->L.N), 1, grid_for(c->L.N), bub_walk_blocks(c->L.N)};
       for (int k = 0; k < kAux; ++k) {
-        if (!(k < AUX_VOL ? st : bub)) continue;
+        if (!(k < AUX_VOL ? st : (k < AUX_BUB ? bub : tracked))) continue;
         BatchEntry& e = s->h_tab[((size_t)g * kTabs + kLaunches + k) * s->max_slots + bl.aux_n[k]];
         e.slot = r.slot;
         e.blk0 = xcursor[k];
@@ -1111,7 +1112,6 @@ int fslbm_server_submit(fslbm_server* s, const fslbm_params* p, const uint8_t* t
                         int64_t nsteps, uint64_t* req_id) {
   if (!s || !req_id || !type || !phi || !rho || !ux || !uy || !uz || nsteps <= 0) return FSLBM_EINVAL;
   if (validate(p)) return FSLBM_EINVAL;
-  if (p->bubble_model == 2) return FSLBM_EINVAL;  // tracked bubbles: single contexts only
   const size_t bytes = make_layout(*p).total;
   if ((size_t)round_up((int64_t)bytes, 256) > s->budget) return FSLBM_EINVAL;
   PendingRun q;
@@ -1189,6 +1189,21 @@ int fslbm_server_advance(fslbm_server* s, int64_t ticks) {
                              bl.aux[AUX_VOL], bl.aux_n[AUX_VOL], t);
           hipLaunchKernelGGL(kb_sum_volume, dim3((unsigned)bl.aux_blocks[AUX_SUMVOL]), dim3(kBlock), 0, st,
                              bl.devs, bl.aux[AUX_SUMVOL], bl.aux_n[AUX_SUMVOL], t);
+        }
+        if (bl.aux_n[AUX_BUB] > 0) {
+          const dim3 gc((unsigned)bl.aux_blocks[AUX_BUB]), gw((unsigned)bl.aux_blocks[AUX_BUBW]), b(kBlock);
+          const BatchEntry *tc = bl.aux[AUX_BUB], *tw = bl.aux[AUX_BUBW];
+          const int nc = bl.aux_n[AUX_BUB], nw = bl.aux_n[AUX_BUBW];
+          hipLaunchKernelGGL(kb_bub_init, gc, b, 0, st, bl.devs, tc, nc, t);
+          if (bl.q == 19)
+            hipLaunchKernelGGL(kb_bub_union<19>, gc, b, 0, st, bl.devs, tc, nc, t);
+          else
+            hipLaunchKernelGGL(kb_bub_union<27>, gc, b, 0, st, bl.devs, tc, nc, t);
+          hipLaunchKernelGGL(kb_bub_volume, gw, b, 0, st, bl.devs, tw, nw, t);
+          hipLaunchKernelGGL(kb_bub_amount, gw, b, 0, st, bl.devs, tw, nw, t);
+          hipLaunchKernelGGL(kb_bub_target, gc, b, 0, st, bl.devs, tc, nc, t);
+          hipLaunchKernelGGL(kb_bub_pressure, gc, b, 0, st, bl.devs, tc, nc, t);
+          hipLaunchKernelGGL(kb_bub_cells, gc, b, 0, st, bl.devs, tc, nc, t);
         }
       }
     if (fork) {

@@ -121,6 +121,33 @@ __global__ __launch_bounds__(kBlock) void kb_sum_volume(const Dev* devs, const B
   if (!batch_dev(devs, e, tick, d)) return;
   sum_volume_body(d.partial, (int)vol_blocks_of(d.g.N), d.partial + kRedN * red_blocks_of(d.g.N), d.pV, 0);
 }
+
+// The seven passes of tracked bubbles (after the compaction) for the runs of
+// a batch that track them; each run has the blocks of its single-context
+// launch (one thread per cell, or bub_walk_blocks for the volume and amount
+// passes), so its per-wave partial sums are the same.
+#define FSLBM_KB_BUB(name, body)                                                                       \
+  __global__ __launch_bounds__(kBlock) void name(const Dev* devs, const BatchEntry* tab, int n, int64_t tick) { \
+    const BatchEntry e = batch_entry(tab, n);                                                          \
+    Dev d;                                                                                             \
+    if (!batch_dev(devs, e, tick, d)) return;                                                          \
+    body;                                                                                              \
+  }
+FSLBM_KB_BUB(kb_bub_init, bub_init_body(d, (int)blockIdx.x - e.blk0, 0))
+FSLBM_KB_BUB(kb_bub_volume, bub_volume_body(d, (int)blockIdx.x - e.blk0))
+FSLBM_KB_BUB(kb_bub_amount, bub_amount_body(d, (int)blockIdx.x - e.blk0))
+FSLBM_KB_BUB(kb_bub_target, bub_target_body(d, (int)blockIdx.x - e.blk0))
+FSLBM_KB_BUB(kb_bub_pressure, bub_pressure_body(d, (int)blockIdx.x - e.blk0))
+FSLBM_KB_BUB(kb_bub_cells, bub_cells_body(d, (int)blockIdx.x - e.blk0))
+#undef FSLBM_KB_BUB
+
+template <int Q>
+__global__ __launch_bounds__(kBlock) void kb_bub_union(const Dev* devs, const BatchEntry* tab, int n, int64_t tick) {
+  const BatchEntry e = batch_entry(tab, n);
+  Dev d;
+  if (!batch_dev(devs, e, tick, d)) return;
+  bub_union_body<Q>(d, (int)blockIdx.x - e.blk0, 0);
+}
 #endif  // FSLBM_HOST_KERNELS
 
 }  // namespace fslbm

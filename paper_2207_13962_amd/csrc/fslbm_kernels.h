@@ -2193,8 +2193,10 @@ __device__ __forceinline__ bool bub_relabel(const Dev& d, int force) {
 // points at the first cell of its run of bubble cells along x (same row), so
 // those links need no union; the runs are joined by the union pass. Without
 // a relabelling the parents are the current labels.
-__global__ __launch_bounds__(kBlock) void k_bub_init(Dev d, int force) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+// (Each pass is a body taking the block index, launched over one run by
+// the k_bub_* kernels and over many by the batched ones.)
+__device__ __forceinline__ void bub_init_body(const Dev& d, int blk, int force) {
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
   // the per-bubble totals are kept at bubble roots: only bubble cells (the
   // new roots are among them) and the old roots (their label is their own
   // index) need clearing; the other entries are never read
@@ -2230,9 +2232,9 @@ __global__ __launch_bounds__(kBlock) void k_bub_init(Dev d, int force) {
 }
 
 template <int Q>
-__global__ __launch_bounds__(kBlock) void k_bub_union(Dev d, int force) {
+__device__ __forceinline__ void bub_union_body(const Dev& d, int blk, int force) {
   if (!bub_relabel(d, force)) return;
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
   if (c >= d.g.N || !bubble_cell(d.flags[c])) return;
   int x, y, z;
   coords(d.g, c, x, y, z);
@@ -2281,9 +2283,9 @@ __global__ __launch_bounds__(kBlock) void k_bub_union(Dev d, int force) {
 // cells (fewer atomics on the few addresses of large bubbles; few enough
 // stretches that the walk's dependent reads stay short).
 constexpr int kBubIters = 4;
-__global__ __launch_bounds__(kBlock) void k_bub_volume(Dev d) {
+__device__ __forceinline__ void bub_volume_body(const Dev& d, int blk) {
   const int lane = threadIdx.x & 63;
-  const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 64 * kBubIters;
+  const int64_t base = ((int64_t)blk * (kBlock / 64) + (threadIdx.x >> 6)) * 64 * kBubIters;
   WaveSum aV, aW;
   WaveMin aT;
   for (int it = 0; it < kBubIters; ++it) {
@@ -2312,9 +2314,9 @@ __global__ __launch_bounds__(kBlock) void k_bub_volume(Dev d) {
 }
 
 // Amounts handed from old to new bubbles through the cells they share.
-__global__ __launch_bounds__(kBlock) void k_bub_amount(Dev d) {
+__device__ __forceinline__ void bub_amount_body(const Dev& d, int blk) {
   const int lane = threadIdx.x & 63;
-  const int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 64 * kBubIters;
+  const int64_t base = ((int64_t)blk * (kBlock / 64) + (threadIdx.x >> 6)) * 64 * kBubIters;
   WaveSum aN, aR;
   for (int it = 0; it < kBubIters; ++it) {
     const int64_t c = base + it * 64 + lane;
@@ -2343,8 +2345,8 @@ __global__ __launch_bounds__(kBlock) void k_bub_amount(Dev d) {
 }
 
 // Each old bubble's target receives the rest of its amount.
-__global__ __launch_bounds__(kBlock) void k_bub_target(Dev d) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void bub_target_body(const Dev& d, int blk) {
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
   if (c >= d.g.N) return;
   const int32_t t = d.btgt[c];
   if (t == INT32_MAX) return;  // (not an old bubble's root)
@@ -2354,8 +2356,8 @@ __global__ __launch_bounds__(kBlock) void k_bub_target(Dev d) {
 }
 
 // Amount and pressure of each new bubble, at its root.
-__global__ __launch_bounds__(kBlock) void k_bub_pressure(Dev d) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void bub_pressure_body(const Dev& d, int blk) {
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
   if (c >= d.g.N || d.bpar[c] != (int32_t)c) return;
   const double p0 = d.pV[1], V = fix_get(d.bV, d.bVl, c);
   const double n = d.bhas[c] ? fix_get(d.bnn, d.bnnl, c) : p0 * V;
@@ -2366,12 +2368,28 @@ __global__ __launch_bounds__(kBlock) void k_bub_pressure(Dev d) {
 // New labels become the current ones; gas density of every bubble cell from
 // its bubble's pressure (interface cells read it in the next step; with
 // surface tension the curvature pass adds the Laplace term).
-__global__ __launch_bounds__(kBlock) void k_bub_cells(Dev d) {
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void bub_cells_body(const Dev& d, int blk) {
+  const int64_t c = (int64_t)blk * kBlock + threadIdx.x;
   if (c >= d.g.N) return;
   const int32_t r = bubble_cell(d.flags[c]) ? d.bpar[c] : -1;
   d.blab[c] = r;
   if (r >= 0) d.rhoG[c] = 3.0 * d.bpr[r];
+}
+
+__global__ __launch_bounds__(kBlock) void k_bub_init(Dev d, int force) { bub_init_body(d, (int)blockIdx.x, force); }
+template <int Q>
+__global__ __launch_bounds__(kBlock) void k_bub_union(Dev d, int force) {
+  bub_union_body<Q>(d, (int)blockIdx.x, force);
+}
+__global__ __launch_bounds__(kBlock) void k_bub_volume(Dev d) { bub_volume_body(d, (int)blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_bub_amount(Dev d) { bub_amount_body(d, (int)blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_bub_target(Dev d) { bub_target_body(d, (int)blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_bub_pressure(Dev d) { bub_pressure_body(d, (int)blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_bub_cells(Dev d) { bub_cells_body(d, (int)blockIdx.x); }
+
+// grid of the volume and amount passes (kBubIters stretches of 64 cells per wave)
+__host__ __device__ inline int64_t bub_walk_blocks(int64_t n) {
+  return (n + kBlock * kBubIters - 1) / (kBlock * kBubIters);
 }
 
 #endif  // FSLBM_HOST_KERNELS

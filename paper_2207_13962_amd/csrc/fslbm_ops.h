@@ -218,8 +218,10 @@ constexpr int kLaunches = 3;  // streaming, re-typing, compaction and completion
 // Launches beside the step for the runs that need them: smoothing and
 // curvature (surface tension) before the streaming launch, the bubble volume
 // and volume pressure (single-bubble model) after the compaction.
-constexpr int kAux = 4;
-enum { AUX_SMOOTH = 0, AUX_CURV = 1, AUX_VOL = 2, AUX_SUMVOL = 3 };
+// Tracked bubbles: the seven bubble passes after the compaction, over a
+// run's cells (AUX_BUB) or its wave stretches (AUX_BUBW).
+constexpr int kAux = 6;
+enum { AUX_SMOOTH = 0, AUX_CURV = 1, AUX_VOL = 2, AUX_SUMVOL = 3, AUX_BUB = 4, AUX_BUBW = 5 };
 constexpr int kTabs = kLaunches + kAux;  // tables per group
 
 struct BatchLaunch {
@@ -229,9 +231,10 @@ struct BatchLaunch {
   int blocks[kLaunches] = {0, 0, 0};         // blocks of each launch
   bool buf = true;                 // buffer addressing (every grid below 2 GiB)
   bool aa = false;                 // in-place layout
-  const BatchEntry* aux[kAux] = {nullptr, nullptr, nullptr, nullptr};  // only the runs that need them
-  int aux_n[kAux] = {0, 0, 0, 0};
-  int aux_blocks[kAux] = {0, 0, 0, 0};
+  int q = 19;                      // lattice of the group
+  const BatchEntry* aux[kAux] = {};  // only the runs that need them
+  int aux_n[kAux] = {};
+  int aux_blocks[kAux] = {};
 };
 
 // Kernel table for one (storage, lattice, collision) combination.

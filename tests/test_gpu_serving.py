@@ -110,10 +110,6 @@ def test_rejects_what_it_cannot_serve():
     srv = Server(8 * MB, max_slots=2)
     with pytest.raises(FslbmError):
         srv.submit(I.wave_slab(L=96), 10)  # workspace above the budget
-    s = I.wave_slab(L=16)
-    s.params = s.params.with_(bubble_model=2)
-    with pytest.raises(FslbmError):
-        srv.submit(s, 10)  # tracked bubbles are not served
     with pytest.raises(FslbmError):
         srv.submit(I.wave_slab(L=16), 0)
     srv.close()
@@ -215,10 +211,59 @@ def test_served_surface_tension_run_matches_oracle():
         assert abs(rep["p_volume"] - r.p_volume) <= 1e-12 * r.p_volume
 
 
-def test_tracked_bubble_runs_are_refused():
-    from paper_2207_13962_amd.fslbm import FslbmError, Server
-    srv = Server(64 * MB, max_slots=2)
-    s = I.bubble_pair("apart", storage=I.F32)
-    with pytest.raises(FslbmError):
-        srv.submit(s, 10)
-    srv.close()
+def _tracked_mix():
+    """Runs with tracked bubbles (merging, splitting, across a periodic face,
+    D3Q27, and a rising bubble with surface tension in a tube) beside runs
+    without them, in several launch groups."""
+    merge = I.bubble_pair("merge", storage=I.F64, g=1e-4)
+    split = I.bubble_pair("split", q=27, storage=I.F32, g=1e-4)
+    straddle = I.bubble_pair("straddle", periodic_x=True, g=2e-4, storage=I.F64)
+    taylor = I.taylor_bubble(nx=20, ny=20, nz=40, tube_radius=8.5, bubble_radius=5.0, z0=10.0, length=10.0,
+                             g=1e-5, nu=0.01, sigma=1e-3, storage=I.F32, variant=I.OM, collision=I.SRT, q=19)
+    taylor.params = taylor.params.with_(bubble_model=2)
+    plain = I.droplet_impact(L=24, velocity=0.03, variant=I.NBRC)
+    single = I.rect_dam_break(nx=32, ny=24, nz=12, wx=10, hy=18, g=2e-4, nu=5e-3, collision=I.SRT,
+                              storage=I.F32, variant=I.NBKC)
+    single.params = single.params.with_(bubble_model=1)
+    return [merge, split, straddle, taylor, plain, single], [41, 37, 60, 55, 45, 52]
+
+
+def test_tracked_bubble_runs_served():
+    """Served runs with tracked bubbles equal their single-context runs
+    bitwise (fill levels, total mass, bubble volume, volume pressure), alone
+    and in a mix with other runs; the per-bubble totals are order-free sums,
+    so this holds whatever shares the launches."""
+    from paper_2207_13962_amd.fslbm import Simulation
+    setups, steps = _tracked_mix()
+    mixed, peak, _ = _serve(setups, steps, ticks=6)
+    assert peak == len(setups)
+    for i, s in enumerate(setups):
+        alone, _, _ = _serve([s], [steps[i]], ticks=13)
+        st_m, rep_m, phi_m = mixed[i]
+        st_a, rep_a, phi_a = alone[0]
+        assert st_m == st_a == 0, i
+        assert np.array_equal(phi_m, phi_a), i
+        sim = Simulation(s)
+        sim.step(steps[i])
+        r = sim.mass()
+        phi_s = sim.fields(pdf=False)["phi"]
+        sim.close()
+        assert np.array_equal(phi_m, phi_s), i
+        for k in ("total_mass", "bubble_volume", "p_volume"):
+            assert rep_m[k] == r[k] == rep_a[k], (i, k)
+
+
+def test_served_tracked_bubbles_match_oracle():
+    """A served FP64 merge of two bubbles against the oracle: fill levels and
+    total mass within 1e-12."""
+    from oracle import Oracle
+    s = I.bubble_pair("merge", storage=I.F64, g=1e-4)
+    out, _, _ = _serve([s, I.droplet_impact(L=20, velocity=0.02)], [40, 30], ticks=9)
+    o = Oracle(s)
+    assert o.step(40) == 0
+    f, r = o.fields(), o.mass()
+    st, rep, phi = out[0]
+    assert st == 0
+    ifc = f["type"] == I.INTERFACE
+    assert np.abs(phi[ifc] - f["phi"][ifc]).max() < 1e-12
+    assert abs(rep["total_mass"] - r.total_mass) <= 1e-12 * r.total_mass
