@@ -213,8 +213,8 @@ def test_served_surface_tension_run_matches_oracle():
 
 def _tracked_mix():
     """Runs with tracked bubbles (merging, splitting, across a periodic face,
-    D3Q27, and a rising bubble with surface tension in a tube) beside runs
-    without them, in several launch groups."""
+    D3Q27, a rising bubble with surface tension in a tube, and one in the
+    in-place layout) beside runs without them, in several launch groups."""
     merge = I.bubble_pair("merge", storage=I.F64, g=1e-4)
     split = I.bubble_pair("split", q=27, storage=I.F32, g=1e-4)
     straddle = I.bubble_pair("straddle", periodic_x=True, g=2e-4, storage=I.F64)
@@ -225,7 +225,9 @@ def _tracked_mix():
     single = I.rect_dam_break(nx=32, ny=24, nz=12, wx=10, hy=18, g=2e-4, nu=5e-3, collision=I.SRT,
                               storage=I.F32, variant=I.NBKC)
     single.params = single.params.with_(bubble_model=1)
-    return [merge, split, straddle, taylor, plain, single], [41, 37, 60, 55, 45, 52]
+    inplace = I.bubble_pair("merge", storage=I.F32, g=1e-4)
+    inplace.params = inplace.params.with_(layout=I.AA)
+    return [merge, split, straddle, taylor, plain, single, inplace], [41, 37, 60, 55, 45, 52, 43]
 
 
 def test_tracked_bubble_runs_served():
