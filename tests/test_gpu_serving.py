@@ -239,6 +239,11 @@ def test_tracked_bubble_runs_served():
     setups, steps = _tracked_mix()
     mixed, peak, _ = _serve(setups, steps, ticks=6)
     assert peak == len(setups)
+    # two slots: runs are admitted at later ticks of either parity
+    staged, peak2, _ = _serve(setups, steps, max_slots=2, ticks=5)
+    assert peak2 == 2
+    for i in range(len(setups)):
+        assert staged[i][0] == 0 and np.array_equal(staged[i][2], mixed[i][2]), i
     for i, s in enumerate(setups):
         alone, _, _ = _serve([s], [steps[i]], ticks=13)
         st_m, rep_m, phi_m = mixed[i]
