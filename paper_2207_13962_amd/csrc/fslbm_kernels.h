@@ -992,6 +992,22 @@ __device__ __forceinline__ bool set_new_type(uint8_t* flags, int64_t j, uint8_t 
   }
 }
 
+// Appends the cells j of the calling wave's lanes with `take` to a list whose
+// length is counter *n: one atomic add per wave (a step with many conversions
+// lists thousands of cells, and adds to one address serialise), lanes in
+// ascending order after the wave's base. The order of a list's entries is
+// not used by any result.
+__device__ __forceinline__ void wave_append(int32_t* list, int32_t* n, bool take, int64_t j) {
+  const uint64_t won = __ballot(take);
+  if (won == 0ull) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const int leader = __ffsll((long long)won) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(n, __popcll(won));
+  base = __shfl(base, leader, 64);
+  if (take) list[base + __popcll(won & ((1ull << lane) - 1ull))] = (int32_t)j;
+}
+
 // Block 0 also starts the compaction that follows: ticket counter reset and,
 // when the compaction will run, a new epoch for its tile-status words.
 template <int Q>
@@ -1021,21 +1037,19 @@ __device__ __forceinline__ void retype_body(const Dev& d, int b, int nb, int reb
     const uint32_t wj = j >= 0 ? *reinterpret_cast<const uint32_t*>(d.flags + (j & ~(int64_t)3)) : 0u;
     const uint8_t fj = (uint8_t)(wj >> (8 * (int)(j & 3)));
     const bool nb_liq_mark = gballot(mj == MK_L) != 0u;
+    // (the list appends are made by the whole wave, both groups together)
+    bool new_gas = false, new_liq = false;
     if (mk == MK_L) {
       if (l == 0) d.flags[c] = (uint8_t)((d.flags[c] & F_STATIC) | T_LIQ | F_CONV);
-      if (j >= 0 && (fj & T_MASK) == T_GAS) {
-        // the one group whose exchange turns the gas byte into an interface
-        // byte lists the cell for its reinitialisation
-        if (set_new_type(d.flags, j, T_GAS, F_NEW_GAS, wj))
-          d.ng_list[atomicAdd(&d.cnt[CNT_NG], 1)] = (int32_t)j;
-      }
+      // the one group whose exchange turns the gas byte into an interface
+      // byte lists the cell for its reinitialisation
+      new_gas = j >= 0 && (fj & T_MASK) == T_GAS && set_new_type(d.flags, j, T_GAS, F_NEW_GAS, wj);
     } else if (mk == MK_G && !nb_liq_mark) {
       if (l == 0) d.flags[c] = (uint8_t)((d.flags[c] & F_STATIC) | T_GAS | F_CONV);
-      if (j >= 0 && (fj & T_MASK) == T_LIQ) {
-        if (set_new_type(d.flags, j, T_LIQ, F_NEW_LIQ, wj))
-          d.nl_list[atomicAdd(&d.cnt[CNT_NL], 1)] = (int32_t)j;
-      }
+      new_liq = j >= 0 && (fj & T_MASK) == T_LIQ && set_new_type(d.flags, j, T_LIQ, F_NEW_LIQ, wj);
     }
+    wave_append(d.ng_list, &d.cnt[CNT_NG], new_gas, j);
+    wave_append(d.nl_list, &d.cnt[CNT_NL], new_liq, j);
   }
 }
 
