@@ -201,7 +201,7 @@ void enqueue_plain(fslbm_ctx* c, int64_t n) {
       hipLaunchKernelGGL(k_smooth, dim3((unsigned)(((c->p.nx + 63) / 64) * ((c->p.ny + 3) / 4) *
                                                    c->p.nz)),
                          dim3(kBlock), 0, s, c->d);
-      hipLaunchKernelGGL(k_curvature, dim3(list_blocks(c)), dim3(kBlock), 0, s, c->d);
+      hipLaunchKernelGGL(k_curvature, dim3(curv_blocks(c)), dim3(kBlock), 0, s, c->d);
     }
     ops.step(c, s);
     ops.convert(c, s, 0);
@@ -916,7 +916,7 @@ int rebuild_plan(fslbm_server* s) {
       // the launches beside the step, for the runs that need them
       const fslbm_ctx* c = r.ctx;
       const bool st = c->p.sigma != 0.0, bub = c->p.bubble_model == 1, tracked = c->p.bubble_model == 2;
-      const int64_t xnb[kAux] = {smooth_tiles(c->p.nx, c->p.ny, c->p.nz), std::min<int64_t>(list_blocks(c), 64),
+      const int64_t xnb[kAux] = {smooth_tiles(c->p.nx, c->p.ny, c->p.nz), std::min<int64_t>(curv_blocks(c), 128),
                                  vol_blocks_of(c->L.N), 1, grid_for(c->L.N), bub_walk_blocks(c->L.N)};
       for (int k = 0; k < kAux; ++k) {
         if (!(k < AUX_VOL ? st : (k < AUX_BUB ? bub : tracked))) continue;

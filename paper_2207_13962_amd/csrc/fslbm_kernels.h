@@ -744,19 +744,47 @@ __device__ __forceinline__ void border_cell(const Dev& d, int64_t c) {
   const int64_t stride = g.stride;
   int x, y, z;
   coords(g, c, x, y, z);
+  // the pull sources in batches of kBB directions: the batch's types in one
+  // load round, then its populations (only a free-slip source needs more
+  // reads), so that a cell waits for a few rounds, not two per direction,
+  // and only a batch's indices are held at once
+  constexpr int kBB = 7;
   R f[Q];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    int64_t src;
-    int dir;
-    bool wall;
-    const int kind = resolve_source<Q>(g, d.flags, x, y, z, k, &src, &dir, &wall);
-    if (kind == SRC_GAS) atomicOr(&d.cnt[CNT_ERR], ERR_LAYER);
-    if (kind != SRC_FLUID) {
-      src = c;
-      dir = opp(k);
+  for (int k0 = 0; k0 < Q; k0 += kBB) {
+    int64_t jj[kBB];
+    int ty[kBB];
+#pragma unroll
+    for (int i = 0; i < kBB; ++i) {
+      const int k = k0 + i;
+      if (k >= Q) break;
+      int w;
+      jj[i] = nb_index(g, x, y, z, -cxd(k), -cyd(k), -czd(k), &w);
+      ty[i] = jj[i] >= 0 ? (d.flags[jj[i]] & T_MASK) : w;
     }
-    f[k] = St::ld(A, dir * stride + src, dir);
+#pragma unroll
+    for (int i = 0; i < kBB; ++i) {
+      const int k = k0 + i;
+      if (k >= Q) break;
+      int64_t src = jj[i];
+      int dir = k;
+      const int st = ty[i];
+      int kind;
+      if (st == T_GAS)
+        kind = SRC_GAS;
+      else if (is_fluid(st))
+        kind = SRC_FLUID;
+      else if (st == T_NOSLIP)
+        kind = SRC_BOUNCE;
+      else
+        kind = reflect_source<Q>(g, d.flags, x, y, z, k, &src, &dir);
+      if (kind == SRC_GAS) atomicOr(&d.cnt[CNT_ERR], ERR_LAYER);
+      if (kind != SRC_FLUID) {
+        src = c;
+        dir = opp(k);
+      }
+      f[k] = St::ld(A, dir * stride + src, dir);
+    }
   }
   CollideParams<R> cp{R(d.omega), R(d.omega_m), R(d.gx), R(d.gy), R(d.gz), R(d.tau0), R(d.lambda), R(d.cs)};
   R rho, ux, uy, uz;
@@ -1840,42 +1868,94 @@ __device__ __forceinline__ void unit_normal_s(const Dev& d, int64_t j, double nh
 
 // kappa = -div(n_hat) by central differences of the unit normals of the face
 // neighbours; rho^G = 3 (p^V + sigma kappa).
+// One interface cell per 32-lane group. The seven normals (the cell's and its
+// six face neighbours') read the smoothed fill levels of 81 points around the
+// cell (offsets up to 2 along at most one axis), which the group stages in
+// LDS with one load round; lane 3p + a then forms component a of normal p
+// with unit_normal_s's terms in its order, so the results are those of
+// unit_normal_s to the bit.
+constexpr int kCurvPts = 125;  // 5x5x5 staging box; 81 of its points are used
+__device__ __forceinline__ int curv_slot(int ox, int oy, int oz) { return (ox + 2) + 5 * ((oy + 2) + 5 * (oz + 2)); }
+
 __device__ __forceinline__ void curvature_body(const Dev& d, int b, int nb) {
+  __shared__ double s_phi[kBlock / kG][kCurvPts];
+  __shared__ uint8_t s_obs[kBlock / kG][kCurvPts];
+  const Geom& g = d.g;
   const int nif = d.cnt[CNT_IF];
-  for (int k = b * kBlock + threadIdx.x; k < nif; k += nb * kBlock) {
-    const int64_t c = list_cell(d.if_list[k]);
+  const int l = threadIdx.x & (kG - 1);
+  const int grp = threadIdx.x / kG;
+  double* ph = s_phi[grp];
+  uint8_t* ob = s_obs[grp];
+  // this lane's normal p (0: the cell, 2a + 1 / 2a + 2: the +a / -a face
+  // neighbour) and component
+  const int p = l < 21 ? l / 3 : 0, a = l < 21 ? l % 3 : 0;
+  const int ea = p == 0 ? 0 : (p - 1) / 2, sg = p == 0 ? 0 : ((p & 1) ? 1 : -1);
+  const int px = ea == 0 ? sg : 0, py = ea == 1 ? sg : 0, pz = ea == 2 ? sg : 0;
+  const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+  for (int item = b * (kBlock / kG) + grp; item < nif; item += nb * (kBlock / kG)) {
+    const int64_t c = list_cell(d.if_list[item]);
     int x, y, z;
-    coords(d.g, c, x, y, z);
-    double nc[3];
-    unit_normal_s(d, c, nc);
-    double div = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      int e[3] = {0, 0, 0};
-      double np_, nm_;
+    coords(g, c, x, y, z);
+    // stage the points: wall ghosts and obstacle cells are marked (their
+    // value is never read); every load of the round is issued at once
+#pragma unroll
+    for (int sl = l; sl < kCurvPts; sl += kG) {
+      const int ox = sl % 5 - 2, oy = (sl / 5) % 5 - 2, oz = sl / 25 - 2;
+      const int far = (ox == 2 || ox == -2) + (oy == 2 || oy == -2) + (oz == 2 || oz == -2);
+      if (far > 1) continue;
       int w;
-      e[a] = 1;
-      int64_t jp = nb_index(d.g, x, y, z, e[0], e[1], e[2], &w);
-      if (jp < 0 || is_obst(d.flags[jp] & T_MASK)) {
-        np_ = nc[a];
-      } else {
-        double t[3];
-        unit_normal_s(d, jp, t);
-        np_ = t[a];
-      }
-      e[a] = -1;
-      int64_t jm = nb_index(d.g, x, y, z, e[0], e[1], e[2], &w);
-      if (jm < 0 || is_obst(d.flags[jm] & T_MASK)) {
-        nm_ = nc[a];
-      } else {
-        double t[3];
-        unit_normal_s(d, jm, t);
-        nm_ = t[a];
-      }
-      div += 0.5 * (np_ - nm_);
+      const int64_t j = wrap_index(g, x + ox, y + oy, z + oz, &w);
+      const bool o = j < 0 || is_obst(d.flags[j] & T_MASK);
+      ob[sl] = o;
+      ph[sl] = j < 0 ? 0.0 : d.phis[j];
     }
-    const double kappa = -div;
-    const double pv = d.bubble == 2 ? d.bpr[d.blab[c]] : d.pV[0];
-    d.rhoG[c] = 3.0 * (pv + d.sigma * kappa);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // component a of the Parker-Youngs normal at the point P of normal p
+    const double W[3] = {1.0, 2.0, 1.0};
+    const double v0 = ph[curv_slot(px, py, pz)];
+    double s = 0.0;
+    for (int bb = -1; bb <= 1; ++bb) {
+      for (int cc = -1; cc <= 1; ++cc) {
+        int dp[3], dm[3];
+        dp[a] = 1;
+        dm[a] = -1;
+        dp[a1] = dm[a1] = bb;
+        dp[a2] = dm[a2] = cc;
+        const int sp = curv_slot(px + dp[0], py + dp[1], pz + dp[2]);
+        const int sm = curv_slot(px + dm[0], py + dm[1], pz + dm[2]);
+        const double vp = ob[sp] ? v0 : ph[sp];
+        const double vm = ob[sm] ? v0 : ph[sm];
+        s += W[bb + 1] * W[cc + 1] * (vp - vm);
+      }
+    }
+    // the unit normal (every lane of normal p forms the same length)
+    const int l0 = 3 * p;
+    const double n0 = __shfl(s, l0, kG), n1 = __shfl(s, l0 + 1, kG), n2 = __shfl(s, l0 + 2, kG);
+    const double len = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    const double nh = len > 0.0 ? s / len : 0.0;
+    // divergence: the face neighbour's normal where it is a fluid cell,
+    // else the cell's own
+    double div = 0.0;
+    for (int e = 0; e < 3; ++e) {
+      const double nc = __shfl(nh, e, kG);
+      const double np_ = __shfl(nh, 3 * (2 * e + 1) + e, kG);
+      const double nm_ = __shfl(nh, 3 * (2 * e + 2) + e, kG);
+      const int op = curv_slot(e == 0 ? 1 : 0, e == 1 ? 1 : 0, e == 2 ? 1 : 0);
+      const int om = curv_slot(e == 0 ? -1 : 0, e == 1 ? -1 : 0, e == 2 ? -1 : 0);
+      div += 0.5 * ((ob[op] ? nc : np_) - (ob[om] ? nc : nm_));
+    }
+    if (l == 0) {
+      const double kappa = -div;
+      const double pv = d.bubble == 2 ? d.bpr[d.blab[c]] : d.pV[0];
+      d.rhoG[c] = 3.0 * (pv + d.sigma * kappa);
+    }
+    // (the next item's staging overwrites the points only after every lane
+    // has read them)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 

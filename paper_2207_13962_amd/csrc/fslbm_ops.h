@@ -195,7 +195,14 @@ inline unsigned retype_blocks(const fslbm_ctx* c) {
   return (unsigned)std::min<int64_t>(b, 512);
 }
 
-// k_classes and k_curvature: one thread per interface cell
+// k_curvature: one 32-lane group per interface cell, about two cells per
+// group at typical interface fractions
+inline unsigned curv_blocks(const fslbm_ctx* c) {
+  int64_t b = grid_for(c->L.N) / 8 + 16;
+  return (unsigned)std::min<int64_t>(b, 2048);
+}
+
+// k_classes: one thread per interface cell
 inline unsigned list_blocks(const fslbm_ctx* c) {
   int64_t b = grid_for(c->L.N) / 32 + 16;
   return (unsigned)std::min<int64_t>(b, 512);
