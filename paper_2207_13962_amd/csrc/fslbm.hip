@@ -132,6 +132,7 @@ void bind(fslbm_ctx* c) {
   const bool tracked = c->p.bubble_model == 2;
   d.rhoG = c->p.sigma != 0.0 || tracked ? reinterpret_cast<double*>(a + L.off_rhoG) : nullptr;
   d.phis = c->p.sigma != 0.0 ? reinterpret_cast<double*>(a + L.off_phis) : nullptr;
+  d.smap = c->p.sigma != 0.0 ? reinterpret_cast<int32_t*>(a + L.off_smap) : nullptr;
   d.lost = reinterpret_cast<double*>(a + L.off_lost);
   d.if_list = reinterpret_cast<int32_t*>(a + L.off_if_list);
   d.conv_list = reinterpret_cast<int32_t*>(a + L.off_conv_list);
@@ -198,6 +199,7 @@ void enqueue_plain(fslbm_ctx* c, int64_t n) {
   for (int64_t i = 0; i < n; ++i) {
     c->d.step = c->step;
     if (st) {
+      hipLaunchKernelGGL(k_smooth_mark, dim3(list_blocks(c)), dim3(kBlock), 0, s, c->d);
       hipLaunchKernelGGL(k_smooth, dim3((unsigned)(((c->p.nx + 63) / 64) * ((c->p.ny + 3) / 4) *
                                                    c->p.nz)),
                          dim3(kBlock), 0, s, c->d);
@@ -404,6 +406,8 @@ int fslbm_create(const fslbm_params* p, const uint8_t* type, const double* phi, 
     INITCHK(hipStreamSynchronize(s));
   }
   INITCHK(hipMemsetAsync(c->d.scan_status, 0, 16 * c->L.tiles, s));
+  if (c->d.smap)  // no smoothing tile is tagged (tags start at 1)
+    INITCHK(hipMemsetAsync(c->d.smap, 0, 4 * (size_t)smooth_tiles(c->p.nx, c->p.ny, c->p.nz), s));
   INITCHK(hipMemsetAsync(c->d.fB, 0, (size_t)c->p.q * c->L.stride * storage_bytes(c->p.storage), s));
   // types go straight into the flag array, fields into buffers used as staging
   INITCHK(hipMemcpyAsync(c->d.flags, type, N, hipMemcpyHostToDevice, s));

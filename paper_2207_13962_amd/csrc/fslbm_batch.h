@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void kb_smooth(const Dev* devs, const Batch
   const BatchEntry e = batch_entry(tab, n);
   Dev d;
   if (!batch_dev(devs, e, tick, d)) return;
-  smooth_body(d, (int)blockIdx.x - e.blk0);
+  smooth_body(d, (int)blockIdx.x - e.blk0, true);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_curvature(const Dev* devs, const BatchEntry* tab, int n,

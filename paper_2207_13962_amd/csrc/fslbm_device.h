@@ -81,6 +81,7 @@ enum {
   CNT_NL = 12,     // new interface cells from liquid in this step
   CNT_SBASE = 13,  // in place: interface cells of this step (stash entries written by the step)
   CNT_SNEW = 14,   // in place: stash entries taken by this step's new interface cells
+  CNT_SMOOTH = 15, // surface tension: smoothing-tile tag of this step, minus one
   CNT_N = 16
 };
 // ERR_STASH: in-place layout, more interface cells than a stash buffer holds;

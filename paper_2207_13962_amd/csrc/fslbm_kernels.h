@@ -64,6 +64,7 @@ struct Dev {
   double* rho_if;
   double* rhoG;  // per-cell gas density (surface tension), or null
   double* phis;  // smoothed fill level (surface tension), or null
+  int32_t* smap;  // surface tension: per smoothing tile, the step tag of its last use
   double* lost;  // per-cell lost excess mass
   int32_t* if_list;
   int32_t* conv_list;
@@ -320,36 +321,6 @@ __device__ __forceinline__ void liquid_cell_aa(const Dev& d, int64_t c, bool min
                       (unsigned)(z - czd(k)) < (unsigned)g.nz;
       St::st(F, in ? k * stride + c - off : opp(k) * stride + c, k, f[opp(k)]);
     }
-  }
-}
-
-// Parker-Youngs normal n = grad(phi) (Sec. 2.2) over the 3x3x3 neighbourhood;
-// obstacle points take the centre value.
-__device__ __forceinline__ void py_normal(const Geom& g, const uint8_t* flags, const double* phi,
-                                          int x, int y, int z, double v0, double n[3]) {
-  const double W[3] = {1.0, 2.0, 1.0};
-#pragma unroll 1
-  for (int a = 0; a < 3; ++a) {
-    const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
-    double s = 0.0;
-#pragma unroll 1
-    for (int b = -1; b <= 1; ++b) {
-#pragma unroll 1
-      for (int cc = -1; cc <= 1; ++cc) {
-        int dp[3], dm[3];
-        dp[a] = 1;
-        dm[a] = -1;
-        dp[a1] = dm[a1] = b;
-        dp[a2] = dm[a2] = cc;
-        int64_t ip, im;
-        int tp = nb_type(g, flags, x, y, z, dp[0], dp[1], dp[2], &ip);
-        int tm = nb_type(g, flags, x, y, z, dm[0], dm[1], dm[2], &im);
-        double vp = is_obst(tp) ? v0 : phi[ip];
-        double vm = is_obst(tm) ? v0 : phi[im];
-        s += W[b + 1] * W[cc + 1] * (vp - vm);
-      }
-    }
-    n[a] = s;
   }
 }
 
@@ -1045,6 +1016,7 @@ __device__ __forceinline__ void retype_body(const Dev& d, int b, int nb, int reb
   if (b == 0 && threadIdx.x == 0) {
     d.cnt[CNT_TICKET] = 0;
     if (rebuild_only || nmk > 0) d.cnt[CNT_EPOCH] += 1;
+    d.cnt[CNT_SMOOTH] += 1;  // the next step's smoothing-tile tag
   }
   const int l = threadIdx.x & (kG - 1);
   const int ngroups = nb * (kBlock / kG);
@@ -1798,19 +1770,69 @@ __global__ __launch_bounds__(kBlock) void k_classes(Dev d) {
 // ---------------------------------------------------------------------------
 // Surface tension (Sec. 2.2): K8-smoothed fill level, curvature, gas density.
 // ---------------------------------------------------------------------------
-#ifdef FSLBM_HOST_KERNELS
-// Smoothed fill level of every cell, K(r) = (1 - r^2/4)^4 over the 3x3x3 box
-// (support radius 2), obstacles left out and the weights renormalised. The
-// block stages a (64+2) x (4+2) x (1+2) halo of phi and flags in LDS.
+// Smoothing tiles: 64 x 4 cells of one plane.
 constexpr int kSmoothTX = 64, kSmoothTY = 4;
 __host__ __device__ inline int64_t smooth_tiles(int nx, int ny, int nz) {
   return (int64_t)((nx + kSmoothTX - 1) / kSmoothTX) * ((ny + kSmoothTY - 1) / kSmoothTY) * nz;
 }
 
-__device__ __forceinline__ void smooth_body(const Dev& d, int bt) {
+#ifdef FSLBM_HOST_KERNELS
+// The curvature reads the smoothed fill level only within two cells of an
+// interface cell (the boxes of the normals of its face neighbours). Before
+// the smoothing, each interface cell tags the smoothing tiles holding such
+// cells (periodic faces wrap, cells beyond a wall are left out); the
+// smoothing skips untagged tiles, whose values are never read. The tag is a
+// device counter that k_retype advances once per step, after the smoothing,
+// so that it changes from step to step under replayed graphs too.
+__device__ __forceinline__ int32_t smooth_tag(const Dev& d) { return d.cnt[CNT_SMOOTH] + 1; }
+
+__device__ __forceinline__ void smooth_mark_body(const Dev& d, int b, int nb) {
+  const Geom& g = d.g;
+  const int nif = d.cnt[CNT_IF];
+  const int tiles_x = (g.nx + kSmoothTX - 1) / kSmoothTX, tiles_y = (g.ny + kSmoothTY - 1) / kSmoothTY;
+  const int32_t tag = smooth_tag(d);
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const int tw[3] = {kSmoothTX, kSmoothTY, 1};
+  for (int k = b * kBlock + threadIdx.x; k < nif; k += nb * kBlock) {
+    const int64_t c = list_cell(d.if_list[k]);
+    int p[3];
+    coords(g, c, p[0], p[1], p[2]);
+    // the tiles covering [p - 2, p + 2] along each axis (at most five)
+    int t[3][5], nt[3];
+    for (int a = 0; a < 3; ++a) {
+      nt[a] = 0;
+      for (int o = -2; o <= 2; ++o) {
+        int v = p[a] + o;
+        if (v < 0 || v >= n[a]) {
+          if (face_kind(g, v < 0 ? 2 * a : 2 * a + 1) != BND_PERIODIC) continue;
+          v = ((v % n[a]) + n[a]) % n[a];
+        }
+        const int ti = v / tw[a];
+        bool seen = false;
+        for (int q = 0; q < nt[a]; ++q) seen |= t[a][q] == ti;
+        if (!seen) t[a][nt[a]++] = ti;
+      }
+    }
+    for (int iz = 0; iz < nt[2]; ++iz)
+      for (int iy = 0; iy < nt[1]; ++iy)
+        for (int ix = 0; ix < nt[0]; ++ix)
+          d.smap[((int64_t)t[2][iz] * tiles_y + t[1][iy]) * tiles_x + t[0][ix]] = tag;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_smooth_mark(Dev d) {
+  smooth_mark_body(d, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// Smoothed fill level, K(r) = (1 - r^2/4)^4 over the 3x3x3 box (support
+// radius 2), obstacles left out and the weights renormalised, of the cells of
+// the tagged tiles (every tile when `all`). The block stages a
+// (64+2) x (4+2) x (1+2) halo of phi and flags in LDS.
+__device__ __forceinline__ void smooth_body(const Dev& d, int bt, bool all) {
   constexpr int TX = kSmoothTX, TY = kSmoothTY;
   __shared__ double s_phi[3][TY + 2][TX + 2];
   __shared__ uint8_t s_obs[3][TY + 2][TX + 2];
+  if (!all && d.smap[bt] != smooth_tag(d)) return;
   const Geom& g = d.g;
   const int tiles_x = (g.nx + TX - 1) / TX, tiles_y = (g.ny + TY - 1) / TY;
   const int tz = bt / (tiles_x * tiles_y);
@@ -1849,31 +1871,19 @@ __device__ __forceinline__ void smooth_body(const Dev& d, int bt) {
   d.phis[c] = num / den;
 }
 
-__global__ __launch_bounds__(kBlock) void k_smooth(Dev d) { smooth_body(d, (int)blockIdx.x); }
-
-__device__ __forceinline__ void unit_normal_s(const Dev& d, int64_t j, double nh[3]) {
-  int x, y, z;
-  coords(d.g, j, x, y, z);
-  double n[3];
-  py_normal(d.g, d.flags, d.phis, x, y, z, d.phis[j], n);
-  const double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-  if (len > 0.0) {
-    nh[0] = n[0] / len;
-    nh[1] = n[1] / len;
-    nh[2] = n[2] / len;
-  } else {
-    nh[0] = nh[1] = nh[2] = 0.0;
-  }
-}
+__global__ __launch_bounds__(kBlock) void k_smooth(Dev d) { smooth_body(d, (int)blockIdx.x, false); }
 
 // kappa = -div(n_hat) by central differences of the unit normals of the face
 // neighbours; rho^G = 3 (p^V + sigma kappa).
 // One interface cell per 32-lane group. The seven normals (the cell's and its
-// six face neighbours') read the smoothed fill levels of 81 points around the
-// cell (offsets up to 2 along at most one axis), which the group stages in
-// LDS with one load round; lane 3p + a then forms component a of normal p
-// with unit_normal_s's terms in its order, so the results are those of
-// unit_normal_s to the bit.
+// six face neighbours') are Parker-Youngs normals (Sec. 2.2) of the smoothed
+// fill level: component a at point P is the sum, over the offsets b, c in
+// {-1, 0, 1} of the other two axes (in that order), of w_b w_c times the
+// difference of the values at P + e_a and P - e_a shifted by (b, c), with
+// w = (1, 2, 1) and obstacle or wall points taking P's value; the unit normal
+// divides by the Euclidean length. They read 81 points around the cell
+// (offsets up to 2 along at most one axis), which the group stages in LDS
+// with one load round; lane 3p + a forms component a of normal p.
 constexpr int kCurvPts = 125;  // 5x5x5 staging box; 81 of its points are used
 __device__ __forceinline__ int curv_slot(int ox, int oy, int oz) { return (ox + 2) + 5 * ((oy + 2) + 5 * (oz + 2)); }
 

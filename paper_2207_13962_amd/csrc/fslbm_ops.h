@@ -28,7 +28,7 @@ struct Layout {
   int64_t stash_cap;  // in place: entries of one stash buffer (0: two grids)
   size_t off_stash, off_prevpos;
   size_t off_fA, off_fB, off_flags, off_mark, off_cls, off_phiA, off_phiB, off_m, off_rho_if,
-      off_rhoG, off_phis, off_lost, off_if_list, off_conv_list, off_chunk_list, off_chunk_mask, off_gen_list,
+      off_rhoG, off_phis, off_smap, off_lost, off_if_list, off_conv_list, off_chunk_list, off_chunk_mask, off_gen_list,
       off_mark_list, off_ng_list, off_nl_list, off_cnt, off_scan_status,
       off_pv, off_partial, off_stage, off_blab, off_bpar, off_btgt, off_bV, off_bW, off_bR, off_bnn,
       off_bVl, off_bWl, off_bRl, off_bnnl,
@@ -73,6 +73,7 @@ inline Layout make_layout(const fslbm_params& p) {
   const bool tracked = p.bubble_model == 2;
   L.off_rhoG = take(p.sigma != 0.0 || tracked ? 8 * L.N : 0);
   L.off_phis = take(p.sigma != 0.0 ? 8 * L.N : 0);
+  L.off_smap = take(p.sigma != 0.0 ? 4 * (size_t)smooth_tiles(p.nx, p.ny, p.nz) : 0);
   L.off_lost = take(8 * L.N);
   L.off_if_list = take(4 * L.N);
   L.off_conv_list = take(4 * L.N);
