@@ -86,6 +86,11 @@ Ops pick(const fslbm_params& p) {
   return p.q == 27 ? ops_f64_q27(p.collision) : ops_f64_q19(p.collision);
 }
 
+// The Dev record is every kernel's argument. Past 512 bytes the streaming
+// launch gets slower (one more unused pointer: 20.6 -> 21.3 us per launch on
+// the 2.1 M-cell dam break), so a new field must displace another.
+static_assert(sizeof(Dev) <= 512, "the kernel-argument record grew past 512 bytes");
+
 void bind(fslbm_ctx* c) {
   const Layout& L = c->L;
   char* a = c->arena;
