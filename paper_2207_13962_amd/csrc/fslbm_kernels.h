@@ -42,7 +42,7 @@ struct Dev {
   // parameters
   double omega, omega_m, gx, gy, gz;
   double tau0, lambda, cs;  // Smagorinsky model (cs = 0: off)
-  double rho_gas, sigma, eps, delta;
+  double sigma, eps, delta;
   int variant, thurey, bubble;
   // state
   void* fA;  // post-collision populations at t (read)
