@@ -1741,6 +1741,17 @@ __global__ __launch_bounds__(kCompBlock) void k_compact(Dev d, int rebuild_only,
   compact_body<S, Q, TRT, AA>(d, (int)blockIdx.x, (int)gridDim.x, rebuild_only, per, workers);
 }
 
+// The two-grid compaction with two argument words (workers < 0: the rebuild
+// at creation, which has no workers): with the record they stay within 512
+// bytes, beyond which a launch costs more (the dam-break step is 1 % faster
+// than with k_compact's three words). The in-place compaction keeps three:
+// with two, its register allocation spilled more and it ran slower.
+template <int S, int Q, bool TRT>
+__global__ __launch_bounds__(kCompBlock) void k_compact2(Dev d, int per, int workers) {
+  compact_body<S, Q, TRT, false>(d, (int)blockIdx.x, (int)gridDim.x, workers < 0 ? 1 : 0, per,
+                                 workers < 0 ? 0 : workers);
+}
+
 // ---------------------------------------------------------------------------
 // k_classes: flux classes of every cell of the interface list from the types
 // around it (when a domain is set up; in a step, the compaction's worker

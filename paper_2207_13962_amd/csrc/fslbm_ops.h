@@ -307,8 +307,8 @@ struct Impl {
       hipLaunchKernelGGL((k_compact<S, Q, TRT, true>), dim3((unsigned)(c->L.tiles + workers)),
                          dim3(kCompBlock), 0, s, c->d, rebuild, (int)c->L.conv_per, workers);
     else
-      hipLaunchKernelGGL((k_compact<S, Q, TRT, false>), dim3((unsigned)(c->L.tiles + workers)),
-                         dim3(kCompBlock), 0, s, c->d, rebuild, (int)c->L.conv_per, workers);
+      hipLaunchKernelGGL((k_compact2<S, Q, TRT>), dim3((unsigned)(c->L.tiles + workers)),
+                         dim3(kCompBlock), 0, s, c->d, (int)c->L.conv_per, rebuild ? -1 : workers);
   }
   static void classes(fslbm_ctx* c, hipStream_t s) {
     hipLaunchKernelGGL((k_classes<Q>), dim3(list_blocks(c)), dim3(kBlock), 0, s, c->d);
